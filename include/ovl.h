@@ -1,0 +1,187 @@
+/*
+ * ovl.h -- C ABI of the MI355X (gfx950) overlap-operator library (libovl.so).
+ *
+ * Method: N. Cundy and W. Lee, "Overlap fermions on GPUs", Lattice 2015 (arXiv:1510.06897).
+ *   Sec. 2, eq. 1:  D[mu] = 1/2 (1 + mu + (1 - mu) gamma5 sign(K)),  K = gamma5 (D_W - m_W).
+ *   Sec. 2, eq. 2:  (D_W psi)(x) = 4 psi(x) - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x + mu)
+ *                                   + (1 + gamma_mu) U_mu(x - mu)^+ psi(x - mu) ].
+ *   Sec. 2, eq. 3:  sign(K) = sum_m alpha_m T_m(K) + sum_i phi_i phi_i^+ [sign(lambda_i)
+ *                                   - sum_m alpha_m T_m(lambda_i)].
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice:  dims[4] = {Lx, Ly, Lz, Lt}, each >= 1; V = Lx Ly Lz Lt sites; periodic boundaries in
+ *           all four directions; site index x + Lx (y + Ly (z + Lz t)) (x fastest).
+ * Gamma matrices: chiral basis, gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 =
+ *           [[0, 1], [1, 0]], gamma5 = diag(1, 1, -1, -1).
+ * Complex numbers are stored as interleaved (re, im) pairs of the element type.
+ * Gauge field (caller layout): U[mu][a][b][site] complex, mu = 0..3 for x, y, z, t, (a, b) the
+ *           colour row and column of U_mu(x).
+ * Spinors:  psi[r][s][c][site] complex, r < nrhs right-hand sides, spin s < 4, colour c < 3.
+ * Polynomial argument: X = K / lmax, lmax an explicit upper bound on ||K||; the coefficient
+ *           alpha_m multiplies T_m(X) and the deflation weights use T_m(lambda_i / lmax).
+ * dtypes:   OVL_F64 (double), OVL_F32 (float), OVL_BF16 (bfloat16, gauge-link storage only).
+ *           Supported operator precisions (spinor dtype / link storage of the gauge handle):
+ *           F64 / F64, F32 / F32, F32 / BF16.  F32 and BF16 forms accumulate in FP32; FP64 is
+ *           used for the deflation inner products, the Gram-Schmidt basis set-up, the deflation
+ *           weights and the final norm check.
+ * Pointers: "_dev" pointers are device memory of the current HIP device, "_host" pointers host
+ *           memory.  The caller owns every data pointer; the library owns only its handles and
+ *           the temporaries it allocates (stream-ordered, freed before the call's work ends).
+ * Streams:  every operator is enqueued on the caller's stream (a hipStream_t passed as void*,
+ *           NULL for the null stream) and is asynchronous: results are visible after the stream
+ *           synchronises.  Calls that share a handle may run on different streams only if they do
+ *           not overlap in time.
+ * Errors:   every function returns OVL_OK (0) or a negative ovl_status; none throws or aborts.
+ *           Arguments are validated on the host before any HIP call; ovl_last_error() returns a
+ *           thread-local message for the most recent failure.  Device-detected problems (a
+ *           non-finite or diverging recurrence) set sticky flags read by ovl_status_flags().
+ * Aliasing: out == in is rejected (OVL_EALIAS): the stencil reads neighbours of the input.
+ */
+#ifndef OVL_H
+#define OVL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OVL_OK = 0,
+  OVL_EINVAL = -1,     /* null pointer, bad count, bad enum value                         */
+  OVL_EDIMS = -2,      /* lattice extents or sizes out of range / mismatched              */
+  OVL_EDTYPE = -3,     /* unsupported dtype or dtype combination                          */
+  OVL_EALIAS = -4,     /* output buffer aliases an input that is read at neighbour sites  */
+  OVL_ENOMEM = -5,     /* device or host allocation failed                                */
+  OVL_EHIP = -6,       /* a HIP runtime call failed (message in ovl_last_error)           */
+  OVL_ENONFINITE = -7, /* non-finite coefficient, lmax, mass or eigenvalue                */
+  OVL_EDIVERGED = -8,  /* lmax below ||K||: the recurrence grew without bound             */
+  OVL_EDEFL = -9       /* deflation basis is rank deficient                               */
+} ovl_status;
+
+typedef enum { OVL_F64 = 0, OVL_F32 = 1, OVL_BF16 = 2 } ovl_dtype;
+
+/* sticky device flags (ovl_status_flags) */
+#define OVL_FLAG_NONFINITE 0x1u /* a final result held NaN or Inf                     */
+#define OVL_FLAG_DIVERGED 0x2u  /* ||result|| exceeded the polynomial's bound * ||in|| */
+
+typedef struct ovl_gauge ovl_gauge; /* packed links on the device (library-owned)     */
+typedef struct ovl_poly ovl_poly;   /* Chebyshev coefficients, lmax, m_W (host FP64)  */
+typedef struct ovl_defl ovl_defl;   /* orthonormal deflation basis + eigenvalues      */
+
+/* ---- handles ------------------------------------------------------------------------------ */
+
+/* Pack a gauge field (Sec. 2, eq. 2: the links U_mu(x)) into the library's layout and storage
+ * dtype.  U_dev: caller layout above, element dtype in_dt (F64 or F32); it is read on `stream`
+ * and may be freed once the stream has passed this call.  store_dt: F64, F32 or BF16 (F64 ->
+ * F32 -> BF16, each rounding to nearest even).  *g receives the new handle.
+ * Errors: EINVAL (null), EDIMS (extent < 1 or > 2^24, V > 2^31), EDTYPE, ENOMEM, EHIP. */
+int ovl_gauge_create(ovl_gauge **g, const int32_t dims[4], const void *U_dev, int in_dt,
+                     int store_dt, void *stream);
+/* Release a handle (synchronises the device first).  NULL is accepted. */
+int ovl_gauge_destroy(ovl_gauge *g);
+/* Extents and storage dtype of a handle. */
+int ovl_gauge_info(const ovl_gauge *g, int32_t dims_out[4], int *store_dt);
+
+/* Polynomial of Sec. 2, eq. 3: coefficients alpha_host[0..n_alpha-1] of T_0 .. T_{n_alpha-1}
+ * (FP64, copied), applied to X = gamma5 (D_W - m_W) / lmax.  n_alpha >= 2 (at least one K
+ * application).  Errors: EINVAL (null, n_alpha < 2 or > 100001, lmax <= 0), ENONFINITE. */
+int ovl_poly_create(ovl_poly **p, const double *alpha_host, int n_alpha, double lmax, double m_W);
+int ovl_poly_destroy(ovl_poly *p);
+/* Value of the polynomial sum_m alpha_m T_m(x) at x = lambda / lmax (host, FP64 Clenshaw). */
+int ovl_poly_eval(const ovl_poly *p, double lambda, double *value_out);
+
+/* Coefficients for a Chebyshev approximation of sign(x) on eps <= |x| <= 1 (the paper asks for
+ * "appropriate coefficients", Sec. 2, eq. 3, and gives none).  Rule: interpolate q(y) ~ y^{-1/2}
+ * on [eps^2, 1] at first-kind Chebyshev nodes with degree (N-1)/2, N the largest odd number
+ * <= degree; p(x) = x q(x^2) re-expanded exactly in T_m(x).  alpha_host receives N+1 values
+ * (alpha_m = 0 for even m).  *n_alpha_out = N + 1.  Host-only, FP64.
+ * Errors: EINVAL (degree < 1 or > 100000, eps outside (0, 1), null). */
+int ovl_cheb_sign_coeffs(int degree, double eps, double *alpha_host, int *n_alpha_out);
+
+/* Deflation basis of Sec. 2, eq. 3: n_ev eigenvectors phi_i of K (device, spinor layout with
+ * nrhs = n_ev, dtype in_dt F64 or F32) and their eigenvalues lambda_host[i] (unscaled).  The
+ * vectors are copied to FP64, orthonormalised on the device by classical Gram-Schmidt applied
+ * twice (CGS2), and kept in FP64 and in store_dt (F64 or F32) for the operator of that
+ * precision.  The weights w_i = sign(lambda_i) - p(lambda_i / lmax) are formed per call from the
+ * polynomial handle.  1 <= n_ev <= 12 V.  Errors: EINVAL, EDIMS, EDTYPE, ENONFINITE, ENOMEM,
+ * EHIP; EDEFL when a vector is numerically dependent on the previous ones (checked on the host
+ * after a stream synchronisation at the end of the call). */
+int ovl_defl_create(ovl_defl **d, const int32_t dims[4], const void *phi_dev, int in_dt,
+                    const double *lambda_host, int n_ev, int store_dt, void *stream);
+int ovl_defl_destroy(ovl_defl *d);
+/* Copy of the orthonormal FP64 basis into phi_out_dev ([n_ev][4][3][V] complex double). */
+int ovl_defl_basis(const ovl_defl *d, void *phi_out_dev, void *stream);
+
+/* ---- operators ------------------------------------------------------------------------------ */
+
+/* out = (D_W - m_W) in (Sec. 2, eq. 2), or its adjoint gamma5 (D_W - m_W) gamma5 when dagger != 0.
+ * in/out: [nrhs][4][3][V] complex of spin_dt, nrhs >= 1.  m_W = 0 gives D_W itself. */
+int ovl_wilson_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, int spin_dt,
+                     double m_W, int dagger, void *stream);
+
+/* out = K in = gamma5 (D_W - m_W) in (Sec. 2, definition of K). */
+int ovl_kernel_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, int spin_dt,
+                     double m_W, void *stream);
+
+/* out = sum_m alpha_m T_m(X) in + [d != NULL] sum_i phi_i w_i phi_i^+ in  (Sec. 2, eq. 3),
+ * evaluated by the Clenshaw recurrence b_k = alpha_k in + 2 X b_{k+1} - b_{k+2}, one fused
+ * stencil + polynomial kernel per K application.  n_alpha - 1 K applications. */
+int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, void *out,
+                   const void *in, int nrhs, int spin_dt, void *stream);
+
+/* out = D[mu] in (Sec. 2, eq. 1) with the sign function above, or D[mu]^+ in = gamma5 D[mu]
+ * gamma5 in when dagger != 0.  mu is the overlap mass parameter. */
+int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                      int dagger, void *out, const void *in, int nrhs, int spin_dt, void *stream);
+
+/* c_dev[r][i] = phi_i^+ in_r (complex double, interleaved; n_ev * nrhs entries), FP64
+ * accumulation with a deterministic two-pass reduction (Sec. 2, eq. 3 projection). */
+int ovl_defl_project(const ovl_defl *d, double *c_dev, const void *in, int nrhs, int spin_dt,
+                     void *stream);
+
+/* inout_r += sum_i phi_i (w_host[i] * c_dev[r][i])  (Sec. 2, eq. 3 correction).  With w = 1 it
+ * is the adjoint of ovl_defl_project. */
+int ovl_defl_correct(const ovl_defl *d, void *inout, const double *c_dev, const double *w_host,
+                     int nrhs, int spin_dt, void *stream);
+
+/* ---- link derivatives (HMC fermion force building blocks) -------------------------------- */
+
+/* G_dev[mu][a][b][site] (complex, dtype spin_dt) = dL/dRe U + i dL/dIm U for
+ * L = Re <chi, D_W psi> (Sec. 2, eq. 2 is affine in U).  Single right-hand side.
+ * accumulate != 0 adds to G_dev instead of overwriting it. */
+int ovl_wilson_link_vjp(const ovl_gauge *g, void *G_dev, const void *chi, const void *psi,
+                        int spin_dt, int accumulate, void *stream);
+
+/* G_dev = d Re <chi, p(X) psi> / dU with p the polynomial of the handle (no deflation term,
+ * lmax held fixed): reverse Clenshaw sweep on chi with the forward Chebyshev vectors of psi
+ * recomputed from checkpoints every ckpt_stride steps (0 = ceil(sqrt(N))).  Layout of G_dev as
+ * in ovl_wilson_link_vjp; single right-hand side. */
+int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const void *chi,
+                   const void *psi, int ckpt_stride, int spin_dt, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------------------------- */
+
+/* Thread-local message describing the most recent failure in this thread ("" if none). */
+const char *ovl_last_error(void);
+
+/* Read (and with clear != 0, reset) the sticky device flags of a gauge handle (OVL_FLAG_*).
+ * Synchronises the device. */
+int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear);
+
+/* Kernel timing of the fused Chebyshev step: when enabled, HIP events are recorded on the call's
+ * stream around every launch of that kernel by the calling thread; ovl_timing_read returns the
+ * summed duration (ms) and launch count since the last reset (synchronising the recorded events)
+ * and resets the counters. */
+int ovl_timing_enable(int on);
+int ovl_timing_read(double *total_ms, int64_t *launches);
+
+/* Library version string. */
+const char *ovl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OVL_H */

@@ -1,0 +1,12 @@
+"""MI355X-native overlap-operator library (Cundy & Lee, "Overlap fermions on GPUs", arXiv:1510.06897).
+
+The compute path is libovl.so (hand-written HIP kernels for gfx950 behind a C ABI, include/ovl.h);
+this package is its PyTorch binding.  Importing the operators loads the library and raises if it
+has not been built (``python -m paper_1510_06897_amd.build``).
+"""
+from ._lib import OvlError, load  # noqa: F401
+from .api import (  # noqa: F401
+    M_W, Deflation, GaugeField, Polynomial, SignFunction, cheb_sign_coeffs, defl_correct,
+    defl_project, kernel_apply, overlap_apply, sign_apply, sign_force, timing_enable,
+    timing_read, wilson_apply, wilson_link_vjp,
+)

@@ -1,0 +1,83 @@
+"""ctypes declarations of libovl.so (the C ABI declared in include/ovl.h).
+
+Loading fails loudly: there is no fallback implementation of any operator.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libovl.so")
+
+OVL_F64, OVL_F32, OVL_BF16 = 0, 1, 2
+STATUS = {
+    0: "OVL_OK", -1: "OVL_EINVAL", -2: "OVL_EDIMS", -3: "OVL_EDTYPE", -4: "OVL_EALIAS",
+    -5: "OVL_ENOMEM", -6: "OVL_EHIP", -7: "OVL_ENONFINITE", -8: "OVL_EDIVERGED", -9: "OVL_EDEFL",
+}
+FLAG_NONFINITE, FLAG_DIVERGED = 0x1, 0x2
+
+# name -> (restype, argtypes); every symbol include/ovl.h declares
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_i32x4 = ctypes.POINTER(ctypes.c_int32)
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "ovl_gauge_create": (_i, [ctypes.POINTER(_vp), _i32x4, _vp, _i, _i, _vp]),
+    "ovl_gauge_destroy": (_i, [_vp]),
+    "ovl_gauge_info": (_i, [_vp, _i32x4, ctypes.POINTER(_i)]),
+    "ovl_poly_create": (_i, [ctypes.POINTER(_vp), _dp, _i, _d, _d]),
+    "ovl_poly_destroy": (_i, [_vp]),
+    "ovl_poly_eval": (_i, [_vp, _d, _dp]),
+    "ovl_cheb_sign_coeffs": (_i, [_i, _d, _dp, ctypes.POINTER(_i)]),
+    "ovl_defl_create": (_i, [ctypes.POINTER(_vp), _i32x4, _vp, _i, _dp, _i, _i, _vp]),
+    "ovl_defl_destroy": (_i, [_vp]),
+    "ovl_defl_basis": (_i, [_vp, _vp, _vp]),
+    "ovl_wilson_apply": (_i, [_vp, _vp, _vp, _i, _i, _d, _i, _vp]),
+    "ovl_kernel_apply": (_i, [_vp, _vp, _vp, _i, _i, _d, _vp]),
+    "ovl_sign_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
+    "ovl_overlap_apply": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
+    "ovl_defl_project": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
+    "ovl_defl_correct": (_i, [_vp, _vp, _vp, _dp, _i, _i, _vp]),
+    "ovl_wilson_link_vjp": (_i, [_vp, _vp, _vp, _vp, _i, _i, _vp]),
+    "ovl_sign_force": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
+    "ovl_last_error": (ctypes.c_char_p, []),
+    "ovl_status_flags": (_i, [_vp, ctypes.POINTER(ctypes.c_uint32), _i]),
+    "ovl_timing_enable": (_i, [_i]),
+    "ovl_timing_read": (_i, [_dp, ctypes.POINTER(ctypes.c_int64)]),
+    "ovl_version": (ctypes.c_char_p, []),
+}
+
+_LIB = None
+
+
+class OvlError(RuntimeError):
+    def __init__(self, name, code, msg):
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+        super().__init__(f"{name} failed with {self.status}: {msg}")
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libovl.so (built by ``paper_1510_06897_amd.build``); raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1510_06897_amd.build`"
+                          " (there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def call(name, *args):
+    lib = load()
+    rc = getattr(lib, name)(*args)
+    if rc != 0:
+        msg = lib.ovl_last_error().decode(errors="replace")
+        raise OvlError(name, rc, msg)
+    return rc

@@ -1,0 +1,251 @@
+// Shared device-side building blocks: complex arithmetic, storage formats, lattice geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ovl {
+
+// ---------------------------------------------------------------------------------------------
+// complex numbers in the compute precision (float or double)
+template <class T>
+struct cx {
+  T re, im;
+};
+
+template <class T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) {
+  return cx<T>{r, i};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return cx<T>{a.re + b.re, a.im + b.im};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return cx<T>{a.re - b.re, a.im - b.im};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a) {
+  return cx<T>{-a.re, -a.im};
+}
+template <class T>
+__host__ __device__ __forceinline__ cx<T> scale(cx<T> a, T s) {
+  return cx<T>{a.re * s, a.im * s};
+}
+// i * a
+template <class T>
+__host__ __device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  return cx<T>{-a.im, a.re};
+}
+// -i * a
+template <class T>
+__host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
+  return cx<T>{a.im, -a.re};
+}
+// acc + a * b
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cmadd(cx<T> acc, cx<T> a, cx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + conj(a) * b
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cjmadd(cx<T> acc, cx<T> a, cx<T> b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
+// a * b
+template <class T>
+__host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return cmadd(cx<T>{T(0), T(0)}, a, b);
+}
+
+// ---------------------------------------------------------------------------------------------
+// storage formats of one complex element.  F64: double2, F32: float2, BF16: two bfloat16 in one
+// 32-bit word (real part in the low half).
+enum : int { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+struct bf16c {
+  uint32_t bits;
+};
+
+template <int DT>
+struct storage;
+template <>
+struct storage<DT_F64> {
+  using elem = double2;
+  using real = double;
+  static constexpr int bytes = 16;
+};
+template <>
+struct storage<DT_F32> {
+  using elem = float2;
+  using real = float;
+  static constexpr int bytes = 8;
+};
+template <>
+struct storage<DT_BF16> {
+  using elem = bf16c;
+  using real = float;
+  static constexpr int bytes = 4;
+};
+
+__host__ __device__ __forceinline__ float bf16_lo(uint32_t w) {
+  return __uint_as_float(w << 16);
+}
+__host__ __device__ __forceinline__ float bf16_hi(uint32_t w) {
+  return __uint_as_float(w & 0xffff0000u);
+}
+// float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
+__host__ __device__ __forceinline__ uint32_t f32_to_bf16_bits(float f) {
+  uint32_t b = __float_as_uint(f);
+  uint32_t lsb = (b >> 16) & 1u;
+  return (b + 0x7fffu + lsb) >> 16;
+}
+
+// Raw buffer resources: every array is addressed as (scalar base, scalar byte offset of the
+// spin-colour component, 32-bit per-lane byte offset of the site).  Component offsets stay in
+// SGPRs, one VGPR per neighbour site carries the lane part, and reads outside the declared range
+// return zero instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  // dword3 0x00020000: raw (untyped) 32-bit data format on gfx9-class devices
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class SE>
+struct elem_traits;
+template <>
+struct elem_traits<double2> {
+  static constexpr uint32_t bytes = 16;
+};
+template <>
+struct elem_traits<float2> {
+  static constexpr uint32_t bytes = 8;
+};
+template <>
+struct elem_traits<bf16c> {
+  static constexpr uint32_t bytes = 4;
+};
+
+template <class SE, class C>
+struct bio;
+template <class C>
+struct bio<double2, C> {
+  static __device__ __forceinline__ cx<C> ld(rsrc_t r, uint32_t voff, uint32_t soff) {
+    u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    const double re = __hiloint2double((int)w.y, (int)w.x);
+    const double im = __hiloint2double((int)w.w, (int)w.z);
+    return cx<C>{C(re), C(im)};
+  }
+  static __device__ __forceinline__ void st(rsrc_t r, uint32_t voff, uint32_t soff, cx<C> v) {
+    const double re = double(v.re), im = double(v.im);
+    u32x4 w;
+    w.x = (unsigned)__double2loint(re);
+    w.y = (unsigned)__double2hiint(re);
+    w.z = (unsigned)__double2loint(im);
+    w.w = (unsigned)__double2hiint(im);
+    __builtin_amdgcn_raw_buffer_store_b128(w, r, voff, soff, 0);
+  }
+};
+template <class C>
+struct bio<float2, C> {
+  static __device__ __forceinline__ cx<C> ld(rsrc_t r, uint32_t voff, uint32_t soff) {
+    u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return cx<C>{C(__uint_as_float(w.x)), C(__uint_as_float(w.y))};
+  }
+  static __device__ __forceinline__ void st(rsrc_t r, uint32_t voff, uint32_t soff, cx<C> v) {
+    u32x2 w;
+    w.x = __float_as_uint(float(v.re));
+    w.y = __float_as_uint(float(v.im));
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, voff, soff, 0);
+  }
+};
+template <class C>
+struct bio<bf16c, C> {
+  static __device__ __forceinline__ cx<C> ld(rsrc_t r, uint32_t voff, uint32_t soff) {
+    const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    return cx<C>{C(bf16_lo(w)), C(bf16_hi(w))};
+  }
+};
+
+// element `comp * V + site` of an array of SE described by resource r
+template <class C, class SE>
+__device__ __forceinline__ cx<C> bld(rsrc_t r, uint32_t comp_soff, uint32_t site) {
+  return bio<SE, C>::ld(r, site * elem_traits<SE>::bytes, comp_soff);
+}
+template <class C, class SE>
+__device__ __forceinline__ void bst(rsrc_t r, uint32_t comp_soff, uint32_t site, cx<C> v) {
+  bio<SE, C>::st(r, site * elem_traits<SE>::bytes, comp_soff, v);
+}
+
+// plain pointer access for the small set-up kernels
+template <class C>
+__device__ __forceinline__ cx<C> load_c(const double2 *p, int64_t i) {
+  double2 v = p[i];
+  return cx<C>{C(v.x), C(v.y)};
+}
+template <class C>
+__device__ __forceinline__ cx<C> load_c(const float2 *p, int64_t i) {
+  float2 v = p[i];
+  return cx<C>{C(v.x), C(v.y)};
+}
+template <class C>
+__device__ __forceinline__ void store_c(double2 *p, int64_t i, cx<C> v) {
+  p[i] = make_double2(double(v.re), double(v.im));
+}
+template <class C>
+__device__ __forceinline__ void store_c(float2 *p, int64_t i, cx<C> v) {
+  p[i] = make_float2(float(v.re), float(v.im));
+}
+
+// ---------------------------------------------------------------------------------------------
+// lattice geometry: extents, strides of the site index x + Lx (y + Ly (z + Lz t))
+struct Geom {
+  int L[4];
+  int stride[4];
+  int V;
+};
+
+__host__ __device__ __forceinline__ void site_coords(const Geom &g, int s, int c[4]) {
+  c[0] = s % g.L[0];
+  int r = s / g.L[0];
+  c[1] = r % g.L[1];
+  r /= g.L[1];
+  c[2] = r % g.L[2];
+  c[3] = r / g.L[2];
+}
+
+// forward and backward neighbour site indices in all four directions (periodic)
+__host__ __device__ __forceinline__ void neighbours(const Geom &g, int s, int fwd[4], int bwd[4]) {
+  int c[4];
+  site_coords(g, s, c);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const int st = g.stride[mu];
+    const int wrap = (g.L[mu] - 1) * st;
+    fwd[mu] = (c[mu] + 1 == g.L[mu]) ? s - wrap : s + st;
+    bwd[mu] = (c[mu] == 0) ? s + wrap : s - st;
+  }
+}
+
+// map a workgroup id so that each of the 8 XCDs (which receive workgroups round robin) works on
+// a contiguous range of logical blocks, keeping stencil neighbours in the same L2
+__device__ __forceinline__ int xcd_block(int b, int n, int remap) {
+  if (!remap) return b;
+  const int xcd = b & 7, local = b >> 3;
+  const int per = n >> 3, rem = n & 7;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+}  // namespace ovl

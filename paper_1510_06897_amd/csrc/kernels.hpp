@@ -1,0 +1,356 @@
+// HIP kernels of the overlap-operator library (gfx950, wave64).
+//
+// One thread per lattice site (and right-hand side), site-fastest coalesced loads of spinors and
+// links, half-spinor projection of every hop, and every per-step vector operation of the
+// Chebyshev recurrence fused into the stencil kernel, so one K application of the recurrence is
+// one pass over memory (the kernel merging the paper credits with its largest gain, Sec. 2).
+#pragma once
+
+#include "common.hpp"
+#include "stencil.hpp"
+
+namespace ovl {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+
+// ---------------------------------------------------------------------------------------------
+// block-wide FP64 sum of NV values per thread, result valid in thread 0 (fixed order: wave
+// butterfly, then waves in index order -> deterministic)
+template <int NV>
+__device__ __forceinline__ void block_sum(double v[NV], double *lds /* >= NV * 16 */) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwave = (blockDim.x + 63) >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[wave * NV + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nwave; ++w) s += lds[w * NV + k];
+      v[k] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fused stencil step.  For every site and right-hand side r:
+//   y   = kd v(x) + kh hop(v)(x)              (hop = the sum in eq. 2; v read with gamma5 if v_g5)
+//   y   = gamma5 y                            (if y_g5)
+//   res = y + a src(x) + t w(x)               (src read with gamma5 if src_g5; w may alias out)
+// final modes add the deflation correction sum_i phi_i w_i c_i and combine into the overlap
+// operator; they also emit FP64 block partials of ||res||^2 and ||src||^2.
+enum : int { MODE_STEP = 0, MODE_SIGN = 1, MODE_OVERLAP = 2, MODE_OVERLAP_DAG = 3 };
+
+struct StepParams {
+  const void *v;
+  const void *src;
+  const void *w;
+  void *out;
+  const void *U;
+  Geom g;
+  double kd, kh, a, t;
+  int v_g5, src_g5, y_g5;
+  int mode;
+  double mu;
+  const void *phi;         // deflation basis [n_ev][12][V] (spinor storage), final modes
+  int n_ev;
+  const double2 *c;        // [nrhs][n_ev] projections
+  const double *wdefl;     // [n_ev] weights
+  double *norm_partial;    // [nblk][nrhs][2] or null
+  int remap;
+};
+
+template <class C, class SE, class LE>
+__global__ void __launch_bounds__(kBlock) step_kernel(StepParams p) {
+  __shared__ double lds[2 * 16];
+  const int nblk = gridDim.x;
+  const int b = xcd_block(blockIdx.x, nblk, p.remap);
+  const int site = b * kBlock + threadIdx.x;
+  const int r = blockIdx.y;
+  const int V = p.g.V;
+  const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;  // component stride (bytes)
+  const uint32_t vb = 12u * cs;                               // one right-hand side (bytes)
+  const int64_t base = (int64_t)r * 12 * V;
+  double nrm[2] = {0.0, 0.0};
+  if (site < V) {
+    const rsrc_t v = make_rsrc(reinterpret_cast<const SE *>(p.v) + base, vb);
+    const LinkRes<LE> U = link_res<LE>(p.U, V);
+    cx<C> acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
+    hop_site<C, SE, LE>(acc, v, U, p.g, site, p.v_g5 != 0);
+    const C kd = C(p.kd), kh = C(p.kh);
+    cx<C> res[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      cx<C> vx = bld<C, SE>(v, i * cs, site);
+      if (p.v_g5 && i >= 6) vx = -vx;
+      cx<C> y = mk<C>(kd * vx.re + kh * acc[i].re, kd * vx.im + kh * acc[i].im);
+      if (p.y_g5 && i >= 6) y = -y;
+      res[i] = y;
+    }
+    cx<C> srcx[12];
+    const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
+    if (need_src) {
+      const rsrc_t s = make_rsrc(reinterpret_cast<const SE *>(p.src) + base, vb);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) srcx[i] = bld<C, SE>(s, i * cs, site);
+    }
+    if (p.a != 0.0) {
+      const C a = C(p.a);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        cx<C> sx = (p.src_g5 && i >= 6) ? -srcx[i] : srcx[i];
+        res[i] = res[i] + scale(sx, a);
+      }
+    }
+    if (p.w != nullptr) {
+      const rsrc_t w = make_rsrc(reinterpret_cast<const SE *>(p.w) + base, vb);
+      const C t = C(p.t);
+#pragma unroll
+      for (int i = 0; i < 12; ++i) res[i] = res[i] + scale(bld<C, SE>(w, i * cs, site), t);
+    }
+    if (p.mode >= MODE_SIGN) {
+      for (int e = 0; e < p.n_ev; ++e) {
+        const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(p.phi) + (int64_t)e * 12 * V, vb);
+        const double2 ce = p.c[r * p.n_ev + e];
+        const double we = p.wdefl[e];
+        const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
+#pragma unroll
+        for (int i = 0; i < 12; ++i) res[i] = cmadd(res[i], bld<C, SE>(ph, i * cs, site), d);
+      }
+      double so = 0.0, si = 0.0;
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        so += double(res[i].re) * double(res[i].re) + double(res[i].im) * double(res[i].im);
+        si += double(srcx[i].re) * double(srcx[i].re) + double(srcx[i].im) * double(srcx[i].im);
+      }
+      nrm[0] = so;
+      nrm[1] = si;
+      if (p.mode == MODE_OVERLAP || p.mode == MODE_OVERLAP_DAG) {
+        const C hp = C(0.5 * (1.0 + p.mu)), hm = C(0.5 * (1.0 - p.mu));
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+          cx<C> sg = (p.mode == MODE_OVERLAP && i >= 6) ? -res[i] : res[i];
+          res[i] = scale(srcx[i], hp) + scale(sg, hm);
+        }
+      }
+    }
+    const rsrc_t o = make_rsrc(reinterpret_cast<SE *>(p.out) + base, vb);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) bst<C, SE>(o, i * cs, site, res[i]);
+  }
+  if (p.norm_partial != nullptr) {
+    block_sum<2>(nrm, lds);
+    if (threadIdx.x == 0) {
+      p.norm_partial[((int64_t)b * gridDim.y + r) * 2 + 0] = nrm[0];
+      p.norm_partial[((int64_t)b * gridDim.y + r) * 2 + 1] = nrm[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// final check of the recurrence: ||res||^2 <= bound2 ||src||^2 and finite, per right-hand side
+__global__ void norm_check_kernel(const double *partial, int nblk, int nrhs, double bound2,
+                                  uint32_t *flags, double *norms_out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double so = 0.0, si = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    so += partial[((int64_t)b * nrhs + r) * 2 + 0];
+    si += partial[((int64_t)b * nrhs + r) * 2 + 1];
+  }
+  if (norms_out != nullptr) {
+    norms_out[2 * r + 0] = so;
+    norms_out[2 * r + 1] = si;
+  }
+  uint32_t f = 0;
+  if (!isfinite(so)) f |= 1u;
+  else if (so > bound2 * si * (1.0 + 1e-6) + 1e-300) f |= 2u;
+  if (f) atomicOr(flags, f);
+}
+
+// ---------------------------------------------------------------------------------------------
+// deflation projection, pass 1: partial[b][r][i] = sum over this block's sites of
+// conj(phi_i) . psi_r (12 components), FP64 accumulation, CH eigenvectors per block row
+template <class SE, int CH>
+__global__ void __launch_bounds__(kBlock)
+    project_partial_kernel(const SE *__restrict__ phi, int n_ev, const SE *__restrict__ psi,
+                           int psi_g5, int V, double2 *__restrict__ partial) {
+  __shared__ double lds[2 * CH * 16];
+  const int i0 = blockIdx.y * CH;
+  const int r = blockIdx.z;
+  const int nblk = gridDim.x;
+  const int nrhs = gridDim.z;
+  double acc[2 * CH];
+#pragma unroll
+  for (int j = 0; j < 2 * CH; ++j) acc[j] = 0.0;
+  const SE *__restrict__ ps = psi + (int64_t)r * 12 * V;
+  for (int site = blockIdx.x * kBlock + threadIdx.x; site < V; site += nblk * kBlock) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      cx<double> x = load_c<double>(ps, (int64_t)i * V + site);
+      if (psi_g5 && i >= 6) x = -x;
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        if (i0 + j < n_ev) {
+          const cx<double> f = load_c<double>(phi, ((int64_t)(i0 + j) * 12 + i) * V + site);
+          acc[2 * j] = fma(f.re, x.re, fma(f.im, x.im, acc[2 * j]));
+          acc[2 * j + 1] = fma(f.re, x.im, fma(-f.im, x.re, acc[2 * j + 1]));
+        }
+      }
+    }
+  }
+  block_sum<2 * CH>(acc, lds);
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < CH && i0 + j < n_ev; ++j)
+      partial[((int64_t)blockIdx.x * nrhs + r) * n_ev + i0 + j] = make_double2(acc[2 * j], acc[2 * j + 1]);
+  }
+}
+
+// pass 2: c[r][i] = sum_b partial[b][r][i] in block order (deterministic)
+__global__ void project_reduce_kernel(const double2 *__restrict__ partial, int nblk, int count,
+                                      double2 *__restrict__ c) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  double re = 0.0, im = 0.0;
+  for (int b = 0; b < nblk; ++b) {
+    const double2 v = partial[(int64_t)b * count + k];
+    re += v.x;
+    im += v.y;
+  }
+  c[k] = make_double2(re, im);
+}
+
+// inout_r += sum_i phi_i (wscale * w_i * c[r][i])   (w == null -> w_i = 1)
+template <class C, class SE>
+__global__ void __launch_bounds__(kBlock)
+    correct_kernel(SE *inout, const SE *__restrict__ phi, int n_ev, const double2 *__restrict__ c,
+                   const double *__restrict__ w, double wscale, int V) {
+  const int site = blockIdx.x * kBlock + threadIdx.x;
+  const int r = blockIdx.y;
+  if (site >= V) return;
+  SE *io = inout + (int64_t)r * 12 * V;
+  cx<C> acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = load_c<C>(io, (int64_t)i * V + site);
+  for (int e = 0; e < n_ev; ++e) {
+    const double2 ce = c[r * n_ev + e];
+    const double we = (w ? w[e] : 1.0) * wscale;
+    const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      acc[i] = cmadd(acc[i], load_c<C>(phi, ((int64_t)e * 12 + i) * V + site), d);
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) store_c(io, (int64_t)i * V + site, acc[i]);
+}
+
+// v *= 1 / sqrt(nrm2[0].x); records the norm before scaling into norms[slot]
+__global__ void normalize_kernel(double2 *v, const double2 *nrm2, int64_t n, double *norms,
+                                 int slot) {
+  const double s = nrm2[0].x;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0 && norms != nullptr) norms[slot] = s;
+  if (k >= n) return;
+  const double inv = 1.0 / sqrt(s);
+  double2 x = v[k];
+  v[k] = make_double2(x.x * inv, x.y * inv);
+}
+
+// records nrm2[0].x into norms[slot]
+__global__ void record_kernel(const double2 *nrm2, double *norms, int slot) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) norms[slot] = nrm2[0].x;
+}
+
+// ---------------------------------------------------------------------------------------------
+// element conversion between storage formats
+__device__ __forceinline__ void cvt(double2 s, double2 &d) { d = s; }
+__device__ __forceinline__ void cvt(float2 s, double2 &d) { d = make_double2(s.x, s.y); }
+__device__ __forceinline__ void cvt(double2 s, float2 &d) { d = make_float2((float)s.x, (float)s.y); }
+__device__ __forceinline__ void cvt(float2 s, float2 &d) { d = s; }
+__device__ __forceinline__ void cvt(double2 s, bf16c &d) {
+  d.bits = f32_to_bf16_bits((float)s.x) | (f32_to_bf16_bits((float)s.y) << 16);
+}
+__device__ __forceinline__ void cvt(float2 s, bf16c &d) {
+  d.bits = f32_to_bf16_bits(s.x) | (f32_to_bf16_bits(s.y) << 16);
+}
+
+template <class S, class D>
+__global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) cvt(src[k], dst[k]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Link vector-Jacobian product of the hopping term.  For L = Re<a, D_W t> (a read with gamma5
+// when a_g5), with h^-(f) = projection of (1 - gamma_mu) f and h^+(f) of (1 + gamma_mu) f:
+//   G_mu(x)_ij (+)= coef * (-1/2) sum_{k<2} [ h^-(a(x))_{k,i} conj(h^-(t(x+mu))_{k,j})
+//                                           + h^+(t(x))_{k,i} conj(h^+(a(x+mu))_{k,j}) ]
+// ((1 -+ gamma_mu)/2 are Hermitian projectors, so the 4-spin sums reduce to half-spinor sums.)
+template <int MU, class C, class SE, class GE>
+__device__ __forceinline__ void vjp_dir(rsrc_t G, uint32_t gs, rsrc_t a, rsrc_t t, uint32_t cs,
+                                        uint32_t site, uint32_t fwd, bool a_g5,
+                                        const cx<C> ax_u[2][3], const cx<C> ax_d[2][3],
+                                        const cx<C> tx_u[2][3], const cx<C> tx_d[2][3], C coef,
+                                        bool accumulate) {
+  cx<C> u[2][3], d[2][3];
+  cx<C> hma[2][3], hmt[2][3], hpt[2][3], hpa[2][3];
+  project<MU, true>(ax_u, ax_d, hma);
+  project<MU, false>(tx_u, tx_d, hpt);
+  load_spinor<C, SE>(t, cs, fwd, false, u, d);
+  project<MU, true>(u, d, hmt);
+  load_spinor<C, SE>(a, cs, fwd, a_g5, u, d);
+  project<MU, false>(u, d, hpa);
+  const uint32_t gbase = (uint32_t)MU * 9u * gs;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<C> s = mk<C>(0, 0);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        s = cjmadd(s, hmt[k][j], hma[k][i]);
+        s = cjmadd(s, hpa[k][j], hpt[k][i]);
+      }
+      s = scale(s, coef);
+      const uint32_t so = gbase + (i * 3 + j) * gs;
+      if (accumulate) s = s + bld<C, GE>(G, so, site);
+      bst<C, GE>(G, so, site, s);
+    }
+}
+
+// G has the layout [4][3][3][V] (36 V elements of GE, < 4 GiB); a and t are single spinors
+template <class C, class SE, class GE>
+__global__ void __launch_bounds__(kBlock)
+    link_vjp_kernel(GE *G, const SE *a, const SE *t, Geom g, double coef, int a_g5,
+                    int accumulate, int remap) {
+  const int b = xcd_block(blockIdx.x, gridDim.x, remap);
+  const int site = b * kBlock + threadIdx.x;
+  if (site >= g.V) return;
+  int fwd[4], bwd[4];
+  neighbours(g, site, fwd, bwd);
+  const uint32_t cs = (uint32_t)g.V * elem_traits<SE>::bytes;
+  const uint32_t gs = (uint32_t)g.V * elem_traits<GE>::bytes;
+  const rsrc_t ra = make_rsrc(a, 12u * cs), rt = make_rsrc(t, 12u * cs);
+  const rsrc_t rg = make_rsrc(G, 36u * gs);
+  cx<C> au[2][3], ad[2][3], tu[2][3], td[2][3];
+  load_spinor<C, SE>(ra, cs, site, a_g5 != 0, au, ad);
+  load_spinor<C, SE>(rt, cs, site, false, tu, td);
+  const C cf = C(-0.5 * coef);
+  const bool acc = accumulate != 0, g5 = a_g5 != 0;
+  vjp_dir<0, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[0], g5, au, ad, tu, td, cf, acc);
+  vjp_dir<1, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[1], g5, au, ad, tu, td, cf, acc);
+  vjp_dir<2, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[2], g5, au, ad, tu, td, cf, acc);
+  vjp_dir<3, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[3], g5, au, ad, tu, td, cf, acc);
+}
+
+}  // namespace ovl

@@ -1,0 +1,916 @@
+// C ABI of libovl.so: argument validation, handle management and kernel orchestration.
+// The declarations and the contract of every entry point are in include/ovl.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/ovl.h"
+#include "kernels.hpp"
+
+namespace ovl {
+bool cheb_sign_coeffs(int degree, double eps, std::vector<double> &alpha);
+double cheb_eval(const std::vector<double> &alpha, double x);
+}  // namespace ovl
+
+using namespace ovl;
+
+// ---------------------------------------------------------------------------------------------
+// error reporting
+namespace {
+
+thread_local char g_err[1024] = "";
+
+int fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      (void)hipGetLastError();                                                            \
+      return fail(e_ == hipErrorOutOfMemory ? OVL_ENOMEM : OVL_EHIP, "%s failed: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+    }                                                                                     \
+  } while (0)
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+int elem_bytes(int dt) { return dt == OVL_F64 ? 16 : dt == OVL_F32 ? 8 : dt == OVL_BF16 ? 4 : 0; }
+
+std::atomic<uint64_t> g_poly_serial{1};
+
+// stream-ordered temporaries from the device's default pool, kept cached between calls
+std::once_flag g_pool_once[64];
+int setup_pool(int dev) {
+  hipMemPool_t pool;
+  HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t thr = UINT64_MAX;
+  HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+  return OVL_OK;
+}
+
+struct Scratch {
+  void *p = nullptr;
+  hipStream_t s = nullptr;
+  ~Scratch() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev >= 0 && dev < 64) {
+    int rc = OVL_OK;
+    std::call_once(g_pool_once[dev], [&] { rc = setup_pool(dev); });
+    if (rc != OVL_OK) return rc;
+  }
+  sc.s = s;
+  HIP_TRY(hipMallocAsync(&sc.p, std::max<size_t>(bytes, 256), s));
+  return OVL_OK;
+}
+
+// kernel timing of the fused Chebyshev step (see ovl_timing_enable)
+std::atomic<int> g_timing{0};
+std::mutex g_timing_mu;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timing_events;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// handles
+struct ovl_gauge {
+  Geom g;
+  int store_dt;
+  int device;
+  void *links;        // [4][3][3][V] complex in store_dt
+  uint32_t *flags;    // sticky device flags
+};
+
+struct ovl_poly {
+  std::vector<double> alpha;
+  double lmax, m_W;
+  double bound;       // sup_{|x| <= 1} |p(x)| (sampled, with margin)
+  uint64_t serial;
+};
+
+struct ovl_defl {
+  Geom g;
+  int n_ev;
+  int store_dt;
+  double2 *phi64;     // [n_ev][12][V] orthonormal, FP64
+  void *phi_store;    // same in store_dt (== phi64 for F64)
+  std::vector<double> lambda;
+  double *w_dev;      // weights for the polynomial with serial w_serial
+  std::vector<double> w_host;
+  uint64_t w_serial;
+  std::mutex mu;
+};
+
+namespace {
+
+int check_dims(const int32_t dims[4], Geom &g) {
+  if (!dims) return fail(OVL_EINVAL, "dims is NULL");
+  int64_t v = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 1 || dims[i] > (1 << 24))
+      return fail(OVL_EDIMS, "lattice extent dims[%d] = %d out of range [1, 2^24]", i, dims[i]);
+    v *= dims[i];
+    if (v > (int64_t)INT32_MAX) return fail(OVL_EDIMS, "lattice volume exceeds 2^31 - 1 sites");
+  }
+  g.V = (int)v;
+  int st = 1;
+  for (int i = 0; i < 4; ++i) {
+    g.L[i] = dims[i];
+    g.stride[i] = st;
+    st *= dims[i];
+  }
+  return OVL_OK;
+}
+
+// operator precision of (spinor dtype, link storage) pairs
+enum Prec { P_F64 = 0, P_F32 = 1, P_F32_BF16 = 2, P_BAD = -1 };
+Prec precision(int spin_dt, int store_dt) {
+  if (spin_dt == OVL_F64 && store_dt == OVL_F64) return P_F64;
+  if (spin_dt == OVL_F32 && store_dt == OVL_F32) return P_F32;
+  if (spin_dt == OVL_F32 && store_dt == OVL_BF16) return P_F32_BF16;
+  return P_BAD;
+}
+
+// every array a kernel addresses through one buffer resource must span < 4 GiB
+bool fits_u32(uint64_t n_elems, int dt) { return n_elems * (uint64_t)elem_bytes(dt) < (1ull << 32); }
+
+int check_spinor_call(const ovl_gauge *g, const void *out, const void *in, int nrhs, int spin_dt,
+                      Prec &prec) {
+  if (!g) return fail(OVL_EINVAL, "gauge handle is NULL");
+  if (!out || !in) return fail(OVL_EINVAL, "spinor pointer is NULL");
+  if (nrhs < 1 || nrhs > 65535) return fail(OVL_EINVAL, "nrhs = %d out of range [1, 65535]", nrhs);
+  if (spin_dt != OVL_F64 && spin_dt != OVL_F32)
+    return fail(OVL_EDTYPE, "spinor dtype %d not supported (F64 or F32)", spin_dt);
+  if (!fits_u32(12ull * g->g.V, spin_dt))
+    return fail(OVL_EDIMS, "one right-hand side of %d sites exceeds 4 GiB", g->g.V);
+  prec = precision(spin_dt, g->store_dt);
+  if (prec == P_BAD)
+    return fail(OVL_EDTYPE, "spinor dtype %d cannot be combined with link storage %d", spin_dt,
+                g->store_dt);
+  const size_t bytes = (size_t)nrhs * 12 * g->g.V * elem_bytes(spin_dt);
+  const char *o = (const char *)out, *i = (const char *)in;
+  if (o < i + bytes && i < o + bytes)
+    return fail(OVL_EALIAS, "output overlaps the input (the stencil reads neighbour sites)");
+  return OVL_OK;
+}
+
+int grid_blocks(int V) { return (V + kBlock - 1) / kBlock; }
+
+template <class C, class SE, class LE>
+int launch_step(const StepParams &p, int nrhs, hipStream_t s, bool timed) {
+  dim3 grid(grid_blocks(p.g.V), nrhs);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    e0 = pool_event();
+    e1 = pool_event();
+  }
+  if (e0 && e1) HIP_TRY(hipEventRecord(e0, s));
+  step_kernel<C, SE, LE><<<grid, kBlock, 0, s>>>(p);
+  HIP_TRY(hipGetLastError());
+  if (e0 && e1) {
+    HIP_TRY(hipEventRecord(e1, s));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_events.emplace_back(e0, e1);
+  }
+  return OVL_OK;
+}
+
+int dispatch_step(Prec prec, const StepParams &p, int nrhs, hipStream_t s, bool timed = false) {
+  switch (prec) {
+    case P_F64: return launch_step<double, double2, double2>(p, nrhs, s, timed);
+    case P_F32: return launch_step<float, float2, float2>(p, nrhs, s, timed);
+    case P_F32_BF16: return launch_step<float, float2, bf16c>(p, nrhs, s, timed);
+    default: return fail(OVL_EDTYPE, "bad precision");
+  }
+}
+
+StepParams base_params(const ovl_gauge *g) {
+  StepParams p;
+  std::memset(&p, 0, sizeof(p));
+  p.U = g->links;
+  p.g = g->g;
+  p.remap = 1;
+  return p;
+}
+
+// c[r][i] = phi_i^+ psi_r (FP64), scratch `partial` of n_blocks * nrhs * n_ev double2
+template <class SE>
+int project(const SE *phi, int n_ev, const SE *psi, int psi_g5, int nrhs, int V, double2 *partial,
+            int nblk, double2 *c, hipStream_t s) {
+  constexpr int CH = 8;
+  dim3 grid(nblk, (n_ev + CH - 1) / CH, nrhs);
+  project_partial_kernel<SE, CH><<<grid, kBlock, 0, s>>>(phi, n_ev, psi, psi_g5, V, partial);
+  HIP_TRY(hipGetLastError());
+  const int count = nrhs * n_ev;
+  project_reduce_kernel<<<(count + 127) / 128, 128, 0, s>>>(partial, nblk, count, c);
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
+
+int project_blocks(int V) { return std::min(grid_blocks(V), 1024); }
+
+// make sure d->w_dev holds w_i = sign(lambda_i) - p(lambda_i / lmax) for this polynomial
+int defl_weights(ovl_defl *d, const ovl_poly *p, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(d->mu);
+  if (d->w_serial == p->serial) return OVL_OK;
+  for (int i = 0; i < d->n_ev; ++i) {
+    const double l = d->lambda[i];
+    const double sg = l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0);
+    d->w_host[i] = sg - cheb_eval(p->alpha, l / p->lmax);
+  }
+  HIP_TRY(hipMemcpyAsync(d->w_dev, d->w_host.data(), sizeof(double) * d->n_ev,
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // w_host may be rewritten by the next polynomial
+  d->w_serial = p->serial;
+  return OVL_OK;
+}
+
+// Clenshaw evaluation of sum_m alpha_m T_m(X) in + deflation, final combine by `mode`.
+// b_k = alpha_k src + 2 X b_{k+1} - b_{k+2}, k = N-1 .. 1 (b_N = alpha_N src and b_{N+1} = 0
+// are folded into the first two steps), result = alpha_0 src + X b_1 - b_2.  b_k lives in
+// `out` for even k and in one scratch vector for odd k; every step updates b_{k+2} in place.
+int run_sign(const ovl_gauge *g, const ovl_poly *p, ovl_defl *d, int mode, double mu, int src_g5,
+             void *out, const void *in, int nrhs, int spin_dt, Prec prec, hipStream_t s) {
+  const int N = (int)p->alpha.size() - 1;
+  const int V = g->g.V;
+  const size_t vec_bytes = (size_t)nrhs * 12 * V * elem_bytes(spin_dt);
+  const int nblk_site = grid_blocks(V);
+  const int nblk_proj = project_blocks(V);
+  const int n_ev = d ? d->n_ev : 0;
+  // scratch: [vector][norm partials][projection partials][c]
+  size_t off_vec = 0;
+  size_t off_norm = off_vec + (N >= 2 ? ((vec_bytes + 255) / 256) * 256 : 0);
+  size_t off_part = off_norm + ((sizeof(double) * 2 * nblk_site * nrhs + 255) / 256) * 256;
+  size_t off_c = off_part + ((sizeof(double2) * (size_t)nblk_proj * nrhs * n_ev + 255) / 256) * 256;
+  size_t total = off_c + sizeof(double2) * (size_t)nrhs * n_ev + 256;
+  if (d) {
+    int rc = defl_weights(d, p, s);
+    if (rc) return rc;
+  }
+  Scratch sc;
+  int rc = scratch_alloc(sc, total, s);
+  if (rc) return rc;
+  char *base = (char *)sc.p;
+  void *ws = base + off_vec;
+  double *norm_partial = (double *)(base + off_norm);
+  double2 *partial = (double2 *)(base + off_part);
+  double2 *cvec = (double2 *)(base + off_c);
+
+  if (d) {
+    if (prec == P_F64)
+      rc = project((const double2 *)d->phi_store, n_ev, (const double2 *)in, src_g5, nrhs, V,
+                   partial, nblk_proj, cvec, s);
+    else
+      rc = project((const float2 *)d->phi_store, n_ev, (const float2 *)in, src_g5, nrhs, V,
+                   partial, nblk_proj, cvec, s);
+    if (rc) return rc;
+  }
+
+  auto buf = [&](int k) -> void * { return (k % 2 == 0) ? out : ws; };
+  const double* al = p->alpha.data();
+  const double kdiag = 4.0 - p->m_W;
+  const bool timed = g_timing.load() != 0;
+  for (int k = N - 1; k >= 0; --k) {
+    StepParams sp = base_params(g);
+    double sfac = (k == 0) ? 1.0 : 2.0;
+    double a = al[k];
+    if (k + 1 == N) {
+      sp.v = in;
+      sp.v_g5 = src_g5;
+      sfac *= al[N];
+    } else {
+      sp.v = buf(k + 1);
+      sp.v_g5 = 0;
+    }
+    if (k + 2 == N + 1) {
+      sp.w = nullptr;
+    } else if (k + 2 == N) {
+      sp.w = nullptr;
+      a -= al[N];
+    } else {
+      sp.w = buf(k + 2);
+      sp.t = -1.0;
+    }
+    sp.src = in;
+    sp.src_g5 = src_g5;
+    sp.a = a;
+    sp.y_g5 = 1;
+    sp.kd = sfac * kdiag / p->lmax;
+    sp.kh = -0.5 * sfac / p->lmax;
+    sp.out = (k == 0) ? out : buf(k);
+    if (k == 0) {
+      sp.mode = mode;
+      sp.mu = mu;
+      sp.phi = d ? d->phi_store : nullptr;
+      sp.n_ev = n_ev;
+      sp.c = cvec;
+      sp.wdefl = d ? d->w_dev : nullptr;
+      sp.norm_partial = norm_partial;
+    } else {
+      sp.mode = MODE_STEP;
+    }
+    rc = dispatch_step(prec, sp, nrhs, s, timed && k > 0);
+    if (rc) return rc;
+  }
+  const double bound = p->bound + (d ? [&] {
+    double m = 0.0;
+    for (double w : d->w_host) m = std::max(m, std::fabs(w));
+    return m;
+  }() : 0.0);
+  norm_check_kernel<<<(nrhs + 255) / 256, 256, 0, s>>>(norm_partial, nblk_site, nrhs,
+                                                      bound * bound, g->flags, nullptr);
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
+
+int check_poly(const ovl_poly *p) {
+  if (!p) return fail(OVL_EINVAL, "polynomial handle is NULL");
+  return OVL_OK;
+}
+
+int check_defl(const ovl_gauge *g, const ovl_defl *d, Prec prec) {
+  if (!d) return OVL_OK;
+  for (int i = 0; i < 4; ++i)
+    if (d->g.L[i] != g->g.L[i]) return fail(OVL_EDIMS, "deflation basis and gauge field differ in extent");
+  const int want = (prec == P_F64) ? OVL_F64 : OVL_F32;
+  if (d->store_dt != want)
+    return fail(OVL_EDTYPE, "deflation basis stored as dtype %d, operator needs %d", d->store_dt, want);
+  return OVL_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+extern "C" {
+
+const char *ovl_last_error(void) { return g_err; }
+
+const char *ovl_version(void) { return "ovl 0.1 (gfx950)"; }
+
+int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, int in_dt,
+                     int store_dt, void *stream) {
+  g_err[0] = 0;
+  if (!out || !U_dev) return fail(OVL_EINVAL, "NULL argument");
+  *out = nullptr;
+  Geom geo;
+  int rc = check_dims(dims, geo);
+  if (rc) return rc;
+  if (in_dt != OVL_F64 && in_dt != OVL_F32) return fail(OVL_EDTYPE, "link input dtype %d", in_dt);
+  if (store_dt != OVL_F64 && store_dt != OVL_F32 && store_dt != OVL_BF16)
+    return fail(OVL_EDTYPE, "link storage dtype %d", store_dt);
+  if (!fits_u32(9ull * geo.V, store_dt))
+    return fail(OVL_EDIMS, "links of one direction (%d sites) exceed 4 GiB", geo.V);
+  hipStream_t s = as_stream(stream);
+  ovl_gauge *g = new (std::nothrow) ovl_gauge();
+  if (!g) return fail(OVL_ENOMEM, "host allocation failed");
+  g->g = geo;
+  g->store_dt = store_dt;
+  g->links = nullptr;
+  g->flags = nullptr;
+  hipError_t e = hipGetDevice(&g->device);
+  const int64_t n = (int64_t)36 * geo.V;
+  if (e == hipSuccess) e = hipMalloc(&g->links, n * elem_bytes(store_dt));
+  if (e == hipSuccess) e = hipMalloc((void **)&g->flags, 256);
+  if (e == hipSuccess) e = hipMemsetAsync(g->flags, 0, 256, s);
+  if (e == hipSuccess) {
+    const int threads = 256;
+    const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+    if (in_dt == OVL_F64) {
+      const double2 *src = (const double2 *)U_dev;
+      if (store_dt == OVL_F64) convert_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, n);
+      else if (store_dt == OVL_F32) convert_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, n);
+      else convert_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, n);
+    } else {
+      const float2 *src = (const float2 *)U_dev;
+      if (store_dt == OVL_F64) convert_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, n);
+      else if (store_dt == OVL_F32) convert_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, n);
+      else convert_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, n);
+    }
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    if (g->links) (void)hipFree(g->links);
+    if (g->flags) (void)hipFree(g->flags);
+    delete g;
+    return fail(e == hipErrorOutOfMemory ? OVL_ENOMEM : OVL_EHIP, "gauge create: %s",
+                hipGetErrorString(e));
+  }
+  *out = g;
+  return OVL_OK;
+}
+
+int ovl_gauge_destroy(ovl_gauge *g) {
+  g_err[0] = 0;
+  if (!g) return OVL_OK;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(g->links);
+  (void)hipFree(g->flags);
+  delete g;
+  return OVL_OK;
+}
+
+int ovl_gauge_info(const ovl_gauge *g, int32_t dims_out[4], int *store_dt) {
+  if (!g || !dims_out || !store_dt) return fail(OVL_EINVAL, "NULL argument");
+  for (int i = 0; i < 4; ++i) dims_out[i] = g->g.L[i];
+  *store_dt = g->store_dt;
+  return OVL_OK;
+}
+
+int ovl_poly_create(ovl_poly **out, const double *alpha, int n_alpha, double lmax, double m_W) {
+  g_err[0] = 0;
+  if (!out || !alpha) return fail(OVL_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n_alpha < 2 || n_alpha > 100001)
+    return fail(OVL_EINVAL, "n_alpha = %d out of range [2, 100001]", n_alpha);
+  if (!std::isfinite(lmax) || !std::isfinite(m_W)) return fail(OVL_ENONFINITE, "lmax or m_W not finite");
+  if (!(lmax > 0.0)) return fail(OVL_EINVAL, "lmax must be positive");
+  for (int i = 0; i < n_alpha; ++i)
+    if (!std::isfinite(alpha[i])) return fail(OVL_ENONFINITE, "alpha[%d] is not finite", i);
+  ovl_poly *p = new (std::nothrow) ovl_poly();
+  if (!p) return fail(OVL_ENOMEM, "host allocation failed");
+  p->alpha.assign(alpha, alpha + n_alpha);
+  p->lmax = lmax;
+  p->m_W = m_W;
+  // sup |p| on [-1, 1] sampled finely, plus the sum of |alpha| beyond as a hard cap
+  double sup = 0.0, l1 = 0.0;
+  for (double a : p->alpha) l1 += std::fabs(a);
+  const int ns = std::max(4096, 16 * n_alpha);
+  for (int j = 0; j <= ns; ++j) {
+    const double x = std::cos(M_PI * j / ns);
+    sup = std::max(sup, std::fabs(cheb_eval(p->alpha, x)));
+  }
+  p->bound = std::min(l1, sup * 1.05 + 1e-3);
+  p->serial = g_poly_serial.fetch_add(1);
+  *out = p;
+  return OVL_OK;
+}
+
+int ovl_poly_destroy(ovl_poly *p) {
+  delete p;
+  return OVL_OK;
+}
+
+int ovl_poly_eval(const ovl_poly *p, double lambda, double *value_out) {
+  if (!p || !value_out) return fail(OVL_EINVAL, "NULL argument");
+  *value_out = cheb_eval(p->alpha, lambda / p->lmax);
+  return OVL_OK;
+}
+
+int ovl_cheb_sign_coeffs(int degree, double eps, double *alpha_host, int *n_alpha_out) {
+  g_err[0] = 0;
+  if (!alpha_host || !n_alpha_out) return fail(OVL_EINVAL, "NULL argument");
+  if (degree < 1 || degree > 100000) return fail(OVL_EINVAL, "degree %d out of range", degree);
+  if (!(eps > 0.0 && eps < 1.0)) return fail(OVL_EINVAL, "eps must lie in (0, 1)");
+  std::vector<double> a;
+  if (!cheb_sign_coeffs(degree, eps, a)) return fail(OVL_EINVAL, "coefficient rule failed");
+  std::memcpy(alpha_host, a.data(), sizeof(double) * a.size());
+  *n_alpha_out = (int)a.size();
+  return OVL_OK;
+}
+
+int ovl_defl_create(ovl_defl **out, const int32_t dims[4], const void *phi_dev, int in_dt,
+                    const double *lambda, int n_ev, int store_dt, void *stream) {
+  g_err[0] = 0;
+  if (!out || !phi_dev || !lambda) return fail(OVL_EINVAL, "NULL argument");
+  *out = nullptr;
+  Geom geo;
+  int rc = check_dims(dims, geo);
+  if (rc) return rc;
+  if (n_ev < 1 || (int64_t)n_ev > (int64_t)12 * geo.V)
+    return fail(OVL_EINVAL, "n_ev = %d out of range [1, 12 V]", n_ev);
+  if (in_dt != OVL_F64 && in_dt != OVL_F32) return fail(OVL_EDTYPE, "eigenvector dtype %d", in_dt);
+  if (store_dt != OVL_F64 && store_dt != OVL_F32) return fail(OVL_EDTYPE, "basis storage %d", store_dt);
+  for (int i = 0; i < n_ev; ++i)
+    if (!std::isfinite(lambda[i])) return fail(OVL_ENONFINITE, "lambda[%d] is not finite", i);
+  if (!fits_u32(12ull * geo.V, OVL_F64))
+    return fail(OVL_EDIMS, "one eigenvector of %d sites exceeds 4 GiB in FP64", geo.V);
+  hipStream_t s = as_stream(stream);
+  ovl_defl *d = new (std::nothrow) ovl_defl();
+  if (!d) return fail(OVL_ENOMEM, "host allocation failed");
+  d->g = geo;
+  d->n_ev = n_ev;
+  d->store_dt = store_dt;
+  d->phi64 = nullptr;
+  d->phi_store = nullptr;
+  d->w_dev = nullptr;
+  d->lambda.assign(lambda, lambda + n_ev);
+  d->w_host.assign(n_ev, 0.0);
+  d->w_serial = 0;
+  const int V = geo.V;
+  const int64_t nv = (int64_t)12 * V;  // complex entries per vector
+  const int64_t n = nv * n_ev;
+  auto cleanup = [&](int code) {
+    if (d->phi_store && d->phi_store != d->phi64) (void)hipFree(d->phi_store);
+    if (d->phi64) (void)hipFree(d->phi64);
+    if (d->w_dev) (void)hipFree(d->w_dev);
+    delete d;
+    return code;
+  };
+  hipError_t e = hipMalloc((void **)&d->phi64, n * sizeof(double2));
+  if (e == hipSuccess) e = hipMalloc((void **)&d->w_dev, sizeof(double) * n_ev);
+  if (e != hipSuccess)
+    return cleanup(fail(e == hipErrorOutOfMemory ? OVL_ENOMEM : OVL_EHIP, "defl alloc: %s",
+                        hipGetErrorString(e)));
+  {
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (in_dt == OVL_F64)
+      convert_kernel<<<blocks, 256, 0, s>>>((const double2 *)phi_dev, d->phi64, n);
+    else
+      convert_kernel<<<blocks, 256, 0, s>>>((const float2 *)phi_dev, d->phi64, n);
+  }
+  // CGS2 in FP64: for each vector, two passes of v -= Q (Q^+ v) against the previous ones,
+  // then v /= ||v||.  norms[2j] = ||v||^2 before, norms[2j+1] = after the two passes.
+  const int nblk = project_blocks(V);
+  Scratch sc;
+  const size_t part_bytes = sizeof(double2) * (size_t)nblk * std::max(n_ev, 1);
+  rc = scratch_alloc(sc, part_bytes + sizeof(double2) * (n_ev + 1) + sizeof(double) * 2 * n_ev + 1024, s);
+  if (rc) return cleanup(rc);
+  double2 *partial = (double2 *)sc.p;
+  double2 *cbuf = (double2 *)((char *)sc.p + part_bytes);
+  double *norms = (double *)((char *)cbuf + sizeof(double2) * (n_ev + 1));
+  const unsigned vblocks = (unsigned)((nv + 255) / 256);
+  for (int j = 0; j < n_ev && rc == OVL_OK; ++j) {
+    double2 *v = d->phi64 + (int64_t)j * nv;
+    rc = project<double2>(v, 1, v, 0, 1, V, partial, nblk, cbuf, s);
+    if (rc) break;
+    record_kernel<<<1, 64, 0, s>>>(cbuf, norms, 2 * j);
+    for (int pass = 0; pass < 2 && j > 0 && rc == OVL_OK; ++pass) {
+      rc = project<double2>(d->phi64, j, v, 0, 1, V, partial, nblk, cbuf, s);
+      if (rc) break;
+      correct_kernel<double, double2><<<dim3(grid_blocks(V), 1), kBlock, 0, s>>>(
+          v, d->phi64, j, cbuf, nullptr, -1.0, V);
+    }
+    if (rc) break;
+    rc = project<double2>(v, 1, v, 0, 1, V, partial, nblk, cbuf, s);
+    if (rc) break;
+    normalize_kernel<<<vblocks, 256, 0, s>>>(v, cbuf, nv, norms, 2 * j + 1);
+  }
+  if (rc) return cleanup(rc);
+  std::vector<double> hn(2 * n_ev);
+  e = hipMemcpyAsync(hn.data(), norms, sizeof(double) * 2 * n_ev, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(fail(OVL_EHIP, "defl create: %s", hipGetErrorString(e)));
+  for (int j = 0; j < n_ev; ++j) {
+    if (!std::isfinite(hn[2 * j]) || !std::isfinite(hn[2 * j + 1]))
+      return cleanup(fail(OVL_ENONFINITE, "eigenvector %d holds non-finite values", j));
+    if (!(hn[2 * j] > 0.0) || hn[2 * j + 1] < 1e-20 * hn[2 * j])
+      return cleanup(fail(OVL_EDEFL, "eigenvector %d is numerically dependent on the previous ones", j));
+  }
+  if (store_dt == OVL_F64) {
+    d->phi_store = d->phi64;
+  } else {
+    e = hipMalloc(&d->phi_store, n * sizeof(float2));
+    if (e == hipSuccess) {
+      convert_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((const double2 *)d->phi64,
+                                                                 (float2 *)d->phi_store, n);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) return cleanup(fail(OVL_EHIP, "defl storage copy: %s", hipGetErrorString(e)));
+  }
+  *out = d;
+  return OVL_OK;
+}
+
+int ovl_defl_destroy(ovl_defl *d) {
+  if (!d) return OVL_OK;
+  (void)hipDeviceSynchronize();
+  if (d->phi_store && d->phi_store != d->phi64) (void)hipFree(d->phi_store);
+  (void)hipFree(d->phi64);
+  (void)hipFree(d->w_dev);
+  delete d;
+  return OVL_OK;
+}
+
+int ovl_defl_basis(const ovl_defl *d, void *phi_out, void *stream) {
+  if (!d || !phi_out) return fail(OVL_EINVAL, "NULL argument");
+  HIP_TRY(hipMemcpyAsync(phi_out, d->phi64, sizeof(double2) * (size_t)12 * d->g.V * d->n_ev,
+                         hipMemcpyDeviceToDevice, as_stream(stream)));
+  return OVL_OK;
+}
+
+int ovl_wilson_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, int spin_dt,
+                     double m_W, int dagger, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if (!std::isfinite(m_W)) return fail(OVL_ENONFINITE, "m_W is not finite");
+  StepParams p = base_params(g);
+  p.v = in;
+  p.v_g5 = dagger ? 1 : 0;
+  p.y_g5 = dagger ? 1 : 0;
+  p.kd = 4.0 - m_W;
+  p.kh = -0.5;
+  p.out = out;
+  p.mode = MODE_STEP;
+  return dispatch_step(prec, p, nrhs, as_stream(stream));
+}
+
+int ovl_kernel_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, int spin_dt,
+                     double m_W, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if (!std::isfinite(m_W)) return fail(OVL_ENONFINITE, "m_W is not finite");
+  StepParams p = base_params(g);
+  p.v = in;
+  p.y_g5 = 1;
+  p.kd = 4.0 - m_W;
+  p.kh = -0.5;
+  p.out = out;
+  p.mode = MODE_STEP;
+  return dispatch_step(prec, p, nrhs, as_stream(stream));
+}
+
+int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, void *out,
+                   const void *in, int nrhs, int spin_dt, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if ((rc = check_poly(p)) || (rc = check_defl(g, d, prec))) return rc;
+  return run_sign(g, p, const_cast<ovl_defl *>(d), MODE_SIGN, 0.0, 0, out, in, nrhs, spin_dt, prec,
+                  as_stream(stream));
+}
+
+int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                      int dagger, void *out, const void *in, int nrhs, int spin_dt, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if ((rc = check_poly(p)) || (rc = check_defl(g, d, prec))) return rc;
+  if (!std::isfinite(mu)) return fail(OVL_ENONFINITE, "mu is not finite");
+  // D^+ psi = 1/2 ((1 + mu) psi + (1 - mu) sign(K) gamma5 psi)
+  return run_sign(g, p, const_cast<ovl_defl *>(d), dagger ? MODE_OVERLAP_DAG : MODE_OVERLAP, mu,
+                  dagger ? 1 : 0, out, in, nrhs, spin_dt, prec, as_stream(stream));
+}
+
+int ovl_defl_project(const ovl_defl *d, double *c_dev, const void *in, int nrhs, int spin_dt,
+                     void *stream) {
+  g_err[0] = 0;
+  if (!d || !c_dev || !in) return fail(OVL_EINVAL, "NULL argument");
+  if (nrhs < 1 || nrhs > 65535) return fail(OVL_EINVAL, "nrhs = %d out of range", nrhs);
+  const int want = spin_dt;
+  if (want != d->store_dt) return fail(OVL_EDTYPE, "spinor dtype %d differs from basis storage %d", spin_dt, d->store_dt);
+  hipStream_t s = as_stream(stream);
+  const int V = d->g.V;
+  const int nblk = project_blocks(V);
+  Scratch sc;
+  int rc = scratch_alloc(sc, sizeof(double2) * (size_t)nblk * nrhs * d->n_ev, s);
+  if (rc) return rc;
+  if (spin_dt == OVL_F64)
+    return project((const double2 *)d->phi_store, d->n_ev, (const double2 *)in, 0, nrhs, V,
+                   (double2 *)sc.p, nblk, (double2 *)c_dev, s);
+  return project((const float2 *)d->phi_store, d->n_ev, (const float2 *)in, 0, nrhs, V,
+                 (double2 *)sc.p, nblk, (double2 *)c_dev, s);
+}
+
+int ovl_defl_correct(const ovl_defl *d, void *inout, const double *c_dev, const double *w_host,
+                     int nrhs, int spin_dt, void *stream) {
+  g_err[0] = 0;
+  if (!d || !c_dev || !inout || !w_host) return fail(OVL_EINVAL, "NULL argument");
+  if (nrhs < 1 || nrhs > 65535) return fail(OVL_EINVAL, "nrhs = %d out of range", nrhs);
+  if (spin_dt != d->store_dt) return fail(OVL_EDTYPE, "spinor dtype %d differs from basis storage %d", spin_dt, d->store_dt);
+  for (int i = 0; i < d->n_ev; ++i)
+    if (!std::isfinite(w_host[i])) return fail(OVL_ENONFINITE, "w[%d] is not finite", i);
+  hipStream_t s = as_stream(stream);
+  Scratch sc;
+  int rc = scratch_alloc(sc, sizeof(double) * d->n_ev, s);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(sc.p, w_host, sizeof(double) * d->n_ev, hipMemcpyHostToDevice, s));
+  const int V = d->g.V;
+  dim3 grid(grid_blocks(V), nrhs);
+  if (spin_dt == OVL_F64)
+    correct_kernel<double, double2><<<grid, kBlock, 0, s>>>((double2 *)inout, (const double2 *)d->phi_store,
+                                                           d->n_ev, (const double2 *)c_dev,
+                                                           (const double *)sc.p, 1.0, V);
+  else
+    correct_kernel<float, float2><<<grid, kBlock, 0, s>>>((float2 *)inout, (const float2 *)d->phi_store,
+                                                         d->n_ev, (const double2 *)c_dev,
+                                                         (const double *)sc.p, 1.0, V);
+  HIP_TRY(hipGetLastError());
+  // the staging copy must complete before the caller may reuse w_host
+  HIP_TRY(hipStreamSynchronize(s));
+  return OVL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// link derivatives
+namespace {
+
+int launch_vjp(Prec prec, const ovl_gauge *g, void *G, const void *a, int a_g5, const void *t,
+               double coef, int accumulate, hipStream_t s) {
+  const dim3 grid(grid_blocks(g->g.V));
+  switch (prec) {
+    case P_F64:
+      link_vjp_kernel<double, double2, double2><<<grid, kBlock, 0, s>>>(
+          (double2 *)G, (const double2 *)a, (const double2 *)t, g->g, coef, a_g5, accumulate, 1);
+      break;
+    case P_F32:
+    case P_F32_BF16:
+      link_vjp_kernel<float, float2, float2><<<grid, kBlock, 0, s>>>(
+          (float2 *)G, (const float2 *)a, (const float2 *)t, g->g, coef, a_g5, accumulate, 1);
+      break;
+    default:
+      return fail(OVL_EDTYPE, "bad precision");
+  }
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ovl_wilson_link_vjp(const ovl_gauge *g, void *G, const void *chi, const void *psi, int spin_dt,
+                        int accumulate, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  if (!G) return fail(OVL_EINVAL, "G is NULL");
+  int rc = check_spinor_call(g, G, chi, 1, spin_dt, prec);
+  if (rc == OVL_EALIAS) return fail(OVL_EALIAS, "G overlaps chi");
+  if (rc) return rc;
+  if (!psi) return fail(OVL_EINVAL, "psi is NULL");
+  if (!fits_u32(36ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "G exceeds 4 GiB");
+  return launch_vjp(prec, g, G, chi, 0, psi, 1.0, accumulate, as_stream(stream));
+}
+
+// dL = Re[<b_1, dX t_0> + 2 sum_{m=1}^{N-1} <b_{m+1}, dX t_m>] with b the Clenshaw vectors of chi
+// and t_m = T_m(X) psi; dX = gamma5 dD_W / lmax.  Forward sweep keeps (t_{js}, t_{js+1}) for every
+// segment j of length s; the backward sweep walks the segments from the top, regenerates the
+// segment's t_m, and advances b_k = alpha_k chi + 2 X b_{k+1} - b_{k+2} downwards.
+int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *chi,
+                   const void *psi, int ckpt_stride, int spin_dt, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  if (!G || !chi || !psi) return fail(OVL_EINVAL, "NULL argument");
+  int rc = check_spinor_call(g, G, psi, 1, spin_dt, prec);
+  if (rc == OVL_EALIAS) return fail(OVL_EALIAS, "G overlaps psi");
+  if (rc) return rc;
+  if ((rc = check_poly(p))) return rc;
+  if (!fits_u32(36ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "G exceeds 4 GiB");
+  if (ckpt_stride < 0) return fail(OVL_EINVAL, "ckpt_stride must be >= 0");
+  const int N = (int)p->alpha.size() - 1;
+  int S = ckpt_stride > 0 ? ckpt_stride : (int)std::ceil(std::sqrt((double)N));
+  S = std::max(1, std::min(S, N));
+  const int nseg = (N + S - 1) / S;  // segments cover m = 0 .. N-1
+  // checkpoint slots: t_{jS} and t_{jS+1} of every segment j (distinct m only, m <= N-1)
+  std::vector<int> slot_of(N + 1, -1);
+  int nslot = 0;
+  for (int j = 0; j < nseg; ++j)
+    for (int m = j * S; m <= j * S + 1 && m <= N - 1; ++m)
+      if (slot_of[m] < 0) slot_of[m] = nslot++;
+  hipStream_t s = as_stream(stream);
+  const size_t vec = (size_t)12 * g->g.V * elem_bytes(spin_dt);
+  const size_t vecp = (vec + 255) / 256 * 256;
+  // checkpoints, segment buffer S (+1 spare), two b vectors
+  const size_t nvec = (size_t)nslot + (S + 1) + 2;
+  Scratch sc;
+  rc = scratch_alloc(sc, nvec * vecp, s);
+  if (rc) return rc;
+  char *base = (char *)sc.p;
+  auto ck = [&](int m) -> void * { return base + (size_t)slot_of[m] * vecp; };
+  auto seg = [&](int i) -> void * { return base + ((size_t)nslot + i) * vecp; };
+  void *bA = base + ((size_t)nslot + S + 1) * vecp;
+  void *bB = base + ((size_t)nslot + S + 2) * vecp;
+  const double kdiag = 4.0 - p->m_W;
+  const double *al = p->alpha.data();
+  // X applied: out = sx * X v + a * src + t * w
+  auto xstep = [&](void *out, const void *v, double sx, const void *src, double a, const void *w,
+                   double t) -> int {
+    StepParams sp = base_params(g);
+    sp.v = v;
+    sp.y_g5 = 1;
+    sp.kd = sx * kdiag / p->lmax;
+    sp.kh = -0.5 * sx / p->lmax;
+    sp.src = src;
+    sp.a = src ? a : 0.0;
+    sp.w = w;
+    sp.t = t;
+    sp.out = out;
+    sp.mode = MODE_STEP;
+    return dispatch_step(prec, sp, 1, s);
+  };
+  // forward sweep: t_0 = psi, t_1 = X psi, t_{m+1} = 2 X t_m - t_{m-1}, keeping the checkpoint
+  // vectors; the others rotate through seg(0), seg(1) (never the buffer read as stencil input)
+  HIP_TRY(hipMemcpyAsync(ck(0), psi, vec, hipMemcpyDeviceToDevice, s));
+  if (N - 1 >= 1) {
+    void *t1 = slot_of[1] >= 0 ? ck(1) : seg(0);
+    if ((rc = xstep(t1, psi, 1.0, nullptr, 0.0, nullptr, 0.0))) return rc;
+    const void *tm1 = ck(0);
+    const void *tm = t1;
+    int which = (t1 == seg(0)) ? 1 : 0;
+    for (int m = 1; m + 1 <= N - 1; ++m) {  // produce t_{m+1} up to t_{N-1}
+      void *dst;
+      if (slot_of[m + 1] >= 0) {
+        dst = ck(m + 1);
+      } else {
+        dst = seg(which);
+        which ^= 1;
+      }
+      if ((rc = xstep(dst, tm, 2.0, nullptr, 0.0, tm1, -1.0))) return rc;
+      tm1 = tm;
+      tm = dst;
+    }
+  }
+  // backward sweep, segments from the top
+  HIP_TRY(hipMemsetAsync(G, 0, (size_t)36 * g->g.V * elem_bytes(spin_dt), s));
+  // b_{N+1} = 0, b_N = alpha_N chi: keep b_{k+1} in cur, b_{k+2} in prev
+  void *cur = bA, *prev = bB;
+  // b_N = alpha_N chi  (X applied to chi with factor 0 is avoided: use a scaled copy via a step
+  // with sx = 0 would still read neighbours; build it as a * src with a zero stencil input)
+  if ((rc = xstep(cur, chi, 0.0, chi, al[N], nullptr, 0.0))) return rc;
+  HIP_TRY(hipMemsetAsync(prev, 0, vec, s));
+  int k = N;  // cur holds b_k
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int m0 = j * S;
+    const int m1 = std::min(N - 1, m0 + S - 1);
+    // regenerate t_{m0} .. t_{m1} into seg(0..)
+    HIP_TRY(hipMemcpyAsync(seg(0), ck(m0), vec, hipMemcpyDeviceToDevice, s));
+    if (m1 >= m0 + 1) HIP_TRY(hipMemcpyAsync(seg(1), ck(m0 + 1), vec, hipMemcpyDeviceToDevice, s));
+    for (int m = m0 + 2; m <= m1; ++m)
+      if ((rc = xstep(seg(m - m0), seg(m - m0 - 1), 2.0, nullptr, 0.0, seg(m - m0 - 2), -1.0))) return rc;
+    for (int m = m1; m >= m0; --m) {
+      // need b_{m+1}: cur holds b_k with k = m + 1 (invariant)
+      const double coef = (m == 0 ? 1.0 : 2.0) / p->lmax;
+      if ((rc = launch_vjp(prec, g, G, cur, 1, seg(m - m0), coef, 1, s))) return rc;
+      if (m >= 1) {
+        // b_m = alpha_m chi + 2 X b_{m+1} - b_{m+2}  -> written over prev (holds b_{m+2})
+        if ((rc = xstep(prev, cur, 2.0, chi, al[m], prev, -1.0))) return rc;
+        std::swap(cur, prev);
+        --k;
+      }
+    }
+  }
+  (void)k;
+  return OVL_OK;
+}
+
+int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear) {
+  if (!g || !flags) return fail(OVL_EINVAL, "NULL argument");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(flags, g->flags, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  if (clear) HIP_TRY(hipMemset(g->flags, 0, sizeof(uint32_t)));
+  return OVL_OK;
+}
+
+int ovl_timing_enable(int on) {
+  g_timing.store(on ? 1 : 0);
+  return OVL_OK;
+}
+
+int ovl_timing_read(double *total_ms, int64_t *launches) {
+  if (!total_ms || !launches) return fail(OVL_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  double tot = 0.0;
+  for (auto &pr : g_timing_events) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+    g_event_pool.push_back(pr.first);
+    g_event_pool.push_back(pr.second);
+  }
+  *launches = (int64_t)g_timing_events.size();
+  *total_ms = tot;
+  g_timing_events.clear();
+  return OVL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+"""Host-side checks of libovl.so that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before any HIP call, and its coefficient rule agrees with
+the oracle's (Sec. 2, eq. 3 leaves the coefficients open; both sides implement the same rule
+independently)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import chebyshev as och
+from paper_1510_06897_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libovl.so is not built (python -m paper_1510_06897_amd.build)")
+    return _lib.load()
+
+
+def header_symbols():
+    text = open(os.path.join(ROOT, "include", "ovl.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(ovl_\w+)\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_symbols()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.ovl_version()
+
+
+@pytest.mark.parametrize("deg,eps", [(64, 0.077), (200, 0.0772), (400, 0.03), (299, 0.05), (1, 0.5)])
+def test_coefficients_match_oracle_rule(lib, deg, eps):
+    buf = (ctypes.c_double * (deg + 1))()
+    n = ctypes.c_int()
+    assert lib.ovl_cheb_sign_coeffs(deg, eps, buf, ctypes.byref(n)) == 0
+    ours = np.array(buf[: n.value])
+    ref = och.coeffs_sign_interp(deg, eps)
+    assert len(ours) == len(ref)
+    # both sides sum O(N) cosine terms of values up to 1/eps in different orders
+    assert np.abs(ours - ref).max() < 2e-15 * (len(ref) + 1) / eps
+    assert np.all(ours[0::2] == 0.0)
+
+
+def test_coefficients_reject_bad_args(lib):
+    buf = (ctypes.c_double * 8)()
+    n = ctypes.c_int()
+    assert lib.ovl_cheb_sign_coeffs(0, 0.1, buf, ctypes.byref(n)) == -1
+    assert lib.ovl_cheb_sign_coeffs(7, 1.5, buf, ctypes.byref(n)) == -1
+    assert lib.ovl_cheb_sign_coeffs(7, 0.1, None, ctypes.byref(n)) == -1
+    assert b"eps" in lib.ovl_last_error() or b"NULL" in lib.ovl_last_error()
+
+
+def test_poly_handle_and_eval(lib):
+    alpha = och.coeffs_sign_interp(31, 0.1)
+    h = ctypes.c_void_p()
+    a = alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.ovl_poly_create(ctypes.byref(h), a, len(alpha), 6.5, 1.5) == 0
+    v = ctypes.c_double()
+    for lam in (-3.0, 0.4, 2.2, 6.4):
+        assert lib.ovl_poly_eval(h, lam, ctypes.byref(v)) == 0
+        assert abs(v.value - och.cheb_eval_scalar(alpha, lam / 6.5)) < 1e-14
+    assert lib.ovl_poly_destroy(h) == 0
+
+
+def test_poly_validation(lib):
+    h = ctypes.c_void_p()
+    good = np.array([0.0, 1.0, 0.0, 0.2])
+    bad = np.array([0.0, np.nan, 0.0])
+    p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    assert lib.ovl_poly_create(ctypes.byref(h), p(bad), 3, 6.5, 1.5) == -7        # ENONFINITE
+    assert lib.ovl_poly_create(ctypes.byref(h), p(good), 1, 6.5, 1.5) == -1        # too short
+    assert lib.ovl_poly_create(ctypes.byref(h), p(good), 4, -1.0, 1.5) == -1       # lmax <= 0
+    assert lib.ovl_poly_create(ctypes.byref(h), p(good), 4, float("inf"), 1.5) == -7
+    assert lib.ovl_poly_create(None, p(good), 4, 6.5, 1.5) == -1
+
+
+def test_gauge_create_validation_before_hip(lib):
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    dims = (ctypes.c_int32 * 4)(4, 4, 0, 4)
+    assert lib.ovl_gauge_create(ctypes.byref(h), dims, dummy, 0, 0, None) == -2    # EDIMS
+    dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    assert lib.ovl_gauge_create(ctypes.byref(h), dims, dummy, 0, 7, None) == -3    # EDTYPE
+    assert lib.ovl_gauge_create(ctypes.byref(h), dims, dummy, 2, 0, None) == -3    # BF16 input
+    assert lib.ovl_gauge_create(ctypes.byref(h), dims, None, 0, 0, None) == -1
+    big = (ctypes.c_int32 * 4)(2048, 2048, 1024, 2)
+    assert lib.ovl_gauge_create(ctypes.byref(h), big, dummy, 0, 0, None) == -2      # V > 2^31
+
+
+def test_operator_validation_before_hip(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.ovl_wilson_apply(None, dummy, dummy, 1, 0, 0.0, 0, None) == -1
+    assert lib.ovl_kernel_apply(None, dummy, dummy, 1, 0, 1.5, None) == -1
+    assert lib.ovl_sign_apply(None, None, None, dummy, dummy, 1, 0, None) == -1
+    assert lib.ovl_overlap_apply(None, None, None, 0.1, 0, dummy, dummy, 1, 0, None) == -1
+    assert lib.ovl_defl_project(None, None, dummy, 1, 0, None) == -1
+    assert lib.ovl_defl_correct(None, dummy, None, None, 1, 0, None) == -1
+    assert lib.ovl_sign_force(None, None, None, dummy, dummy, 0, 0, None) == -1
+    assert lib.ovl_status_flags(None, None, 0) == -1
+    h = ctypes.c_void_p()
+    lam = (ctypes.c_double * 1)(0.5)
+    dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    assert lib.ovl_defl_create(ctypes.byref(h), dims, dummy, 0, lam, 0, 0, None) == -1
+    lam_bad = (ctypes.c_double * 1)(float("nan"))
+    assert lib.ovl_defl_create(ctypes.byref(h), dims, dummy, 0, lam_bad, 1, 0, None) == -7
+    assert lib.ovl_defl_create(ctypes.byref(h), dims, dummy, 2, lam, 1, 0, None) == -3
+
+
+def test_destroy_null_is_ok(lib):
+    assert lib.ovl_gauge_destroy(None) == 0
+    assert lib.ovl_poly_destroy(None) == 0
+    assert lib.ovl_defl_destroy(None) == 0
+
+
+def test_python_binding_raises_with_status(lib):
+    from paper_1510_06897_amd import cheb_sign_coeffs, OvlError
+    with pytest.raises(OvlError) as e:
+        cheb_sign_coeffs(10, 2.0)
+    assert e.value.status == "OVL_EINVAL"

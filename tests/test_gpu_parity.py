@@ -1,0 +1,353 @@
+"""GPU parity: every C-ABI operator against the FP64 oracle on the same seeded inputs.
+
+Operators of Cundy & Lee, Sec. 2: D_W (eq. 2), K, the deflated Chebyshev sign function (eq. 3),
+the overlap operator (eq. 1), deflation projection/correction and the link derivatives.
+Tolerances: 1e-12 relative for the FP64 path (the GPU evaluates the polynomial by Clenshaw's
+recurrence, the oracle by the forward recurrence, so they agree only up to rounding that grows
+with the degree), 1e-6 for the FP32 path.  Mixed-precision results are compared with the oracle
+run on the same rounded inputs (link rounding is an input, not kernel error).
+"""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import chebyshev as och
+from oracle import deflation as odefl
+from oracle import force as oforce
+from oracle import overlap as oov
+from oracle import wilson as ow
+from tests.conftest import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LMAX = 6.5
+
+
+@pytest.fixture(scope="module")
+def ovl():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1510_06897_amd as m
+    m.load()
+    return m
+
+
+def dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to("cpu", torch.complex128).numpy()
+
+
+def max_rel(a, b):
+    """max |a - b| over max |b| (element-wise bound) and the norm ratio."""
+    return max(float(np.abs(a - b).max() / np.abs(b).max()), rel_err(a, b))
+
+
+DIMS_SMALL = [(4, 4, 4, 4), (2, 3, 4, 5), (1, 3, 2, 2), (5, 2, 3, 7)]
+
+
+@pytest.mark.parametrize("dims", DIMS_SMALL + [(8, 8, 8, 16)])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_wilson_kernel_fp64(ovl, dims, nrhs):
+    u = latgen.random_su3_field(dims, 10100, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20100, nrhs=nrhs)
+    g = ovl.GaugeField(dev(u), "f64")
+    d_psi = dev(psi)
+    got_dw = host(ovl.wilson_apply(g, d_psi, m_w=0.0))
+    got_dag = host(ovl.wilson_apply(g, d_psi, m_w=1.5, dagger=True))
+    got_k = host(ovl.kernel_apply(g, d_psi, m_w=1.5))
+    for r in range(nrhs):
+        assert max_rel(got_dw[r], ow.dw(u, psi[r])) < 1e-14
+        ref_dag = ow.gamma5(ow.dw_minus_mass(u, ow.gamma5(psi[r]), 1.5))
+        assert max_rel(got_dag[r], ref_dag) < 1e-14
+        assert max_rel(got_k[r], ow.kop(u, psi[r])) < 1e-14
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 2, 4), (8, 8, 8, 16)])
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_kernel_mixed(ovl, dims, store):
+    u = latgen.smeared_field(dims, 10200, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20200, nrhs=2)
+    u_r = latgen.round_to_f32(u) if store == "f32" else latgen.round_to_bf16(u)
+    psi_r = latgen.round_to_f32(psi)
+    g = ovl.GaugeField(dev(u), store)
+    got = host(ovl.kernel_apply(g, dev(psi, torch.complex64)))
+    for r in range(2):
+        ref_same = ow.kop(u_r, psi_r[r])
+        assert max_rel(got[r], ref_same) < 1e-6                  # kernel arithmetic
+        end_to_end = rel_err(got[r], ow.kop(u, psi[r]))
+        assert end_to_end < (1e-6 if store == "f32" else 1e-2)   # includes link rounding
+
+
+def c1_inputs():
+    dims = (4, 4, 4, 4)
+    u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 1))
+    psi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 1))
+    from oracle.eigen import low_modes
+    lam, _, _ = low_modes(u, 1, LMAX, filter_degree=16)
+    eps = abs(lam[0]) / LMAX
+    alpha = och.coeffs_sign_interp(64, eps)
+    return dims, u, psi, alpha
+
+
+def test_sign_overlap_c1_fp64(ovl):
+    dims, u, psi, alpha = c1_inputs()
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d_psi = dev(psi)
+    s = host(ovl.sign_apply(g, p, d_psi))
+    ref_s = och.sign_apply(u, psi, alpha, LMAX)
+    assert max_rel(s, ref_s) < 1e-12
+    for dag in (False, True):
+        o = host(ovl.overlap_apply(g, p, d_psi, 0.1, dagger=dag))
+        ref = (oov.overlap_dagger_apply if dag else oov.overlap_apply)(u, psi, 0.1, alpha, LMAX)
+        assert max_rel(o, ref) < 1e-12
+    assert g.flags() == 0
+
+
+@pytest.mark.parametrize("n_alpha", [2, 3, 4, 5])
+def test_sign_low_degrees(ovl, n_alpha):
+    """Degree 1..4, including even top index: exercises the folded first Clenshaw steps."""
+    dims = (3, 2, 4, 2)
+    u = latgen.random_su3_field(dims, 7)
+    psi = latgen.gaussian_spinor(dims, 8, nrhs=2)
+    alpha = np.random.default_rng(n_alpha).standard_normal(n_alpha) * 0.5
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    s = host(ovl.sign_apply(g, p, dev(psi)))
+    for r in range(2):
+        assert max_rel(s[r], och.poly_apply(u, psi[r], alpha, LMAX)) < 1e-13
+
+
+def random_basis(dims, n_ev, seed):
+    raw = latgen.gaussian_spinor(dims, seed, nrhs=n_ev)
+    phi = odefl.cgs2(raw)
+    lam = np.linspace(-0.52, 0.52, n_ev) + 0.003
+    return phi, lam
+
+
+@pytest.fixture(scope="module")
+def c2():
+    dims = (8, 8, 8, 16)
+    u = latgen.smeared_field(dims, latgen.seed_for("gauge", 2))
+    psi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 2))
+    phi, lam = random_basis(dims, 12, 777)
+    alpha = och.coeffs_sign_interp(200, 0.077)
+    ref_s = och.sign_apply(u, psi, alpha, LMAX, phi, lam)
+    return dims, u, psi, phi, lam, alpha, ref_s
+
+
+def test_sign_c2_deflated_fp64(ovl, c2):
+    dims, u, psi, phi, lam, alpha, ref_s = c2
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f64")
+    d_psi = dev(psi)
+    s = host(ovl.sign_apply(g, p, d_psi, defl=d))
+    assert max_rel(s, ref_s) < 1e-12
+    for mu in (0.01, 0.05):
+        o = host(ovl.overlap_apply(g, p, d_psi, mu, defl=d))
+        ref = 0.5 * ((1 + mu) * psi + (1 - mu) * ow.gamma5(ref_s))
+        assert max_rel(o, ref) < 1e-12
+    assert g.flags() == 0
+
+
+def test_sign_c2_deflated_fp32(ovl, c2):
+    dims, u, psi, phi, lam, alpha, ref_s = c2
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    s = host(ovl.sign_apply(g, p, dev(psi, torch.complex64), defl=d))
+    err = rel_err(s, ref_s)
+    assert err < 1e-6, err
+    assert g.flags() == 0
+
+
+def test_overlap_dagger_deflated_fp64(ovl):
+    dims = (4, 4, 2, 4)
+    u = latgen.smeared_field(dims, 31)
+    psi = latgen.gaussian_spinor(dims, 32)
+    phi, lam = random_basis(dims, 5, 33)
+    alpha = och.coeffs_sign_interp(41, 0.08)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f64")
+    o = host(ovl.overlap_apply(g, p, dev(psi), 0.05, defl=d, dagger=True))
+    ref = oov.overlap_dagger_apply(u, psi, 0.05, alpha, LMAX, phi, lam)
+    assert max_rel(o, ref) < 1e-12
+
+
+def test_deflation_exact_on_true_eigenvectors(ovl):
+    from oracle.eigen import dense_eigs
+    dims = (4, 4, 2, 4)
+    u = latgen.random_su3_field(dims, 41, noise=0.6)
+    lam_all, vec_all = dense_eigs(u)
+    lam, phi = lam_all[:6], vec_all[:6]
+    alpha = och.coeffs_sign_interp(63, 0.05)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f64")
+    s = host(ovl.sign_apply(g, p, dev(phi), defl=d))
+    for i in range(6):
+        assert rel_err(s[i], np.sign(lam[i]) * phi[i]) < 1e-12
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_defl_project_correct(ovl, store):
+    dims = (4, 2, 4, 6)
+    phi, lam = random_basis(dims, 7, 51)
+    psi = latgen.gaussian_spinor(dims, 52, nrhs=3)
+    cdt = torch.complex128 if store == "f64" else torch.complex64
+    d = ovl.Deflation(dev(phi), lam, store)
+    basis = host(d.basis())
+    assert rel_err(basis, phi) < 1e-13
+    c = host(ovl.defl_project(d, dev(psi, cdt)))
+    psi_in = latgen.round_to_f32(psi) if store == "f32" else psi
+    phi_in = latgen.round_to_f32(phi) if store == "f32" else phi
+    tol = 1e-13 if store == "f64" else 1e-6
+    c_ref = np.stack([odefl.project(phi_in, psi_in[r]) for r in range(3)])
+    for r in range(3):
+        assert max_rel(c[r], c_ref[r]) < tol
+    # the correction takes the oracle's projections as its input on both sides
+    w = np.linspace(-1.0, 2.0, 7)
+    out = dev(psi, cdt)
+    ovl.defl_correct(d, out, dev(c_ref), w)
+    out = host(out)
+    for r in range(3):
+        ref = odefl.correct(phi_in, psi_in[r], c_ref[r], w)
+        assert max_rel(out[r], ref) < tol
+
+
+def test_defl_rank_deficient(ovl):
+    dims = (2, 2, 2, 2)
+    raw = latgen.gaussian_spinor(dims, 61, nrhs=3)
+    raw[2] = 2.0 * raw[0] - raw[1]
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.Deflation(dev(raw), np.array([0.1, 0.2, 0.3]), "f64")
+    assert e.value.status == "OVL_EDEFL"
+
+
+def test_link_vjp_fp64(ovl):
+    dims = (4, 3, 2, 4)
+    u = latgen.random_su3_field(dims, 71)
+    chi = latgen.gaussian_spinor(dims, 72)
+    psi = latgen.gaussian_spinor(dims, 73)
+    g = ovl.GaugeField(dev(u), "f64")
+    got = host(ovl.wilson_link_vjp(g, dev(chi), dev(psi)))
+    assert max_rel(got, oforce.wilson_link_vjp(chi, psi)) < 1e-14
+    acc = ovl.wilson_link_vjp(g, dev(chi), dev(psi))
+    ovl.wilson_link_vjp(g, dev(chi), dev(psi), out=acc, accumulate=True)
+    assert max_rel(host(acc), 2 * oforce.wilson_link_vjp(chi, psi)) < 1e-14
+
+
+@pytest.mark.parametrize("stride", [0, 1, 5, 63])
+def test_sign_force_fp64(ovl, stride):
+    dims = (4, 4, 4, 4)
+    u = latgen.smeared_field(dims, 81, steps=1)
+    chi = latgen.gaussian_spinor(dims, 82)
+    psi = latgen.gaussian_spinor(dims, 83)
+    alpha = och.coeffs_sign_interp(63, 0.07)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    got = host(ovl.sign_force(g, p, dev(chi), dev(psi), ckpt_stride=stride))
+    ref = oforce.sign_force(u, chi, psi, alpha, LMAX)
+    assert max_rel(got, ref) < 1e-12
+
+
+def test_sign_force_fp32(ovl):
+    dims = (4, 4, 4, 4)
+    u = latgen.smeared_field(dims, 84, steps=1)
+    chi = latgen.gaussian_spinor(dims, 85)
+    psi = latgen.gaussian_spinor(dims, 86)
+    alpha = och.coeffs_sign_interp(63, 0.07)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    got = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64)))
+    ref = oforce.sign_force(u, chi, psi, alpha, LMAX)
+    assert rel_err(got, ref) < 1e-5
+
+
+def test_autograd_sign_function(ovl):
+    dims = (2, 2, 2, 4)
+    u = latgen.random_su3_field(dims, 91)
+    psi = latgen.gaussian_spinor(dims, 92)
+    chi = latgen.gaussian_spinor(dims, 93)
+    alpha = och.coeffs_sign_interp(15, 0.1)
+    p = ovl.Polynomial(alpha, LMAX)
+    du = dev(u).requires_grad_(True)
+    dpsi = dev(psi).requires_grad_(True)
+    y = ovl.SignFunction.apply(du, dpsi, p, "f64")
+    loss = torch.real(torch.vdot(dev(chi).reshape(-1), y.reshape(-1)))
+    loss.backward()
+    assert max_rel(host(du.grad), oforce.sign_force(u, chi, psi, alpha, LMAX)) < 1e-12
+    assert max_rel(host(dpsi.grad), och.poly_apply(u, chi, alpha, LMAX)) < 1e-12
+
+
+def test_gauge_covariance_gpu(ovl):
+    dims = (4, 4, 2, 4)
+    u = latgen.random_su3_field(dims, 101, noise=0.6)
+    psi = latgen.gaussian_spinor(dims, 102)
+    om = latgen.random_gauge_transform(dims, 103)
+    alpha = och.coeffs_sign_interp(31, 0.08)
+    p = ovl.Polynomial(alpha, LMAX)
+    a = host(ovl.sign_apply(ovl.GaugeField(dev(latgen.gauge_transform_links(u, om)), "f64"), p,
+                            dev(latgen.gauge_transform_spinor(psi, om))))
+    b = latgen.gauge_transform_spinor(host(ovl.sign_apply(ovl.GaugeField(dev(u), "f64"), p,
+                                                          dev(psi))), om)
+    assert rel_err(a, b) < 1e-13
+
+
+def test_divergence_flag(ovl):
+    dims = (4, 4, 4, 4)
+    u = latgen.random_su3_field(dims, 111)
+    psi = latgen.gaussian_spinor(dims, 112)
+    alpha = och.coeffs_sign_interp(63, 0.1)
+    g = ovl.GaugeField(dev(u), "f64")
+    ovl.sign_apply(g, ovl.Polynomial(alpha, LMAX), dev(psi))
+    assert g.flags() == 0
+    ovl.sign_apply(g, ovl.Polynomial(alpha, 3.0), dev(psi))     # lmax below ||K||
+    assert g.flags() & 0x2
+    assert g.flags() == 0                                         # cleared by the read
+
+
+def test_alias_rejected(ovl):
+    dims = (2, 2, 2, 2)
+    g = ovl.GaugeField(dev(latgen.random_su3_field(dims, 1)), "f64")
+    x = dev(latgen.gaussian_spinor(dims, 2))
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.wilson_apply(g, x, out=x)
+    assert e.value.status == "OVL_EALIAS"
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.kernel_apply(g, dev(latgen.gaussian_spinor(dims, 2), torch.complex64))
+    assert e.value.status == "OVL_EDTYPE"
+
+
+def test_repeatable_bitwise(ovl):
+    dims = (8, 8, 8, 16)
+    u = latgen.random_su3_field(dims, 121)
+    psi = dev(latgen.gaussian_spinor(dims, 122), torch.complex64)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(och.coeffs_sign_interp(99, 0.08), LMAX)
+    phi, lam = random_basis(dims, 4, 123)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    a = ovl.overlap_apply(g, p, psi, 0.05, defl=d)
+    b = ovl.overlap_apply(g, p, psi, 0.05, defl=d)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_dw_full_size_24x24x24x48(ovl):
+    """The force lattice at full size, in the launch configuration the benchmark times."""
+    dims = (24, 24, 24, 48)
+    u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 5))
+    psi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5))
+    ref = ow.kop(u, psi)
+    g64 = ovl.GaugeField(dev(u), "f64")
+    assert max_rel(host(ovl.kernel_apply(g64, dev(psi))), ref) < 1e-14
+    g32 = ovl.GaugeField(dev(u), "f32")
+    got32 = host(ovl.kernel_apply(g32, dev(psi, torch.complex64)))
+    assert rel_err(got32, ref) < 1e-6
