@@ -189,6 +189,16 @@ __device__ __forceinline__ void bst(rsrc_t r, uint32_t comp_soff, uint32_t site,
   bio<SE, C>::st(r, site * elem_traits<SE>::bytes, comp_soff, v);
 }
 
+// element `index` (lane-dependent, any component) of an array of SE described by resource r
+template <class C, class SE>
+__device__ __forceinline__ cx<C> bldv(rsrc_t r, uint32_t index) {
+  return bio<SE, C>::ld(r, index * elem_traits<SE>::bytes, 0u);
+}
+template <class C, class SE>
+__device__ __forceinline__ void bstv(rsrc_t r, uint32_t index, cx<C> v) {
+  bio<SE, C>::st(r, index * elem_traits<SE>::bytes, 0u, v);
+}
+
 // plain pointer access for the small set-up kernels
 template <class C>
 __device__ __forceinline__ cx<C> load_c(const double2 *p, int64_t i) {

@@ -8,6 +8,7 @@
 
 #include "common.hpp"
 #include "stencil.hpp"
+#include "stencil_quad.hpp"
 
 namespace ovl {
 
@@ -68,55 +69,79 @@ struct StepParams {
   int remap;
 };
 
-template <class C, class SE, class LE>
-__global__ void __launch_bounds__(kBlock) step_kernel(StepParams p) {
+// 4 * SPB threads cover SPB sites; thread (q = threadIdx.x / SPB, sl = threadIdx.x % SPB) owns
+// direction q for the hopping sum and spin component q for everything after the LDS reduction.
+template <class C, class SE, class LE, int SPB>
+__global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
   __shared__ double lds[2 * 16];
+  __shared__ cx<C> part[4][12][SPB];  // directional partial sums
   const int nblk = gridDim.x;
   const int b = xcd_block(blockIdx.x, nblk, p.remap);
-  const int site = b * kBlock + threadIdx.x;
+  const int q = threadIdx.x / SPB;
+  const int sl = threadIdx.x % SPB;
+  const int site = b * SPB + sl;
   const int r = blockIdx.y;
   const int V = p.g.V;
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;  // component stride (bytes)
   const uint32_t vb = 12u * cs;                               // one right-hand side (bytes)
+  const uint32_t ls = (uint32_t)V * elem_traits<LE>::bytes;
   const int64_t base = (int64_t)r * 12 * V;
+  const bool lower = q >= 2;                                  // spin components 2, 3
   double nrm[2] = {0.0, 0.0};
-  if (site < V) {
-    const rsrc_t v = make_rsrc(reinterpret_cast<const SE *>(p.v) + base, vb);
-    const LinkRes<LE> U = link_res<LE>(p.U, V);
+  const bool active = site < V;
+  const rsrc_t v = make_rsrc(reinterpret_cast<const SE *>(p.v) + base, vb);
+  const bool vg5 = p.v_g5 != 0;
+  {
     cx<C> acc[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
-    hop_site<C, SE, LE>(acc, v, U, p.g, site, p.v_g5 != 0);
-    const C kd = C(p.kd), kh = C(p.kh);
-    cx<C> res[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-      cx<C> vx = bld<C, SE>(v, i * cs, site);
-      if (p.v_g5 && i >= 6) vx = -vx;
-      cx<C> y = mk<C>(kd * vx.re + kh * acc[i].re, kd * vx.im + kh * acc[i].im);
-      if (p.y_g5 && i >= 6) y = -y;
-      res[i] = y;
+    if (active) {
+      const rsrc_t U = make_rsrc(p.U, 36u * ls);
+      int fwd, bwd;
+      lane_neighbours(p.g, site, q, fwd, bwd);
+      const DirCoef<C> k = dir_coef<C>(q);
+      const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)V;
+      quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + site, k, C(1), vg5);
+      quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + bwd, k, C(-1), vg5);
     }
-    cx<C> srcx[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) part[q][i][sl] = acc[i];
+  }
+  __syncthreads();
+  if (active) {
+    cx<C> hop[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      hop[c] = part[0][3 * q + c][sl] + part[1][3 * q + c][sl] + part[2][3 * q + c][sl] +
+               part[3][3 * q + c][sl];
+    const C kd = C(p.kd), kh = C(p.kh);
+    const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + site;  // element of component 3q
+    cx<C> res[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cx<C> vx = bldv<C, SE>(v, e0 + c * V);
+      if (vg5 && lower) vx = -vx;
+      cx<C> y = mk<C>(kd * vx.re + kh * hop[c].re, kd * vx.im + kh * hop[c].im);
+      if (p.y_g5 && lower) y = -y;
+      res[c] = y;
+    }
+    cx<C> srcx[3];
     const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
     if (need_src) {
       const rsrc_t s = make_rsrc(reinterpret_cast<const SE *>(p.src) + base, vb);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) srcx[i] = bld<C, SE>(s, i * cs, site);
+      for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(s, e0 + c * V);
     }
     if (p.a != 0.0) {
-      const C a = C(p.a);
+      const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        cx<C> sx = (p.src_g5 && i >= 6) ? -srcx[i] : srcx[i];
-        res[i] = res[i] + scale(sx, a);
-      }
+      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
     }
     if (p.w != nullptr) {
       const rsrc_t w = make_rsrc(reinterpret_cast<const SE *>(p.w) + base, vb);
       const C t = C(p.t);
 #pragma unroll
-      for (int i = 0; i < 12; ++i) res[i] = res[i] + scale(bld<C, SE>(w, i * cs, site), t);
+      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(bldv<C, SE>(w, e0 + c * V), t);
     }
     if (p.mode >= MODE_SIGN) {
       for (int e = 0; e < p.n_ev; ++e) {
@@ -125,28 +150,23 @@ __global__ void __launch_bounds__(kBlock) step_kernel(StepParams p) {
         const double we = p.wdefl[e];
         const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
 #pragma unroll
-        for (int i = 0; i < 12; ++i) res[i] = cmadd(res[i], bld<C, SE>(ph, i * cs, site), d);
+        for (int c = 0; c < 3; ++c) res[c] = cmadd(res[c], bldv<C, SE>(ph, e0 + c * V), d);
       }
-      double so = 0.0, si = 0.0;
 #pragma unroll
-      for (int i = 0; i < 12; ++i) {
-        so += double(res[i].re) * double(res[i].re) + double(res[i].im) * double(res[i].im);
-        si += double(srcx[i].re) * double(srcx[i].re) + double(srcx[i].im) * double(srcx[i].im);
+      for (int c = 0; c < 3; ++c) {
+        nrm[0] += double(res[c].re) * double(res[c].re) + double(res[c].im) * double(res[c].im);
+        nrm[1] += double(srcx[c].re) * double(srcx[c].re) + double(srcx[c].im) * double(srcx[c].im);
       }
-      nrm[0] = so;
-      nrm[1] = si;
       if (p.mode == MODE_OVERLAP || p.mode == MODE_OVERLAP_DAG) {
-        const C hp = C(0.5 * (1.0 + p.mu)), hm = C(0.5 * (1.0 - p.mu));
+        const C hp = C(0.5 * (1.0 + p.mu));
+        const C hm = (p.mode == MODE_OVERLAP && lower) ? C(-0.5 * (1.0 - p.mu)) : C(0.5 * (1.0 - p.mu));
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-          cx<C> sg = (p.mode == MODE_OVERLAP && i >= 6) ? -res[i] : res[i];
-          res[i] = scale(srcx[i], hp) + scale(sg, hm);
-        }
+        for (int c = 0; c < 3; ++c) res[c] = scale(srcx[c], hp) + scale(res[c], hm);
       }
     }
     const rsrc_t o = make_rsrc(reinterpret_cast<SE *>(p.out) + base, vb);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) bst<C, SE>(o, i * cs, site, res[i]);
+    for (int c = 0; c < 3; ++c) bstv<C, SE>(o, e0 + c * V, res[c]);
   }
   if (p.norm_partial != nullptr) {
     block_sum<2>(nrm, lds);

@@ -186,9 +186,18 @@ int check_spinor_call(const ovl_gauge *g, const void *out, const void *in, int n
 
 int grid_blocks(int V) { return (V + kBlock - 1) / kBlock; }
 
+// fused step kernel launch shape: 4 threads per site, SPB sites per workgroup; small lattices
+// get one-wave workgroups so that the sites spread over more compute units
+int step_spb(int V) { return V >= 64 * 1024 ? 64 : 16; }
+int step_blocks(int V) {
+  const int spb = step_spb(V);
+  return (V + spb - 1) / spb;
+}
+
 template <class C, class SE, class LE>
 int launch_step(const StepParams &p, int nrhs, hipStream_t s, bool timed) {
-  dim3 grid(grid_blocks(p.g.V), nrhs);
+  const int spb = step_spb(p.g.V);
+  dim3 grid(step_blocks(p.g.V), nrhs);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     std::lock_guard<std::mutex> lk(g_timing_mu);
@@ -196,7 +205,10 @@ int launch_step(const StepParams &p, int nrhs, hipStream_t s, bool timed) {
     e1 = pool_event();
   }
   if (e0 && e1) HIP_TRY(hipEventRecord(e0, s));
-  step_kernel<C, SE, LE><<<grid, kBlock, 0, s>>>(p);
+  if (spb == 64)
+    step_kernel<C, SE, LE, 64><<<grid, 256, 0, s>>>(p);
+  else
+    step_kernel<C, SE, LE, 16><<<grid, 64, 0, s>>>(p);
   HIP_TRY(hipGetLastError());
   if (e0 && e1) {
     HIP_TRY(hipEventRecord(e1, s));
@@ -265,7 +277,7 @@ int run_sign(const ovl_gauge *g, const ovl_poly *p, ovl_defl *d, int mode, doubl
   const int N = (int)p->alpha.size() - 1;
   const int V = g->g.V;
   const size_t vec_bytes = (size_t)nrhs * 12 * V * elem_bytes(spin_dt);
-  const int nblk_site = grid_blocks(V);
+  const int nblk_site = step_blocks(V);
   const int nblk_proj = project_blocks(V);
   const int n_ev = d ? d->n_ev : 0;
   // scratch: [vector][norm partials][projection partials][c]
@@ -389,8 +401,8 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
   if (in_dt != OVL_F64 && in_dt != OVL_F32) return fail(OVL_EDTYPE, "link input dtype %d", in_dt);
   if (store_dt != OVL_F64 && store_dt != OVL_F32 && store_dt != OVL_BF16)
     return fail(OVL_EDTYPE, "link storage dtype %d", store_dt);
-  if (!fits_u32(9ull * geo.V, store_dt))
-    return fail(OVL_EDIMS, "links of one direction (%d sites) exceed 4 GiB", geo.V);
+  if (!fits_u32(36ull * geo.V, store_dt))
+    return fail(OVL_EDIMS, "links of %d sites exceed 4 GiB", geo.V);
   hipStream_t s = as_stream(stream);
   ovl_gauge *g = new (std::nothrow) ovl_gauge();
   if (!g) return fail(OVL_ENOMEM, "host allocation failed");
