@@ -67,6 +67,7 @@ struct StepParams {
   const double *wdefl;     // [n_ev] weights
   double *norm_partial;    // [nblk][nrhs][2] or null
   int remap;
+  int lstride;             // elements between consecutive link components (>= V, padded)
 };
 
 // 4 * SPB threads cover SPB sites; thread (q = threadIdx.x / SPB, sl = threadIdx.x % SPB) owns
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
   const int V = p.g.V;
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;  // component stride (bytes)
   const uint32_t vb = 12u * cs;                               // one right-hand side (bytes)
-  const uint32_t ls = (uint32_t)V * elem_traits<LE>::bytes;
+  const uint32_t ls = (uint32_t)p.lstride * elem_traits<LE>::bytes;
   const int64_t base = (int64_t)r * 12 * V;
   const bool lower = q >= 2;                                  // spin components 2, 3
   double nrm[2] = {0.0, 0.0};
@@ -100,7 +101,7 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
       int fwd, bwd;
       lane_neighbours(p.g, site, q, fwd, bwd);
       const DirCoef<C> k = dir_coef<C>(q);
-      const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)V;
+      const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)p.lstride;
       quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + site, k, C(1), vg5);
       quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + bwd, k, C(-1), vg5);
     }
@@ -308,6 +309,16 @@ template <class S, class D>
 __global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) cvt(src[k], dst[k]);
+}
+
+// links [36][V] (caller layout) -> [36][lstride] in the storage format
+template <class S, class D>
+__global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst, int V,
+                                  int lstride) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)36 * V) return;
+  const int64_t comp = k / V, site = k - comp * V;
+  cvt(src[k], dst[comp * lstride + site]);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -107,7 +107,8 @@ struct ovl_gauge {
   Geom g;
   int store_dt;
   int device;
-  void *links;        // [4][3][3][V] complex in store_dt
+  int lstride;        // elements between link components (padded, see link_stride)
+  void *links;        // [4][3][3][lstride] complex in store_dt
   uint32_t *flags;    // sticky device flags
 };
 
@@ -159,6 +160,16 @@ Prec precision(int spin_dt, int store_dt) {
   if (spin_dt == OVL_F32 && store_dt == OVL_F32) return P_F32;
   if (spin_dt == OVL_F32 && store_dt == OVL_BF16) return P_F32_BF16;
   return P_BAD;
+}
+
+// Component stride of the packed links: at least V elements, rounded so that the stride in bytes
+// is an odd multiple of 256.  With a stride of V elements the 36 components of one site sit a
+// multiple of a large power of two apart (V = 2^17 for 16^3x32) and compete for the same L2 sets;
+// the odd multiple spreads them over channels and sets.
+int link_stride(int V, int esize) {
+  int64_t bytes = ((int64_t)V * esize + 255) / 256 * 256;
+  if ((bytes / 256) % 2 == 0) bytes += 256;
+  return (int)(bytes / esize);
 }
 
 // every array a kernel addresses through one buffer resource must span < 4 GiB
@@ -232,6 +243,7 @@ StepParams base_params(const ovl_gauge *g) {
   std::memset(&p, 0, sizeof(p));
   p.U = g->links;
   p.g = g->g;
+  p.lstride = g->lstride;
   p.remap = 1;
   return p;
 }
@@ -401,7 +413,8 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
   if (in_dt != OVL_F64 && in_dt != OVL_F32) return fail(OVL_EDTYPE, "link input dtype %d", in_dt);
   if (store_dt != OVL_F64 && store_dt != OVL_F32 && store_dt != OVL_BF16)
     return fail(OVL_EDTYPE, "link storage dtype %d", store_dt);
-  if (!fits_u32(36ull * geo.V, store_dt))
+  const int lstride = link_stride(geo.V, elem_bytes(store_dt));
+  if (!fits_u32(36ull * lstride, store_dt))
     return fail(OVL_EDIMS, "links of %d sites exceed 4 GiB", geo.V);
   hipStream_t s = as_stream(stream);
   ovl_gauge *g = new (std::nothrow) ovl_gauge();
@@ -410,24 +423,26 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
   g->store_dt = store_dt;
   g->links = nullptr;
   g->flags = nullptr;
+  g->lstride = lstride;
   hipError_t e = hipGetDevice(&g->device);
   const int64_t n = (int64_t)36 * geo.V;
-  if (e == hipSuccess) e = hipMalloc(&g->links, n * elem_bytes(store_dt));
+  if (e == hipSuccess) e = hipMalloc(&g->links, (int64_t)36 * lstride * elem_bytes(store_dt));
   if (e == hipSuccess) e = hipMalloc((void **)&g->flags, 256);
   if (e == hipSuccess) e = hipMemsetAsync(g->flags, 0, 256, s);
   if (e == hipSuccess) {
     const int threads = 256;
     const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+    const int V = geo.V;
     if (in_dt == OVL_F64) {
       const double2 *src = (const double2 *)U_dev;
-      if (store_dt == OVL_F64) convert_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, n);
-      else if (store_dt == OVL_F32) convert_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, n);
-      else convert_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, n);
+      if (store_dt == OVL_F64) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, V, lstride);
+      else if (store_dt == OVL_F32) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, V, lstride);
+      else pack_links_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, V, lstride);
     } else {
       const float2 *src = (const float2 *)U_dev;
-      if (store_dt == OVL_F64) convert_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, n);
-      else if (store_dt == OVL_F32) convert_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, n);
-      else convert_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, n);
+      if (store_dt == OVL_F64) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, V, lstride);
+      else if (store_dt == OVL_F32) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, V, lstride);
+      else pack_links_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, V, lstride);
     }
     e = hipGetLastError();
   }
