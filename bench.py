@@ -50,7 +50,138 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="run only the timed mixed-precision loop (for rocprofv3 runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the batched, BF16/24-mode and force measurements")
     return ap.parse_args()
+
+
+def gpu_ms(torch, fn, reps, warmup=1):
+    """Average milliseconds of fn() on the current stream (HIP events)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def measure_extra(ovl, latgen, low_modes, torch, dev):
+    """Batched mixed-volume form, BF16 links with 24 deflated modes, and the force."""
+    out = {}
+    # (1) batched: 12 spin-colour point sources on 16^3x32 + 4 x 8^3x16 + 2 x 12^3x24, degree 299
+    t0 = time.time()
+    alpha = ovl.cheb_sign_coeffs(300, 0.05)
+    p32 = ovl.Polynomial(alpha, LMAX)
+    probs32, probs64 = [], []
+    shapes = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
+    n_rhs_total = 0
+    for i, (dims, nrhs) in enumerate(shapes):
+        u = torch.from_numpy(latgen.smeared_field(dims, latgen.seed_for("gauge", 4, i))).to(dev)
+        if nrhs == 12:
+            src = np.stack([latgen.point_source(dims, s, c) for s in range(4) for c in range(3)])
+        else:
+            src = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 4, i), nrhs=1)
+        s64 = torch.from_numpy(src).to(dev)
+        probs32.append((ovl.GaugeField(u, "f32"), s64.to(torch.complex64)))
+        probs64.append((ovl.GaugeField(u, "f64"), s64))
+        n_rhs_total += nrhs
+    log(f"batched inputs {time.time() - t0:.1f}s")
+    outs = [torch.empty_like(x) for _, x in probs32]
+    outs64 = [torch.empty_like(x) for _, x in probs64]
+    ms_b = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs32, outs), 5)
+    ms_u = gpu_ms(torch, lambda: [ovl.sign_apply(g, p32, x, out=o)
+                                  for (g, x), o in zip(probs32, outs)], 3)
+    ms_64 = gpu_ms(torch, lambda: [ovl.sign_apply(g, p32, x, out=o)
+                                   for (g, x), o in zip(probs64, outs64)], 2)
+    ovl.batch_sign_apply(p32, probs32, outs)
+    [ovl.sign_apply(g, p32, x, out=o) for (g, x), o in zip(probs64, outs64)]
+    torch.cuda.synchronize()
+    num = sum(float(torch.linalg.vector_norm(a.to(torch.complex128) - b) ** 2)
+              for a, b in zip(outs, outs64))
+    den = sum(float(torch.linalg.vector_norm(b) ** 2) for b in outs64)
+    out["batched"] = {
+        "workload": "sign(K)psi, degree 299, eps 0.05, no deflation: 12 point sources on "
+                    "16^3x32 + 4 x 8^3x16 + 2 x 12^3x24 (own stout-smeared fields), FP32",
+        "rhs_applies_per_s": round(n_rhs_total * 1e3 / ms_b, 2),
+        "ms_per_batch": round(ms_b, 3),
+        "unbatched_f32_ms": round(ms_u, 3),
+        "plain_f64_ms": round(ms_64, 3),
+        "speedup_vs_unbatched_f32": round(ms_u / ms_b, 3),
+        "speedup_vs_plain_f64": round(ms_64 / ms_b, 3),
+        "rel_err_vs_f64_gpu": (num / den) ** 0.5,
+    }
+    log(f"batched: {ms_b:.2f} ms/batch, unbatched {ms_u:.2f}, FP64 {ms_64:.2f}")
+    del probs32, probs64, outs, outs64
+
+    # (2) BF16 links, FP32 spinors, 24 deflated modes (FP32 matrix-core projection), degree 399
+    t0 = time.time()
+    dims = (16, 16, 16, 32)
+    u = torch.from_numpy(latgen.smeared_field(dims, latgen.seed_for("gauge", 3))).to(dev)
+    psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 3))).to(dev)
+    g64 = ovl.GaugeField(u, "f64")
+    gbf = ovl.GaugeField(u, "bf16")
+    lam, phi, res, eps = low_modes(g64, 24, LMAX, block=64, cut=1.0)
+    alpha = ovl.cheb_sign_coeffs(400, eps)
+    lmax_bf = LMAX * (1 + 2.0 ** -6)
+    pbf = ovl.Polynomial(alpha, lmax_bf)
+    p64 = ovl.Polynomial(alpha, lmax_bf)
+    dbf = ovl.Deflation(phi, lam, "f32")
+    d64 = ovl.Deflation(phi, lam, "f64")
+    x32 = psi.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    y64 = torch.empty_like(psi)
+    log(f"BF16/24-mode set-up {time.time() - t0:.1f}s (eigen residual {res.max():.1e})")
+    ms_bf = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), 5)
+    ms_p64 = gpu_ms(torch, lambda: ovl.sign_apply(g64, p64, psi, defl=d64, out=y64), 3)
+    ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
+    ovl.sign_apply(g64, p64, psi, defl=d64, out=y64)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y64)
+                / torch.linalg.vector_norm(y64))
+    # the deflation projection alone (FP32 matrix cores), for its utilisation
+    ms_proj = gpu_ms(torch, lambda: ovl.defl_project(dbf, x32), 20)
+    proj_flops = 8.0 * 24 * 12 * int(np.prod(dims))    # complex MAC = 8 real flops
+    out["bf16_24modes"] = {
+        "workload": "sign(K)psi on 16^3x32 stout-smeared links stored in BF16, FP32 spinors and "
+                    "accumulation, degree 399, 24 deflated modes (FP32 matrix-core projection)",
+        "applies_per_s": round(1e3 / ms_bf, 2),
+        "plain_f64_applies_per_s": round(1e3 / ms_p64, 2),
+        "speedup_vs_plain_f64": round(ms_p64 / ms_bf, 3),
+        "rel_err_vs_f64_gpu_same_polynomial": err,
+        "lmax": lmax_bf, "eps": round(float(eps), 5), "eigen_residual_max": float(res.max()),
+        "projection_us": round(ms_proj * 1e3, 2),
+        "projection_mfma_TFLOPs": round(proj_flops / (ms_proj * 1e-3) / 1e12, 3),
+        "projection_mfma_frac_of_fp32_peak": round(proj_flops / (ms_proj * 1e-3) / 157.3e12, 5),
+        "projection_GBps": round(24 * 12 * int(np.prod(dims)) * 8 / (ms_proj * 1e-3) / 1e9, 1),
+    }
+    log(f"BF16 24-mode: {ms_bf:.2f} ms/apply, FP64 {ms_p64:.2f} ms, err {err:.2e}")
+    del g64, gbf, dbf, d64, phi
+
+    # (3) force d Re<chi, p(X) psi>/dU at 24^3x48, degree 299, FP32, sqrt(N) checkpoints
+    t0 = time.time()
+    dims = (24, 24, 24, 48)
+    u = torch.from_numpy(latgen.random_su3_field(dims, latgen.seed_for("gauge", 5))).to(dev)
+    psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5))).to(dev)
+    chi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5, 1))).to(dev)
+    g32 = ovl.GaugeField(u, "f32")
+    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(300, 0.05), LMAX)
+    G = torch.empty((4, 3, 3) + tuple(psi.shape[-4:]), dtype=torch.complex64, device=dev)
+    x32, c32 = psi.to(torch.complex64), chi.to(torch.complex64)
+    log(f"force inputs {time.time() - t0:.1f}s")
+    ms_f = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, out=G), 2)
+    out["force"] = {
+        "workload": "d Re<chi, p(K/lmax) psi>/dU on 24^3x48 near-unit links, degree 299, FP32, "
+                    "checkpoint stride ceil(sqrt 299) = 18",
+        "ms_per_force": round(ms_f, 2),
+        "forces_per_s": round(1e3 / ms_f, 3),
+    }
+    log(f"force 24^3x48: {ms_f:.1f} ms")
+    return out
 
 
 def main():
@@ -176,6 +307,8 @@ def main():
         gb.close()
     del d_ub, d_pb
 
+    extra = {} if args.no_extra else measure_extra(ovl, latgen, low_modes, torch, dev)
+
     # ---------------- CPU oracle baseline (bounded sample) ----------------
     cpu = None
     err_vs_oracle = None
@@ -256,6 +389,7 @@ def main():
         "cpu_baseline": cpu,
         "dw_24x24x24x48": dw,
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

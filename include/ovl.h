@@ -136,6 +136,21 @@ int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, voi
 int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
                       int dagger, void *out, const void *in, int nrhs, int spin_dt, void *stream);
 
+/* Batched form of ovl_sign_apply (no deflation): up to 16 lattice problems -- each its own gauge
+ * field, volume and right-hand-side count -- evaluated with one polynomial in one kernel launch
+ * per K application, so small volumes fill the GPU together and the right-hand sides of one field
+ * share its links through L2.  All items must have the same operator precision (spin_dt and link
+ * storage).  Errors as ovl_sign_apply, plus EINVAL (n_items outside [1, 16]) and EALIAS (an
+ * output overlapping any item's input or another output). */
+typedef struct {
+  const ovl_gauge *g; /* gauge field of this item                                  */
+  const void *in;     /* [nrhs][4][3][V] complex of spin_dt                        */
+  void *out;          /* same shape                                                */
+  int nrhs;
+} ovl_batch_item;
+int ovl_batch_sign_apply(const ovl_batch_item *items, int n_items, const ovl_poly *p, int spin_dt,
+                         void *stream);
+
 /* c_dev[r][i] = phi_i^+ in_r (complex double, interleaved; n_ev * nrhs entries), FP64
  * accumulation with a deterministic two-pass reduction (Sec. 2, eq. 3 projection). */
 int ovl_defl_project(const ovl_defl *d, double *c_dev, const void *in, int nrhs, int spin_dt,
@@ -160,6 +175,23 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G_dev, const void *chi, const 
  * in ovl_wilson_link_vjp; single right-hand side. */
 int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const void *chi,
                    const void *psi, int ckpt_stride, int spin_dt, void *stream);
+
+/* ---- launch tuning ------------------------------------------------------------------------ */
+
+/* Measure the fused stencil kernel on this gauge field for nrhs right-hand sides of spin_dt over
+ * its launch configurations (sites per workgroup 16 or 64; t-streaming tile order or memory
+ * order; XCD-contiguous workgroup remap on or off), keep the fastest for every later call with the
+ * same extents, precision and nrhs, and append it to the text file cache_path when not NULL
+ * (one line: Lx Ly Lz Lt precision nrhs spb tiles remap microseconds).  *best_us (nullable)
+ * receives the winner's time per K application.  Synchronises the stream; allocates two
+ * temporary vectors.  Errors: EINVAL, EDTYPE, EDIMS, ENOMEM, EHIP. */
+int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_path,
+                 double *best_us, void *stream);
+/* Load configurations written by ovl_autotune; returns the number of entries read (>= 0) or
+ * OVL_EINVAL when the file cannot be opened. */
+int ovl_autotune_load(const char *cache_path);
+/* The configuration the library will use: cfg_out = {sites per workgroup, tile order, remap}. */
+int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]);
 
 /* ---- diagnostics ------------------------------------------------------------------------- */
 

@@ -36,16 +36,28 @@ SIGNATURES = {
     "ovl_kernel_apply": (_i, [_vp, _vp, _vp, _i, _i, _d, _vp]),
     "ovl_sign_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_overlap_apply": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
+    "ovl_batch_sign_apply": (_i, [_vp, _i, _vp, _i, _vp]),
     "ovl_defl_project": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "ovl_defl_correct": (_i, [_vp, _vp, _vp, _dp, _i, _i, _vp]),
     "ovl_wilson_link_vjp": (_i, [_vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_sign_force": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
+    "ovl_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p, _dp, _vp]),
+    "ovl_autotune_load": (_i, [ctypes.c_char_p]),
+    "ovl_launch_config": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
     "ovl_last_error": (ctypes.c_char_p, []),
     "ovl_status_flags": (_i, [_vp, ctypes.POINTER(ctypes.c_uint32), _i]),
     "ovl_timing_enable": (_i, [_i]),
     "ovl_timing_read": (_i, [_dp, ctypes.POINTER(ctypes.c_int64)]),
     "ovl_version": (ctypes.c_char_p, []),
 }
+
+
+
+class BatchItem(ctypes.Structure):
+    """ovl_batch_item"""
+    _fields_ = [("g", ctypes.c_void_p), ("inp", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int)]
+
 
 _LIB = None
 

@@ -220,6 +220,24 @@ def overlap_apply(g: GaugeField, poly: Polynomial, psi, mu: float, defl: Deflati
     return out
 
 
+def batch_sign_apply(poly: Polynomial, problems, outs=None):
+    """sum_m alpha_m T_m(X_i) psi_i for a list of (GaugeField, psi) problems in one launch per
+    K application (Sec. 2, eq. 3 without deflation).  Returns the list of outputs."""
+    if not 1 <= len(problems) <= 16:
+        raise ValueError("between 1 and 16 problems")
+    arr = (_lib.BatchItem * len(problems))()
+    res = []
+    dt = None
+    for i, (g, psi) in enumerate(problems):
+        nrhs = _check_spinor(psi, g.dims)
+        out = _out_like(psi, None if outs is None else outs[i])
+        dt = _spin_dtype(psi)
+        arr[i] = _lib.BatchItem(g.handle.value, psi.data_ptr(), out.data_ptr(), nrhs)
+        res.append(out)
+    call("ovl_batch_sign_apply", arr, len(problems), poly._h, dt, _stream())
+    return res
+
+
 def defl_project(defl: Deflation, psi) -> torch.Tensor:
     """c[r, i] = phi_i^+ psi_r as complex128 (nrhs, n_ev), FP64 accumulation."""
     nrhs = _check_spinor(psi, defl.dims)
@@ -296,6 +314,31 @@ class SignFunction(torch.autograd.Function):
         if ctx.needs_input_grad[1]:
             grad_psi = sign_apply(ctx.g, ctx.poly, grad_y)
         return grad_u, grad_psi, None, None
+
+
+def autotune(g: GaugeField, nrhs: int = 1, dtype=None, cache_path: str = None) -> float:
+    """Pick the fastest launch configuration of the fused stencil for this lattice; returns its
+    microseconds per K application.  The choice applies to every later call in this process."""
+    dt = _spin_dtype(torch.empty(0, dtype=dtype or g.spin_dtype))
+    us = ctypes.c_double(0)
+    call("ovl_autotune", g.handle, int(nrhs), dt, cache_path.encode() if cache_path else None,
+         ctypes.byref(us), _stream())
+    return us.value
+
+
+def autotune_load(cache_path: str) -> int:
+    n = _lib.load().ovl_autotune_load(cache_path.encode())
+    if n < 0:
+        raise _lib.OvlError("ovl_autotune_load", n, _lib.load().ovl_last_error().decode())
+    return n
+
+
+def launch_config(g: GaugeField, nrhs: int = 1, dtype=None):
+    """(sites per workgroup, tile order on, XCD remap on) the library will use."""
+    dt = _spin_dtype(torch.empty(0, dtype=dtype or g.spin_dtype))
+    out = (ctypes.c_int * 3)()
+    call("ovl_launch_config", g.handle, int(nrhs), dt, out)
+    return tuple(out)
 
 
 def timing_enable(on: bool = True):

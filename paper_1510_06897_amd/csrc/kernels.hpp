@@ -49,59 +49,123 @@ __device__ __forceinline__ void block_sum(double v[NV], double *lds /* >= NV * 1
 // final modes add the deflation correction sum_i phi_i w_i c_i and combine into the overlap
 // operator; they also emit FP64 block partials of ||res||^2 and ||src||^2.
 enum : int { MODE_STEP = 0, MODE_SIGN = 1, MODE_OVERLAP = 2, MODE_OVERLAP_DAG = 3 };
+// which vector of an item a step reads as v / w or writes as out
+enum : int { ROLE_NONE = -1, ROLE_PSI = 0, ROLE_B0 = 1, ROLE_B1 = 2, ROLE_B2 = 3 };
 
-struct StepParams {
-  const void *v;
-  const void *src;
-  const void *w;
-  void *out;
-  const void *U;
+// One lattice problem of a step launch.  A launch covers up to NI problems (different gauge
+// fields, volumes and right-hand-side counts) that share the step's coefficients.
+struct StepItem {
+  const void *U;          // packed links [36][lstride] (link storage)
+  const void *psi;        // source [nrhs][12][V]: the alpha_k term and the overlap combine
+  void *buf[3];           // vectors addressed by role
+  const void *phi;        // deflation basis [n_ev][12][V] (spinor storage), final modes
+  const double2 *c;       // [nrhs][n_ev] projections
+  const double *wdefl;    // [n_ev] weights
+  double *norm_partial;   // [nblk * nrhs][2] or null
   Geom g;
-  double kd, kh, a, t;
-  int v_g5, src_g5, y_g5;
-  int mode;
-  double mu;
-  const void *phi;         // deflation basis [n_ev][12][V] (spinor storage), final modes
-  int n_ev;
-  const double2 *c;        // [nrhs][n_ev] projections
-  const double *wdefl;     // [n_ev] weights
-  double *norm_partial;    // [nblk][nrhs][2] or null
-  int remap;
-  int lstride;             // elements between consecutive link components (>= V, padded)
+  int lstride;            // elements between consecutive link components (>= V, padded)
+  // Workgroup order.  ty > 0: the (x, y, z) volume is cut into tiles of Lx x ty x tz sites
+  // (whole x lines); consecutive workgroups cover one t-slice of a tile, then the same tile at
+  // t + 1, ... through all t, then the next tile.  The t-, z- and y-neighbours a workgroup reads
+  // were then touched by workgroups that ran a tile-slice (well under 2 MB) earlier and are still
+  // in the XCD's L2; halos arise only on the y and z faces of a tile.  ty = 0: memory order.
+  int ty, tz;
+  int n_ev, nrhs;
+  int blk0;               // first global logical workgroup of this item
 };
 
+// Step coefficients plus the problems of one launch: a single problem travels in the kernel
+// arguments (TABLE = false); a batch reads its item table from device memory (TABLE = true),
+// written once per evaluation by write_item_kernel, so the arguments stay small.
+template <bool TABLE>
+struct StepArgs {
+  double kd, kh, a, t, mu;
+  int v_role, w_role, out_role;
+  int v_g5, src_g5, y_g5, mode, remap, n_items;
+  int total_blocks;       // workgroups of the launch
+  const StepItem *table;  // TABLE: n_items items in device memory
+  StepItem item;          // !TABLE: the one problem
+};
+
+__global__ void write_item_kernel(StepItem it, StepItem *dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = it;
+}
+
+// Fused stencil step.  For every site and right-hand side r of every item:
+//   y   = kd v(x) + kh hop(v)(x)              (hop = the sum in eq. 2; v read with gamma5 if v_g5)
+//   y   = gamma5 y                            (if y_g5)
+//   res = y + a psi(x) + t w(x)               (psi read with gamma5 if src_g5; w may alias out)
+// final modes add the deflation correction sum_i phi_i w_i c_i and combine into the overlap
+// operator; they also emit FP64 block partials of ||res||^2 and ||psi||^2.
+//
 // 4 * SPB threads cover SPB sites; thread (q = threadIdx.x / SPB, sl = threadIdx.x % SPB) owns
 // direction q for the hopping sum and spin component q for everything after the LDS reduction.
-template <class C, class SE, class LE, int SPB>
-__global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
+// Within an item the right-hand side is the fastest logical index, so the workgroups that read
+// the same links run together and share them through L2.
+template <class C, class SE, class LE, int SPB, bool TABLE>
+__global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
   __shared__ double lds[2 * 16];
   __shared__ cx<C> part[4][12][SPB];  // directional partial sums
-  const int nblk = gridDim.x;
-  const int b = xcd_block(blockIdx.x, nblk, p.remap);
+  const int gb = xcd_block(blockIdx.x, gridDim.x, p.remap);
+  int it = 0;
+  if (TABLE)
+    for (int i = 1; i < p.n_items; ++i)
+      if (p.table[i].blk0 <= gb) it = i;
+  const StepItem &I = TABLE ? p.table[it] : p.item;
+  const Ext4 ex = ext_of(I.g);
+  const int nrhs = I.nrhs;
+  const int lb = gb - I.blk0;
+  const int r = lb % nrhs;
+  const int b = lb / nrhs;
   const int q = threadIdx.x / SPB;
   const int sl = threadIdx.x % SPB;
-  const int site = b * SPB + sl;
-  const int r = blockIdx.y;
-  const int V = p.g.V;
+  Coord4 c4;
+  int site;
+  bool active;
+  if (I.ty > 0) {
+    const int slice = ex.lx * I.ty * I.tz;  // sites of one tile at one t
+    const int nsub = slice / SPB;
+    int tb = b;
+    const int sub = tb % nsub;
+    tb /= nsub;
+    c4.t = tb % ex.lt;
+    const int tile = tb / ex.lt;
+    const int nty = ex.ly / I.ty;
+    const int local = sub * SPB + sl;
+    c4.x = local % ex.lx;
+    const int rr = local / ex.lx;
+    c4.y = (tile % nty) * I.ty + rr % I.ty;
+    c4.z = (tile / nty) * I.tz + rr / I.ty;
+    site = c4.x + ex.sy * c4.y + ex.sz * c4.z + ex.st * c4.t;
+    active = true;
+  } else {
+    site = b * SPB + sl;
+    active = site < ex.V;
+    c4 = coords_of(ex, active ? site : 0);
+  }
+  const int V = ex.V;
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;  // component stride (bytes)
   const uint32_t vb = 12u * cs;                               // one right-hand side (bytes)
-  const uint32_t ls = (uint32_t)p.lstride * elem_traits<LE>::bytes;
+  const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
   const int64_t base = (int64_t)r * 12 * V;
   const bool lower = q >= 2;                                  // spin components 2, 3
+  auto vec = [&](int role) -> const SE * {
+    const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
+    return reinterpret_cast<const SE *>(ptr) + base;
+  };
   double nrm[2] = {0.0, 0.0};
-  const bool active = site < V;
-  const rsrc_t v = make_rsrc(reinterpret_cast<const SE *>(p.v) + base, vb);
+  const rsrc_t v = make_rsrc(vec(p.v_role), vb);
   const bool vg5 = p.v_g5 != 0;
   {
     cx<C> acc[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
     if (active) {
-      const rsrc_t U = make_rsrc(p.U, 36u * ls);
+      const rsrc_t U = make_rsrc(I.U, 36u * ls);
       int fwd, bwd;
-      lane_neighbours(p.g, site, q, fwd, bwd);
+      dir_neighbours(ex, c4, site, q, fwd, bwd);
       const DirCoef<C> k = dir_coef<C>(q);
-      const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)p.lstride;
+      const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)I.lstride;
       quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + site, k, C(1), vg5);
       quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + bwd, k, C(-1), vg5);
     }
@@ -129,7 +193,7 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
     cx<C> srcx[3];
     const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
     if (need_src) {
-      const rsrc_t s = make_rsrc(reinterpret_cast<const SE *>(p.src) + base, vb);
+      const rsrc_t s = make_rsrc(vec(ROLE_PSI), vb);
 #pragma unroll
       for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(s, e0 + c * V);
     }
@@ -138,17 +202,17 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
     }
-    if (p.w != nullptr) {
-      const rsrc_t w = make_rsrc(reinterpret_cast<const SE *>(p.w) + base, vb);
+    if (p.w_role != ROLE_NONE) {
+      const rsrc_t w = make_rsrc(vec(p.w_role), vb);
       const C t = C(p.t);
 #pragma unroll
       for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(bldv<C, SE>(w, e0 + c * V), t);
     }
     if (p.mode >= MODE_SIGN) {
-      for (int e = 0; e < p.n_ev; ++e) {
-        const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(p.phi) + (int64_t)e * 12 * V, vb);
-        const double2 ce = p.c[r * p.n_ev + e];
-        const double we = p.wdefl[e];
+      for (int e = 0; e < I.n_ev; ++e) {
+        const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(I.phi) + (int64_t)e * 12 * V, vb);
+        const double2 ce = I.c[r * I.n_ev + e];
+        const double we = I.wdefl[e];
         const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
 #pragma unroll
         for (int c = 0; c < 3; ++c) res[c] = cmadd(res[c], bldv<C, SE>(ph, e0 + c * V), d);
@@ -165,15 +229,15 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepParams p) {
         for (int c = 0; c < 3; ++c) res[c] = scale(srcx[c], hp) + scale(res[c], hm);
       }
     }
-    const rsrc_t o = make_rsrc(reinterpret_cast<SE *>(p.out) + base, vb);
+    const rsrc_t o = make_rsrc(vec(p.out_role), vb);
 #pragma unroll
     for (int c = 0; c < 3; ++c) bstv<C, SE>(o, e0 + c * V, res[c]);
   }
-  if (p.norm_partial != nullptr) {
+  if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
     block_sum<2>(nrm, lds);
     if (threadIdx.x == 0) {
-      p.norm_partial[((int64_t)b * gridDim.y + r) * 2 + 0] = nrm[0];
-      p.norm_partial[((int64_t)b * gridDim.y + r) * 2 + 1] = nrm[1];
+      I.norm_partial[(int64_t)lb * 2 + 0] = nrm[0];
+      I.norm_partial[(int64_t)lb * 2 + 1] = nrm[1];
     }
   }
 }
@@ -234,6 +298,79 @@ __global__ void __launch_bounds__(kBlock)
   if (threadIdx.x == 0) {
     for (int j = 0; j < CH && i0 + j < n_ev; ++j)
       partial[((int64_t)blockIdx.x * nrhs + r) * n_ev + i0 + j] = make_double2(acc[2 * j], acc[2 * j + 1]);
+  }
+}
+
+// Deflation projection on the matrix cores (FP32 storage): c[r][e] = sum_k conj(phi_e[k]) psi_r[k]
+// as a real product C = A B with K = 24 V reals (complex numbers stored as (re, im) pairs):
+//   A[e][k] = raw phi_e data,  B[k][2r] = raw psi_r data,  B[k][2r+1] = psi_r pairs (re, im)
+//   turned into (im, -re),  so C[e][2r] = Re c and C[e][2r+1] = Im c.
+// One wave accumulates a 16 x 16 tile (16 eigenvectors x 8 right-hand sides) with
+// v_mfma_f32_16x16x4f32 over its share of K (lane l holds A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16]; each lane reads MT consecutive reals per step); the four waves of a
+// workgroup are added in FP64 in fixed order and pass 2 sums the workgroups in FP64.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaT = 4;  // reals per lane per step
+
+__global__ void __launch_bounds__(256)
+    project_mfma_kernel(const float *phi, int n_ev, const float *psi, int nrhs, int psi_g5, int V,
+                        int chunk, double2 *__restrict__ partial) {
+  __shared__ double tile[4][16][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int e = blockIdx.y * 16 + i;          // A row of this lane
+  const int col = i;                          // B column of this lane
+  const int r = blockIdx.z * 8 + (col >> 1);  // right-hand side of the column
+  const bool imcol = (col & 1) != 0;
+  const int64_t K = (int64_t)24 * V;          // reals per vector
+  const uint32_t vecb = (uint32_t)K * 4u;     // bytes per vector
+  const rsrc_t ra = make_rsrc(phi, vecb * (uint32_t)n_ev);
+  const rsrc_t rb = make_rsrc(psi, vecb * (uint32_t)nrhs);
+  const bool arow = e < n_ev, bcol = r < nrhs;
+  const int64_t k_begin = (int64_t)blockIdx.x * chunk;
+  const int64_t k_end = k_begin + chunk < K ? k_begin + chunk : K;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  // Each step covers 4 waves x 4 lane groups x MT reals.  The loop bound is uniform over the wave:
+  // an MFMA reads its operands from every lane regardless of the execution mask, so no lane may
+  // leave the loop early; positions past the chunk are masked to zero instead.
+  for (int64_t kw = k_begin + (int64_t)wave * 4 * kMfmaT; kw < k_end; kw += 16 * kMfmaT) {
+    const int64_t k0 = kw + (int64_t)g * kMfmaT;
+    float a[kMfmaT], bv[kMfmaT];
+    // row offsets differ per lane: they go in the VGPR offset (rows beyond the data read 0)
+    const u32x4 wa = __builtin_amdgcn_raw_buffer_load_b128(ra, (uint32_t)e * vecb + (uint32_t)k0 * 4u, 0u, 0);
+    const u32x4 wb = __builtin_amdgcn_raw_buffer_load_b128(rb, (uint32_t)r * vecb + (uint32_t)k0 * 4u, 0u, 0);
+    a[0] = __uint_as_float(wa.x); a[1] = __uint_as_float(wa.y);
+    a[2] = __uint_as_float(wa.z); a[3] = __uint_as_float(wa.w);
+    float x0 = __uint_as_float(wb.x), y0 = __uint_as_float(wb.y);
+    float x1 = __uint_as_float(wb.z), y1 = __uint_as_float(wb.w);
+    if (psi_g5) {  // gamma5: spin components 2, 3 (complex index >= 6 V) change sign
+      if ((k0 >> 1) >= 6 * (int64_t)V) { x0 = -x0; y0 = -y0; }
+      if (((k0 + 2) >> 1) >= 6 * (int64_t)V) { x1 = -x1; y1 = -y1; }
+    }
+    if (imcol) { bv[0] = y0; bv[1] = -x0; bv[2] = y1; bv[3] = -x1; }
+    else { bv[0] = x0; bv[1] = y0; bv[2] = x1; bv[3] = y1; }
+#pragma unroll
+    for (int t = 0; t < kMfmaT; ++t) {
+      const bool in = (k0 + t < k_end) && arow && bcol;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in ? a[t] : 0.f, in ? bv[t] : 0.f, acc, 0, 0, 0);
+    }
+  }
+  // lane holds C[row = 4 g + q][col = i], q = 0..3
+#pragma unroll
+  for (int q = 0; q < 4; ++q) tile[wave][4 * g + q][i] = (double)acc[q];
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    const int row = threadIdx.x >> 4, c = threadIdx.x & 15;
+    const double sum = tile[0][row][c] + tile[1][row][c] + tile[2][row][c] + tile[3][row][c];
+    tile[0][row][c] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x < 128) {
+    const int row = threadIdx.x >> 3, rr = threadIdx.x & 7;
+    const int ee = blockIdx.y * 16 + row, rhs = blockIdx.z * 8 + rr;
+    if (ee < n_ev && rhs < nrhs)
+      partial[((int64_t)blockIdx.x * nrhs + rhs) * n_ev + ee] =
+          make_double2(tile[0][row][2 * rr], tile[0][row][2 * rr + 1]);
   }
 }
 

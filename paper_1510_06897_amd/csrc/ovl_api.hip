@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/ovl.h"
@@ -197,18 +199,82 @@ int check_spinor_call(const ovl_gauge *g, const void *out, const void *in, int n
 
 int grid_blocks(int V) { return (V + kBlock - 1) / kBlock; }
 
-// fused step kernel launch shape: 4 threads per site, SPB sites per workgroup; small lattices
-// get one-wave workgroups so that the sites spread over more compute units
-int step_spb(int V) { return V >= 64 * 1024 ? 64 : 16; }
-int step_blocks(int V) {
-  const int spb = step_spb(V);
-  return (V + spb - 1) / spb;
+// Fused step kernel launch shape: 4 threads per site, SPB sites per workgroup.  Launches that
+// cover fewer than 64K site-right-hand-sides get one-wave workgroups (SPB 16) so that the work
+// spreads over more compute units.
+int launch_spb(int64_t site_rhs) { return site_rhs >= 64 * 1024 ? 64 : 16; }
+int item_blocks(int V, int spb) { return (V + spb - 1) / spb; }
+// workgroups (over all right-hand sides) of a single-problem launch
+int single_blocks(int V, int nrhs) { return item_blocks(V, launch_spb((int64_t)V * nrhs)) * nrhs; }
+
+// t-streaming tile (ty, tz) of the step kernel's workgroup order: the largest candidate whose
+// slice Lx ty tz splits into whole workgroups and holds at most 1.25 MB of links and spinor data
+void step_tile(const Geom &g, int spb, int site_bytes, int &ty, int &tz) {
+  ty = tz = 0;
+  if (spb != 64 || g.V < 64 * 1024) return;
+  static const int cand[][2] = {{8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}};
+  for (const auto &c : cand) {
+    const int64_t slice = (int64_t)g.L[0] * c[0] * c[1];
+    if (g.L[1] % c[0] || g.L[2] % c[1] || slice % spb) continue;
+    if (slice * site_bytes > 1280 * 1024) continue;
+    ty = c[0];
+    tz = c[1];
+    return;
+  }
 }
 
-template <class C, class SE, class LE>
-int launch_step(const StepParams &p, int nrhs, hipStream_t s, bool timed) {
-  const int spb = step_spb(p.g.V);
-  dim3 grid(step_blocks(p.g.V), nrhs);
+// Launch configuration of the fused step kernel: sites per workgroup, t-streaming tile order
+// (where a tile fits) and the XCD-contiguous workgroup remap.  Default rules unless ovl_autotune
+// measured a better one for the lattice, precision and right-hand-side count.
+struct LaunchCfg {
+  int spb, tiles, remap;
+};
+struct TuneKey {
+  int L[4], prec, nrhs;
+  bool operator<(const TuneKey &o) const {
+    return std::lexicographical_compare(L, L + 4, o.L, o.L + 4) ||
+           (std::equal(L, L + 4, o.L) && (prec < o.prec || (prec == o.prec && nrhs < o.nrhs)));
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, LaunchCfg> g_tuned;
+
+LaunchCfg default_cfg(int64_t work) { return LaunchCfg{launch_spb(work), 1, 1}; }
+
+LaunchCfg lookup_cfg(const Geom &g, int prec, int nrhs, int64_t work) {
+  TuneKey k{{g.L[0], g.L[1], g.L[2], g.L[3]}, prec, nrhs};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(k);
+  return it == g_tuned.end() ? default_cfg(work) : it->second;
+}
+
+// workgroup order and first workgroup of every item; returns the launch's workgroup count
+int plan_items(StepItem *items, int n, const LaunchCfg &cfg, int site_bytes) {
+  int total = 0;
+  for (int i = 0; i < n; ++i) {
+    StepItem &it = items[i];
+    it.blk0 = total;
+    it.ty = it.tz = 0;
+    if (cfg.tiles) step_tile(it.g, cfg.spb, site_bytes, it.ty, it.tz);
+    total += item_blocks(it.g.V, cfg.spb) * it.nrhs;
+  }
+  return total;
+}
+
+int site_bytes_of(Prec prec) {
+  return prec == P_F64 ? 36 * 16 + 12 * 16 : prec == P_F32 ? 36 * 8 + 12 * 8 : 36 * 4 + 12 * 8;
+}
+
+int64_t items_work(const StepItem *items, int n) {
+  int64_t w = 0;
+  for (int i = 0; i < n; ++i) w += (int64_t)items[i].g.V * items[i].nrhs;
+  return w;
+}
+
+// launch one step; a single-problem launch plans its item here, a table launch was planned when
+// its table was written (p.total_blocks, spb)
+template <class C, class SE, class LE, bool TABLE>
+int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool timed) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     std::lock_guard<std::mutex> lk(g_timing_mu);
@@ -217,9 +283,9 @@ int launch_step(const StepParams &p, int nrhs, hipStream_t s, bool timed) {
   }
   if (e0 && e1) HIP_TRY(hipEventRecord(e0, s));
   if (spb == 64)
-    step_kernel<C, SE, LE, 64><<<grid, 256, 0, s>>>(p);
+    step_kernel<C, SE, LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
   else
-    step_kernel<C, SE, LE, 16><<<grid, 64, 0, s>>>(p);
+    step_kernel<C, SE, LE, 16, TABLE><<<p.total_blocks, 64, 0, s>>>(p);
   HIP_TRY(hipGetLastError());
   if (e0 && e1) {
     HIP_TRY(hipEventRecord(e1, s));
@@ -229,35 +295,83 @@ int launch_step(const StepParams &p, int nrhs, hipStream_t s, bool timed) {
   return OVL_OK;
 }
 
-int dispatch_step(Prec prec, const StepParams &p, int nrhs, hipStream_t s, bool timed = false) {
+template <bool TABLE>
+int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s, bool timed) {
   switch (prec) {
-    case P_F64: return launch_step<double, double2, double2>(p, nrhs, s, timed);
-    case P_F32: return launch_step<float, float2, float2>(p, nrhs, s, timed);
-    case P_F32_BF16: return launch_step<float, float2, bf16c>(p, nrhs, s, timed);
+    case P_F64: return launch_step<double, double2, double2, TABLE>(p, spb, s, timed);
+    case P_F32: return launch_step<float, float2, float2, TABLE>(p, spb, s, timed);
+    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, spb, s, timed);
     default: return fail(OVL_EDTYPE, "bad precision");
   }
 }
 
-StepParams base_params(const ovl_gauge *g) {
-  StepParams p;
+// single problem: plan its item with the tuned (or default) configuration, then launch
+int dispatch_cfg(Prec prec, StepArgs<false> &p, const LaunchCfg &cfg, hipStream_t s, bool timed) {
+  p.total_blocks = plan_items(&p.item, 1, cfg, site_bytes_of(prec));
+  p.remap = cfg.remap;
+  return dispatch_step(prec, p, cfg.spb, s, timed);
+}
+int dispatch_single(Prec prec, StepArgs<false> &p, hipStream_t s, bool timed = false) {
+  const LaunchCfg cfg = lookup_cfg(p.item.g, prec, p.item.nrhs, items_work(&p.item, 1));
+  return dispatch_cfg(prec, p, cfg, s, timed);
+}
+
+void fill_item(StepItem &it, const ovl_gauge *g, int nrhs) {
+  std::memset(&it, 0, sizeof(it));
+  it.U = g->links;
+  it.g = g->g;
+  it.lstride = g->lstride;
+  it.nrhs = nrhs;
+}
+
+template <bool TABLE>
+void clear_args(StepArgs<TABLE> &p) {
   std::memset(&p, 0, sizeof(p));
-  p.U = g->links;
-  p.g = g->g;
-  p.lstride = g->lstride;
+  p.v_role = ROLE_PSI;
+  p.w_role = ROLE_NONE;
+  p.out_role = ROLE_B0;
+  p.mode = MODE_STEP;
   p.remap = 1;
+}
+
+// a one-problem launch: psi = src, buf = {b0, b1, b2}
+StepArgs<false> single_args(const ovl_gauge *g, int nrhs) {
+  StepArgs<false> p;
+  clear_args(p);
+  fill_item(p.item, g, nrhs);
+  p.n_items = 1;
   return p;
 }
 
-// c[r][i] = phi_i^+ psi_r (FP64), scratch `partial` of n_blocks * nrhs * n_ev double2
-template <class SE>
-int project(const SE *phi, int n_ev, const SE *psi, int psi_g5, int nrhs, int V, double2 *partial,
-            int nblk, double2 *c, hipStream_t s) {
+// c[r][i] = phi_i^+ psi_r (FP64 result), scratch `partial` of n_blocks * nrhs * n_ev double2.
+// FP64 storage: VALU kernel with FP64 products; FP32 storage: FP32 matrix-core kernel.
+int project(const double2 *phi, int n_ev, const double2 *psi, int psi_g5, int nrhs, int V,
+            double2 *partial, int nblk, double2 *c, hipStream_t s) {
   constexpr int CH = 8;
   dim3 grid(nblk, (n_ev + CH - 1) / CH, nrhs);
-  project_partial_kernel<SE, CH><<<grid, kBlock, 0, s>>>(phi, n_ev, psi, psi_g5, V, partial);
+  project_partial_kernel<double2, CH><<<grid, kBlock, 0, s>>>(phi, n_ev, psi, psi_g5, V, partial);
   HIP_TRY(hipGetLastError());
   const int count = nrhs * n_ev;
   project_reduce_kernel<<<(count + 127) / 128, 128, 0, s>>>(partial, nblk, count, c);
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
+
+int project(const float2 *phi, int n_ev, const float2 *psi, int psi_g5, int nrhs, int V,
+            double2 *partial, int nblk, double2 *c, hipStream_t s) {
+  if (!fits_u32(12ull * V * nrhs, OVL_F32))
+    return fail(OVL_EDIMS, "%d right-hand sides of %d sites exceed 4 GiB", nrhs, V);
+  const int64_t K = (int64_t)24 * V;
+  // reals per workgroup: a multiple of 64 (4 waves x 4 lane groups x 4 reals)
+  int64_t chunk = (K + nblk - 1) / nblk;
+  chunk = (chunk + 63) / 64 * 64;
+  const int blocks = (int)((K + chunk - 1) / chunk);
+  dim3 grid(blocks, (n_ev + 15) / 16, (nrhs + 7) / 8);
+  project_mfma_kernel<<<grid, 256, 0, s>>>((const float *)phi, n_ev, (const float *)psi, nrhs,
+                                           psi_g5, V, (int)chunk, partial);
+  HIP_TRY(hipGetLastError());
+  const int count = nrhs * n_ev;
+  project_reduce_kernel<<<(count + 127) / 128, 128, 0, s>>>(partial, blocks, count, c);
   HIP_TRY(hipGetLastError());
   return OVL_OK;
 }
@@ -280,102 +394,154 @@ int defl_weights(ovl_defl *d, const ovl_poly *p, hipStream_t s) {
   return OVL_OK;
 }
 
-// Clenshaw evaluation of sum_m alpha_m T_m(X) in + deflation, final combine by `mode`.
+// One problem of a sign / overlap evaluation.
+struct SignJob {
+  const ovl_gauge *g;
+  ovl_defl *d;  // nullable
+  const void *in;
+  void *out;
+  int nrhs;
+};
+
+constexpr int kMaxBatch = 16;
+
+// Clenshaw evaluation of sum_m alpha_m T_m(X) in + deflation, final combine by `mode`, for up to
+// NI problems that share the polynomial, in one launch per K application.
 // b_k = alpha_k src + 2 X b_{k+1} - b_{k+2}, k = N-1 .. 1 (b_N = alpha_N src and b_{N+1} = 0
 // are folded into the first two steps), result = alpha_0 src + X b_1 - b_2.  b_k lives in
 // `out` for even k and in one scratch vector for odd k; every step updates b_{k+2} in place.
-int run_sign(const ovl_gauge *g, const ovl_poly *p, ovl_defl *d, int mode, double mu, int src_g5,
-             void *out, const void *in, int nrhs, int spin_dt, Prec prec, hipStream_t s) {
+template <bool TABLE>
+int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, double mu, int src_g5,
+                  int spin_dt, Prec prec, hipStream_t s) {
   const int N = (int)p->alpha.size() - 1;
-  const int V = g->g.V;
-  const size_t vec_bytes = (size_t)nrhs * 12 * V * elem_bytes(spin_dt);
-  const int nblk_site = step_blocks(V);
-  const int nblk_proj = project_blocks(V);
-  const int n_ev = d ? d->n_ev : 0;
-  // scratch: [vector][norm partials][projection partials][c]
-  size_t off_vec = 0;
-  size_t off_norm = off_vec + (N >= 2 ? ((vec_bytes + 255) / 256) * 256 : 0);
-  size_t off_part = off_norm + ((sizeof(double) * 2 * nblk_site * nrhs + 255) / 256) * 256;
-  size_t off_c = off_part + ((sizeof(double2) * (size_t)nblk_proj * nrhs * n_ev + 255) / 256) * 256;
-  size_t total = off_c + sizeof(double2) * (size_t)nrhs * n_ev + 256;
-  if (d) {
-    int rc = defl_weights(d, p, s);
-    if (rc) return rc;
+  int64_t work = 0;
+  for (int j = 0; j < nj; ++j) work += (int64_t)jobs[j].g->g.V * jobs[j].nrhs;
+  const LaunchCfg cfg = TABLE ? default_cfg(work) : lookup_cfg(jobs[0].g->g, prec, jobs[0].nrhs, work);
+  const int spb = cfg.spb;
+  // scratch: [item table] then per job [vector][norm partials][projection partials][c]
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  size_t off[kMaxBatch][4];
+  size_t total = TABLE ? up(sizeof(StepItem) * nj) : 0;
+  for (int j = 0; j < nj; ++j) {
+    const int V = jobs[j].g->g.V, nrhs = jobs[j].nrhs;
+    const int n_ev = jobs[j].d ? jobs[j].d->n_ev : 0;
+    off[j][0] = total;
+    total += N >= 2 ? up((size_t)nrhs * 12 * V * elem_bytes(spin_dt)) : 0;
+    off[j][1] = total;
+    total += up(sizeof(double) * 2 * (size_t)item_blocks(V, spb) * nrhs);
+    off[j][2] = total;
+    total += up(sizeof(double2) * (size_t)project_blocks(V) * nrhs * n_ev);
+    off[j][3] = total;
+    total += up(sizeof(double2) * (size_t)nrhs * n_ev);
   }
+  for (int j = 0; j < nj; ++j)
+    if (jobs[j].d) {
+      int rc = defl_weights(jobs[j].d, p, s);
+      if (rc) return rc;
+    }
   Scratch sc;
   int rc = scratch_alloc(sc, total, s);
   if (rc) return rc;
   char *base = (char *)sc.p;
-  void *ws = base + off_vec;
-  double *norm_partial = (double *)(base + off_norm);
-  double2 *partial = (double2 *)(base + off_part);
-  double2 *cvec = (double2 *)(base + off_c);
 
-  if (d) {
-    if (prec == P_F64)
-      rc = project((const double2 *)d->phi_store, n_ev, (const double2 *)in, src_g5, nrhs, V,
-                   partial, nblk_proj, cvec, s);
-    else
-      rc = project((const float2 *)d->phi_store, n_ev, (const float2 *)in, src_g5, nrhs, V,
-                   partial, nblk_proj, cvec, s);
-    if (rc) return rc;
+  StepItem items[kMaxBatch];
+  for (int j = 0; j < nj; ++j) {
+    const SignJob &J = jobs[j];
+    StepItem &it = items[j];
+    fill_item(it, J.g, J.nrhs);
+    it.psi = J.in;
+    it.buf[0] = J.out;
+    it.buf[1] = base + off[j][0];
+    it.norm_partial = (double *)(base + off[j][1]);
+    if (J.d) {
+      const int V = J.g->g.V;
+      double2 *partial = (double2 *)(base + off[j][2]);
+      double2 *cvec = (double2 *)(base + off[j][3]);
+      if (prec == P_F64)
+        rc = project((const double2 *)J.d->phi_store, J.d->n_ev, (const double2 *)J.in, src_g5,
+                     J.nrhs, V, partial, project_blocks(V), cvec, s);
+      else
+        rc = project((const float2 *)J.d->phi_store, J.d->n_ev, (const float2 *)J.in, src_g5,
+                     J.nrhs, V, partial, project_blocks(V), cvec, s);
+      if (rc) return rc;
+      it.phi = J.d->phi_store;
+      it.n_ev = J.d->n_ev;
+      it.c = cvec;
+      it.wdefl = J.d->w_dev;
+    }
+  }
+  StepArgs<TABLE> args;
+  clear_args(args);
+  args.n_items = nj;
+  args.total_blocks = plan_items(items, nj, cfg, site_bytes_of(prec));
+  args.remap = cfg.remap;
+  if (TABLE) {
+    StepItem *table = (StepItem *)base;
+    for (int j = 0; j < nj; ++j) {
+      write_item_kernel<<<1, 64, 0, s>>>(items[j], table + j);
+      HIP_TRY(hipGetLastError());
+    }
+    args.table = table;
+  } else {
+    args.item = items[0];
   }
 
-  auto buf = [&](int k) -> void * { return (k % 2 == 0) ? out : ws; };
-  const double* al = p->alpha.data();
+  auto role = [](int k) { return (k % 2 == 0) ? ROLE_B0 : ROLE_B1; };
+  const double *al = p->alpha.data();
   const double kdiag = 4.0 - p->m_W;
   const bool timed = g_timing.load() != 0;
   for (int k = N - 1; k >= 0; --k) {
-    StepParams sp = base_params(g);
     double sfac = (k == 0) ? 1.0 : 2.0;
     double a = al[k];
     if (k + 1 == N) {
-      sp.v = in;
-      sp.v_g5 = src_g5;
+      args.v_role = ROLE_PSI;
+      args.v_g5 = src_g5;
       sfac *= al[N];
     } else {
-      sp.v = buf(k + 1);
-      sp.v_g5 = 0;
+      args.v_role = role(k + 1);
+      args.v_g5 = 0;
     }
+    args.t = 0.0;
     if (k + 2 == N + 1) {
-      sp.w = nullptr;
+      args.w_role = ROLE_NONE;
     } else if (k + 2 == N) {
-      sp.w = nullptr;
+      args.w_role = ROLE_NONE;
       a -= al[N];
     } else {
-      sp.w = buf(k + 2);
-      sp.t = -1.0;
+      args.w_role = role(k + 2);
+      args.t = -1.0;
     }
-    sp.src = in;
-    sp.src_g5 = src_g5;
-    sp.a = a;
-    sp.y_g5 = 1;
-    sp.kd = sfac * kdiag / p->lmax;
-    sp.kh = -0.5 * sfac / p->lmax;
-    sp.out = (k == 0) ? out : buf(k);
-    if (k == 0) {
-      sp.mode = mode;
-      sp.mu = mu;
-      sp.phi = d ? d->phi_store : nullptr;
-      sp.n_ev = n_ev;
-      sp.c = cvec;
-      sp.wdefl = d ? d->w_dev : nullptr;
-      sp.norm_partial = norm_partial;
-    } else {
-      sp.mode = MODE_STEP;
-    }
-    rc = dispatch_step(prec, sp, nrhs, s, timed && k > 0);
+    args.src_g5 = src_g5;
+    args.a = a;
+    args.y_g5 = 1;
+    args.kd = sfac * kdiag / p->lmax;
+    args.kh = -0.5 * sfac / p->lmax;
+    args.out_role = role(k);
+    args.mode = (k == 0) ? mode : MODE_STEP;
+    args.mu = mu;
+    rc = dispatch_step(prec, args, spb, s, timed && k > 0);
     if (rc) return rc;
   }
-  const double bound = p->bound + (d ? [&] {
-    double m = 0.0;
-    for (double w : d->w_host) m = std::max(m, std::fabs(w));
-    return m;
-  }() : 0.0);
-  norm_check_kernel<<<(nrhs + 255) / 256, 256, 0, s>>>(norm_partial, nblk_site, nrhs,
-                                                      bound * bound, g->flags, nullptr);
-  HIP_TRY(hipGetLastError());
+  for (int j = 0; j < nj; ++j) {
+    const SignJob &J = jobs[j];
+    double bound = p->bound;
+    if (J.d) {
+      double m = 0.0;
+      for (double w : J.d->w_host) m = std::max(m, std::fabs(w));
+      bound += m;
+    }
+    norm_check_kernel<<<(J.nrhs + 255) / 256, 256, 0, s>>>(
+        items[j].norm_partial, item_blocks(J.g->g.V, spb), J.nrhs, bound * bound, J.g->flags,
+        nullptr);
+    HIP_TRY(hipGetLastError());
+  }
   return OVL_OK;
+}
+
+int run_sign(const ovl_gauge *g, const ovl_poly *p, ovl_defl *d, int mode, double mu, int src_g5,
+             void *out, const void *in, int nrhs, int spin_dt, Prec prec, hipStream_t s) {
+  SignJob j{g, d, in, out, nrhs};
+  return run_sign_jobs<false>(&j, 1, p, mode, mu, src_g5, spin_dt, prec, s);
 }
 
 int check_poly(const ovl_poly *p) {
@@ -542,6 +708,8 @@ int ovl_defl_create(ovl_defl **out, const int32_t dims[4], const void *phi_dev, 
     if (!std::isfinite(lambda[i])) return fail(OVL_ENONFINITE, "lambda[%d] is not finite", i);
   if (!fits_u32(12ull * geo.V, OVL_F64))
     return fail(OVL_EDIMS, "one eigenvector of %d sites exceeds 4 GiB in FP64", geo.V);
+  if (store_dt == OVL_F32 && !fits_u32(12ull * geo.V * n_ev, OVL_F32))
+    return fail(OVL_EDIMS, "an FP32 basis of %d vectors of %d sites exceeds 4 GiB", n_ev, geo.V);
   hipStream_t s = as_stream(stream);
   ovl_defl *d = new (std::nothrow) ovl_defl();
   if (!d) return fail(OVL_ENOMEM, "host allocation failed");
@@ -589,17 +757,17 @@ int ovl_defl_create(ovl_defl **out, const int32_t dims[4], const void *phi_dev, 
   const unsigned vblocks = (unsigned)((nv + 255) / 256);
   for (int j = 0; j < n_ev && rc == OVL_OK; ++j) {
     double2 *v = d->phi64 + (int64_t)j * nv;
-    rc = project<double2>(v, 1, v, 0, 1, V, partial, nblk, cbuf, s);
+    rc = project(v, 1, v, 0, 1, V, partial, nblk, cbuf, s);
     if (rc) break;
     record_kernel<<<1, 64, 0, s>>>(cbuf, norms, 2 * j);
     for (int pass = 0; pass < 2 && j > 0 && rc == OVL_OK; ++pass) {
-      rc = project<double2>(d->phi64, j, v, 0, 1, V, partial, nblk, cbuf, s);
+      rc = project(d->phi64, j, v, 0, 1, V, partial, nblk, cbuf, s);
       if (rc) break;
       correct_kernel<double, double2><<<dim3(grid_blocks(V), 1), kBlock, 0, s>>>(
           v, d->phi64, j, cbuf, nullptr, -1.0, V);
     }
     if (rc) break;
-    rc = project<double2>(v, 1, v, 0, 1, V, partial, nblk, cbuf, s);
+    rc = project(v, 1, v, 0, 1, V, partial, nblk, cbuf, s);
     if (rc) break;
     normalize_kernel<<<vblocks, 256, 0, s>>>(v, cbuf, nv, norms, 2 * j + 1);
   }
@@ -654,15 +822,16 @@ int ovl_wilson_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, in
   int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
   if (rc) return rc;
   if (!std::isfinite(m_W)) return fail(OVL_ENONFINITE, "m_W is not finite");
-  StepParams p = base_params(g);
-  p.v = in;
+  StepArgs<false> p = single_args(g, nrhs);
+  p.item.psi = in;
+  p.item.buf[0] = out;
+  p.v_role = ROLE_PSI;
+  p.out_role = ROLE_B0;
   p.v_g5 = dagger ? 1 : 0;
   p.y_g5 = dagger ? 1 : 0;
   p.kd = 4.0 - m_W;
   p.kh = -0.5;
-  p.out = out;
-  p.mode = MODE_STEP;
-  return dispatch_step(prec, p, nrhs, as_stream(stream));
+  return dispatch_single(prec, p, as_stream(stream));
 }
 
 int ovl_kernel_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, int spin_dt,
@@ -672,14 +841,15 @@ int ovl_kernel_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, in
   int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
   if (rc) return rc;
   if (!std::isfinite(m_W)) return fail(OVL_ENONFINITE, "m_W is not finite");
-  StepParams p = base_params(g);
-  p.v = in;
+  StepArgs<false> p = single_args(g, nrhs);
+  p.item.psi = in;
+  p.item.buf[0] = out;
+  p.v_role = ROLE_PSI;
+  p.out_role = ROLE_B0;
   p.y_g5 = 1;
   p.kd = 4.0 - m_W;
   p.kh = -0.5;
-  p.out = out;
-  p.mode = MODE_STEP;
-  return dispatch_step(prec, p, nrhs, as_stream(stream));
+  return dispatch_single(prec, p, as_stream(stream));
 }
 
 int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, void *out,
@@ -704,6 +874,41 @@ int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
   // D^+ psi = 1/2 ((1 + mu) psi + (1 - mu) sign(K) gamma5 psi)
   return run_sign(g, p, const_cast<ovl_defl *>(d), dagger ? MODE_OVERLAP_DAG : MODE_OVERLAP, mu,
                   dagger ? 1 : 0, out, in, nrhs, spin_dt, prec, as_stream(stream));
+}
+
+int ovl_batch_sign_apply(const ovl_batch_item *items, int n_items, const ovl_poly *p,
+                         int spin_dt, void *stream) {
+  g_err[0] = 0;
+  if (!items) return fail(OVL_EINVAL, "items is NULL");
+  if (n_items < 1 || n_items > kMaxBatch)
+    return fail(OVL_EINVAL, "n_items = %d out of range [1, %d]", n_items, kMaxBatch);
+  int rc = check_poly(p);
+  if (rc) return rc;
+  SignJob jobs[kMaxBatch];
+  Prec prec0 = P_BAD;
+  for (int i = 0; i < n_items; ++i) {
+    Prec prec;
+    rc = check_spinor_call(items[i].g, items[i].out, items[i].in, items[i].nrhs, spin_dt, prec);
+    if (rc) return fail(rc, "item %d: %s", i, std::string(g_err).c_str());
+    if (i > 0 && prec != prec0)
+      return fail(OVL_EDTYPE, "item %d: link storage differs from item 0", i);
+    prec0 = prec;
+    jobs[i] = SignJob{items[i].g, nullptr, items[i].in, items[i].out, items[i].nrhs};
+  }
+  // outputs are written while other items' inputs are still read
+  for (int i = 0; i < n_items; ++i)
+    for (int j = 0; j < n_items; ++j) {
+      const size_t bi = (size_t)items[i].nrhs * 12 * items[i].g->g.V * elem_bytes(spin_dt);
+      const size_t bj = (size_t)items[j].nrhs * 12 * items[j].g->g.V * elem_bytes(spin_dt);
+      const char *o = (const char *)items[i].out, *x = (const char *)items[j].in;
+      const char *oj = (const char *)items[j].out;
+      if (o < x + bj && x < o + bi)
+        return fail(OVL_EALIAS, "output of item %d overlaps the input of item %d", i, j);
+      if (i != j && o < oj + bj && oj < o + bi)
+        return fail(OVL_EALIAS, "outputs of items %d and %d overlap", i, j);
+    }
+  return run_sign_jobs<true>(jobs, n_items, p, MODE_SIGN, 0.0, 0, spin_dt, prec0,
+                                  as_stream(stream));
 }
 
 int ovl_defl_project(const ovl_defl *d, double *c_dev, const void *in, int nrhs, int spin_dt,
@@ -841,18 +1046,20 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
   // X applied: out = sx * X v + a * src + t * w
   auto xstep = [&](void *out, const void *v, double sx, const void *src, double a, const void *w,
                    double t) -> int {
-    StepParams sp = base_params(g);
-    sp.v = v;
+    StepArgs<false> sp = single_args(g, 1);
+    sp.item.psi = src;
+    sp.item.buf[0] = const_cast<void *>(v);
+    sp.item.buf[1] = const_cast<void *>(w);
+    sp.item.buf[2] = out;
+    sp.v_role = ROLE_B0;
+    sp.w_role = w ? ROLE_B1 : ROLE_NONE;
+    sp.out_role = ROLE_B2;
     sp.y_g5 = 1;
     sp.kd = sx * kdiag / p->lmax;
     sp.kh = -0.5 * sx / p->lmax;
-    sp.src = src;
     sp.a = src ? a : 0.0;
-    sp.w = w;
     sp.t = t;
-    sp.out = out;
-    sp.mode = MODE_STEP;
-    return dispatch_step(prec, sp, 1, s);
+    return dispatch_single(prec, sp, s);
   };
   // forward sweep: t_0 = psi, t_1 = X psi, t_{m+1} = 2 X t_m - t_{m-1}, keeping the checkpoint
   // vectors; the others rotate through seg(0), seg(1) (never the buffer read as stencil input)
@@ -906,6 +1113,106 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
     }
   }
   (void)k;
+  return OVL_OK;
+}
+
+int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_path,
+                 double *best_us, void *stream) {
+  g_err[0] = 0;
+  if (!g) return fail(OVL_EINVAL, "gauge handle is NULL");
+  if (nrhs < 1 || nrhs > 65535) return fail(OVL_EINVAL, "nrhs = %d out of range", nrhs);
+  if (spin_dt != OVL_F64 && spin_dt != OVL_F32) return fail(OVL_EDTYPE, "spinor dtype %d", spin_dt);
+  const Prec prec = precision(spin_dt, g->store_dt);
+  if (prec == P_BAD) return fail(OVL_EDTYPE, "spinor dtype %d with link storage %d", spin_dt, g->store_dt);
+  if (!fits_u32(12ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "lattice too large");
+  hipStream_t s = as_stream(stream);
+  const size_t vec = (size_t)nrhs * 12 * g->g.V * elem_bytes(spin_dt);
+  const size_t vecp = (vec + 255) / 256 * 256;
+  Scratch sc;
+  int rc = scratch_alloc(sc, 2 * vecp, s);
+  if (rc) return rc;
+  HIP_TRY(hipMemsetAsync(sc.p, 0, 2 * vecp, s));
+  StepArgs<false> args = single_args(g, nrhs);
+  args.item.psi = sc.p;
+  args.item.buf[0] = (char *)sc.p + vecp;
+  args.y_g5 = 1;
+  args.kd = 2.5;
+  args.kh = -0.5;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  LaunchCfg best{0, 0, 0};
+  float best_ms = 1e30f;
+  const int sb = site_bytes_of(prec);
+  for (int spb : {64, 16})
+    for (int tiles : {1, 0})
+      for (int remap : {1, 0}) {
+        const LaunchCfg cfg{spb, tiles, remap};
+        if (tiles) {
+          int ty, tz;
+          step_tile(g->g, spb, sb, ty, tz);
+          if (ty == 0) continue;
+        }
+        for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s, false);
+        if (rc == OVL_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
+        for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s, false);
+        if (rc == OVL_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
+        float ms = 0.f;
+        if (rc == OVL_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = fail(OVL_EHIP, "event timing");
+        if (rc) break;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cfg;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[TuneKey{{g->g.L[0], g->g.L[1], g->g.L[2], g->g.L[3]}, (int)prec, nrhs}] = best;
+  }
+  if (best_us) *best_us = 1e3 * best_ms / 10.0;
+  if (cache_path) {
+    FILE *f = std::fopen(cache_path, "a");
+    if (!f) return fail(OVL_EINVAL, "cannot open tuning cache %s", cache_path);
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.3f\n", g->g.L[0], g->g.L[1], g->g.L[2],
+                 g->g.L[3], (int)prec, nrhs, best.spb, best.tiles, best.remap,
+                 1e3 * best_ms / 10.0);
+    std::fclose(f);
+  }
+  return OVL_OK;
+}
+
+int ovl_autotune_load(const char *cache_path) {
+  g_err[0] = 0;
+  if (!cache_path) return fail(OVL_EINVAL, "NULL path");
+  FILE *f = std::fopen(cache_path, "r");
+  if (!f) return fail(OVL_EINVAL, "cannot open tuning cache %s", cache_path);
+  int L[4], prec, nrhs, spb, tiles, remap;
+  double us;
+  int n = 0;
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &L[0], &L[1], &L[2], &L[3], &prec,
+                     &nrhs, &spb, &tiles, &remap, &us) == 10) {
+    if ((spb != 16 && spb != 64) || prec < 0 || prec > 2 || nrhs < 1) continue;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[TuneKey{{L[0], L[1], L[2], L[3]}, prec, nrhs}] = LaunchCfg{spb, tiles != 0, remap != 0};
+    ++n;
+  }
+  std::fclose(f);
+  return n;
+}
+
+int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]) {
+  if (!g || !cfg_out) return fail(OVL_EINVAL, "NULL argument");
+  const Prec prec = precision(spin_dt, g->store_dt);
+  if (prec == P_BAD) return fail(OVL_EDTYPE, "spinor dtype %d with link storage %d", spin_dt, g->store_dt);
+  const LaunchCfg c = lookup_cfg(g->g, prec, nrhs, (int64_t)g->g.V * nrhs);
+  cfg_out[0] = c.spb;
+  cfg_out[1] = c.tiles;
+  cfg_out[2] = c.remap;
   return OVL_OK;
 }
 

@@ -99,14 +99,51 @@ __device__ __forceinline__ void quad_hop(cx<C> acc[12], rsrc_t v, uint32_t cs, r
   }
 }
 
-// per-lane neighbour sites along mu (periodic)
-__device__ __forceinline__ void lane_neighbours(const Geom &g, int site, int mu, int &fwd, int &bwd) {
-  const int st = mu == 0 ? g.stride[0] : mu == 1 ? g.stride[1] : mu == 2 ? g.stride[2] : g.stride[3];
-  const int L = mu == 0 ? g.L[0] : mu == 1 ? g.L[1] : mu == 2 ? g.L[2] : g.L[3];
-  const int c = (site / st) % L;
+// Extents, strides and coordinates as named scalars.  The direction-split kernel selects one of
+// four values per thread; with arrays the compiler turns those selects into dynamically indexed
+// private memory, so everything here is plain scalars.
+struct Ext4 {
+  int lx, ly, lz, lt;  // extents
+  int sy, sz, st;      // strides of y, z, t in the site index (x has stride 1)
+  int V;
+};
+struct Coord4 {
+  int x, y, z, t;
+};
+
+__device__ __forceinline__ Ext4 ext_of(const Geom &g) {
+  Ext4 e;
+  e.lx = g.L[0];
+  e.ly = g.L[1];
+  e.lz = g.L[2];
+  e.lt = g.L[3];
+  e.sy = g.stride[1];
+  e.sz = g.stride[2];
+  e.st = g.stride[3];
+  e.V = g.V;
+  return e;
+}
+
+__device__ __forceinline__ Coord4 coords_of(const Ext4 &e, int s) {
+  Coord4 c;
+  c.x = s % e.lx;
+  int r = s / e.lx;
+  c.y = r % e.ly;
+  r /= e.ly;
+  c.z = r % e.lz;
+  c.t = r / e.lz;
+  return c;
+}
+
+// neighbour sites of `site` along mu (periodic)
+__device__ __forceinline__ void dir_neighbours(const Ext4 &e, const Coord4 &c, int site, int mu,
+                                               int &fwd, int &bwd) {
+  const int st = mu == 0 ? 1 : mu == 1 ? e.sy : mu == 2 ? e.sz : e.st;
+  const int L = mu == 0 ? e.lx : mu == 1 ? e.ly : mu == 2 ? e.lz : e.lt;
+  const int x = mu == 0 ? c.x : mu == 1 ? c.y : mu == 2 ? c.z : c.t;
   const int wrap = (L - 1) * st;
-  fwd = (c + 1 == L) ? site - wrap : site + st;
-  bwd = (c == 0) ? site + wrap : site - st;
+  fwd = (x + 1 == L) ? site - wrap : site + st;
+  bwd = (x == 0) ? site + wrap : site - st;
 }
 
 }  // namespace ovl

@@ -128,3 +128,11 @@ def test_python_binding_raises_with_status(lib):
     with pytest.raises(OvlError) as e:
         cheb_sign_coeffs(10, 2.0)
     assert e.value.status == "OVL_EINVAL"
+
+
+def test_autotune_cache_file(lib, tmp_path):
+    missing = str(tmp_path / "none.txt").encode()
+    assert lib.ovl_autotune_load(missing) == -1
+    f = tmp_path / "tune.txt"
+    f.write_text("16 16 16 32 1 1 64 1 1 17.5\n8 8 8 16 0 1 16 0 1 9.0\nbad line\n")
+    assert lib.ovl_autotune_load(str(f).encode()) == 2

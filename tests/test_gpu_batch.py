@@ -1,0 +1,86 @@
+"""Batched form: several lattice problems (own gauge fields, volumes and right-hand-side counts)
+evaluated with one polynomial in one launch per K application (Sec. 2, eq. 3 without deflation)."""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import chebyshev as och
+from tests.conftest import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+LMAX = 6.5
+
+
+@pytest.fixture(scope="module")
+def ovl():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1510_06897_amd as m
+    m.load()
+    return m
+
+
+def dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+def test_batch_mixed_volumes_vs_oracle(ovl, store):
+    shapes = [((4, 4, 4, 4), 3), ((2, 3, 4, 5), 1), ((6, 4, 2, 4), 2), ((8, 8, 8, 16), 1)]
+    alpha = och.coeffs_sign_interp(31, 0.08)
+    p = ovl.Polynomial(alpha, LMAX)
+    cdt = torch.complex128 if store == "f64" else torch.complex64
+    probs, refs = [], []
+    for i, (dims, nrhs) in enumerate(shapes):
+        u = latgen.smeared_field(dims, 10400 + i, steps=1)
+        psi = latgen.gaussian_spinor(dims, 20400 + i, nrhs=nrhs)
+        u_in = u if store == "f64" else (latgen.round_to_f32(u) if store == "f32"
+                                         else latgen.round_to_bf16(u))
+        psi_in = psi if store == "f64" else latgen.round_to_f32(psi)
+        probs.append((ovl.GaugeField(dev(u), store), dev(psi, cdt)))
+        refs.append([och.poly_apply(u_in, psi_in[r], alpha, LMAX) for r in range(nrhs)])
+    outs = ovl.batch_sign_apply(p, probs)
+    torch.cuda.synchronize()
+    tol = 1e-12 if store == "f64" else 1e-6
+    for (g, _), out, ref in zip(probs, outs, refs):
+        got = out.cpu().to(torch.complex128).numpy()
+        for r in range(len(ref)):
+            assert rel_err(got[r], ref[r]) < tol
+        assert g.flags() == 0
+
+
+def test_batch_equals_single_launches_c4_shapes(ovl):
+    """Full-size mixed-volume batch (12 point sources on 16^3x32, 4 x 8^3x16, 2 x 12^3x24) gives
+    bitwise the results of the one-problem path (whose parity is pinned at smaller sizes)."""
+    alpha = och.coeffs_sign_interp(300, 0.05)
+    p = ovl.Polynomial(alpha, LMAX)
+    probs = []
+    dims0 = (16, 16, 16, 32)
+    u0 = latgen.random_su3_field(dims0, 10400)
+    src = np.stack([latgen.point_source(dims0, s, c) for s in range(4) for c in range(3)])
+    probs.append((ovl.GaugeField(dev(u0), "f32"), dev(src, torch.complex64)))
+    for i, dims in enumerate([(8, 8, 8, 16)] * 4 + [(12, 12, 12, 24)] * 2):
+        u = latgen.random_su3_field(dims, 10401 + i)
+        psi = latgen.gaussian_spinor(dims, 20401 + i, nrhs=1)
+        probs.append((ovl.GaugeField(dev(u), "f32"), dev(psi, torch.complex64)))
+    outs = ovl.batch_sign_apply(p, probs)
+    for (g, psi), out in zip(probs, outs):
+        single = ovl.sign_apply(g, p, psi)
+        torch.cuda.synchronize()
+        assert torch.equal(single, out)
+        assert g.flags() == 0
+
+
+def test_batch_validation(ovl):
+    dims = (2, 2, 2, 2)
+    g = ovl.GaugeField(dev(latgen.random_su3_field(dims, 1)), "f64")
+    x = dev(latgen.gaussian_spinor(dims, 2))
+    p = ovl.Polynomial(och.coeffs_sign_interp(7, 0.1), LMAX)
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.batch_sign_apply(p, [(g, x)], outs=[x])
+    assert e.value.status == "OVL_EALIAS"
+    g32 = ovl.GaugeField(dev(latgen.random_su3_field(dims, 1)), "f32")
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.batch_sign_apply(p, [(g, x), (g32, x)])
+    assert e.value.status == "OVL_EDTYPE"

@@ -67,6 +67,18 @@ def test_wilson_kernel_fp64(ovl, dims, nrhs):
         assert max_rel(got_k[r], ow.kop(u, psi[r])) < 1e-14
 
 
+@pytest.mark.parametrize("dims", [(20, 12, 12, 24), (24, 6, 10, 48), (16, 16, 16, 16)])
+def test_kernel_large_orders(ovl, dims):
+    """Lattices above 64K sites: the t-streaming tile order (Lx x 4 x 4, Lx x 8 x 8) and the
+    memory-order fallback when no tile divides the extents, FP64, two right-hand sides."""
+    u = latgen.random_su3_field(dims, 10150, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20150, nrhs=2)
+    g = ovl.GaugeField(dev(u), "f64")
+    got = host(ovl.kernel_apply(g, dev(psi)))
+    for r in range(2):
+        assert max_rel(got[r], ow.kop(u, psi[r])) < 1e-14
+
+
 @pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 2, 4), (8, 8, 8, 16)])
 @pytest.mark.parametrize("store", ["f32", "bf16"])
 def test_kernel_mixed(ovl, dims, store):
@@ -220,6 +232,35 @@ def test_defl_project_correct(ovl, store):
     for r in range(3):
         ref = odefl.correct(phi_in, psi_in[r], c_ref[r], w)
         assert max_rel(out[r], ref) < tol
+
+
+def test_defl_project_mfma_tiles(ovl):
+    """FP32 projection on the matrix cores: more than 16 eigenvectors and 8 right-hand sides
+    (several MFMA tiles), a volume that leaves ragged chunks, FP64 oracle on the rounded data."""
+    dims = (5, 3, 4, 6)
+    phi, lam = random_basis(dims, 20, 55)
+    psi = latgen.gaussian_spinor(dims, 56, nrhs=10)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    c = host(ovl.defl_project(d, dev(psi, torch.complex64)))
+    phi_r, psi_r = latgen.round_to_f32(phi), latgen.round_to_f32(psi)
+    for r in range(10):
+        ref = odefl.project(phi_r, psi_r[r])
+        assert max_rel(c[r], ref) < 1e-6
+
+
+def test_overlap_dagger_deflated_fp32(ovl):
+    """gamma5 applied to the source inside the FP32 matrix-core projection (the adjoint)."""
+    dims = (4, 4, 2, 4)
+    u = latgen.smeared_field(dims, 34)
+    psi = latgen.gaussian_spinor(dims, 35)
+    phi, lam = random_basis(dims, 5, 36)
+    alpha = och.coeffs_sign_interp(41, 0.08)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    o = host(ovl.overlap_apply(g, p, dev(psi, torch.complex64), 0.05, defl=d, dagger=True))
+    ref = oov.overlap_dagger_apply(u, psi, 0.05, alpha, LMAX, phi, lam)
+    assert rel_err(o, ref) < 1e-6
 
 
 def test_defl_rank_deficient(ovl):
