@@ -459,66 +459,71 @@ __global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst
 }
 
 // ---------------------------------------------------------------------------------------------
-// Link vector-Jacobian product of the hopping term.  For L = Re<a, D_W t> (a read with gamma5
-// when a_g5), with h^-(f) = projection of (1 - gamma_mu) f and h^+(f) of (1 + gamma_mu) f:
-//   G_mu(x)_ij (+)= coef * (-1/2) sum_{k<2} [ h^-(a(x))_{k,i} conj(h^-(t(x+mu))_{k,j})
-//                                           + h^+(t(x))_{k,i} conj(h^+(a(x+mu))_{k,j}) ]
+// Link vector-Jacobian products of the hopping term, summed over a segment of vector pairs.
+// For L = Re<a, D_W t> (a read with gamma5 when a_g5), with h^-(f) the half-spinor of
+// (1 - gamma_mu) f and h^+(f) of (1 + gamma_mu) f:
+//   G_mu(x)_ij (+)= -1/2 sum_pairs coef sum_{k<2} [ h^-(a(x))_{k,i} conj(h^-(t(x+mu))_{k,j})
+//                                                 + h^+(t(x))_{k,i} conj(h^+(a(x+mu))_{k,j}) ]
 // ((1 -+ gamma_mu)/2 are Hermitian projectors, so the 4-spin sums reduce to half-spinor sums.)
-template <int MU, class C, class SE, class GE>
-__device__ __forceinline__ void vjp_dir(rsrc_t G, uint32_t gs, rsrc_t a, rsrc_t t, uint32_t cs,
-                                        uint32_t site, uint32_t fwd, bool a_g5,
-                                        const cx<C> ax_u[2][3], const cx<C> ax_d[2][3],
-                                        const cx<C> tx_u[2][3], const cx<C> tx_d[2][3], C coef,
-                                        bool accumulate) {
-  cx<C> u[2][3], d[2][3];
-  cx<C> hma[2][3], hmt[2][3], hpt[2][3], hpa[2][3];
-  project<MU, true>(ax_u, ax_d, hma);
-  project<MU, false>(tx_u, tx_d, hpt);
-  load_spinor<C, SE>(t, cs, fwd, false, u, d);
-  project<MU, true>(u, d, hmt);
-  load_spinor<C, SE>(a, cs, fwd, a_g5, u, d);
-  project<MU, false>(u, d, hpa);
-  const uint32_t gbase = (uint32_t)MU * 9u * gs;
+// Pair i uses a_i = a0 + i * a_step and t_i = t0 + i * t_step (elements), coef = coef_first for
+// i = 0 and coef_rest otherwise.  Thread (site, mu) owns link G_mu(x): it accumulates the whole
+// segment in registers and reads and writes G once (gather only, no atomics).
+template <class C, class SE, class GE>
+__global__ void __launch_bounds__(256)
+    link_vjp_kernel(GE *G, const SE *a0, int64_t a_step, const SE *t0, int64_t t_step, int len,
+                    double coef_first, double coef_rest, Geom geo, int a_g5, int accumulate) {
+  const int mu = threadIdx.x >> 6, sl = threadIdx.x & 63;
+  const int site = blockIdx.x * 64 + sl;
+  const Ext4 ex = ext_of(geo);
+  if (site >= ex.V) return;
+  const Coord4 c4 = coords_of(ex, site);
+  int fwd, bwd;
+  dir_neighbours(ex, c4, site, mu, fwd, bwd);
+  const DirCoef<C> k = dir_coef<C>(mu);
+  const uint32_t cs = (uint32_t)ex.V * elem_traits<SE>::bytes;
+  cx<C> acc[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[i][j] = mk<C>(0, 0);
+  for (int pi = 0; pi < len; ++pi) {
+    const rsrc_t ra = make_rsrc(a0 + pi * a_step, 12u * cs);
+    const rsrc_t rt = make_rsrc(t0 + pi * t_step, 12u * cs);
+    cx<C> u[2][3], d[2][3], hma[2][3], hmt[2][3], hpt[2][3], hpa[2][3];
+    load_spinor<C, SE>(ra, cs, site, a_g5 != 0, u, d);
+    dir_project(u, d, k, C(1), hma);
+    load_spinor<C, SE>(rt, cs, fwd, false, u, d);
+    dir_project(u, d, k, C(1), hmt);
+    load_spinor<C, SE>(rt, cs, site, false, u, d);
+    dir_project(u, d, k, C(-1), hpt);
+    load_spinor<C, SE>(ra, cs, fwd, a_g5 != 0, u, d);
+    dir_project(u, d, k, C(-1), hpa);
+    const C cf = C(pi == 0 ? coef_first : coef_rest);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        cx<C> s = mk<C>(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+          s = cjmadd(s, hmt[kk][j], hma[kk][i]);
+          s = cjmadd(s, hpa[kk][j], hpt[kk][i]);
+        }
+        acc[i][j] = acc[i][j] + scale(s, cf);
+      }
+  }
+  const uint32_t gs = (uint32_t)ex.V * elem_traits<GE>::bytes;
+  const rsrc_t rg = make_rsrc(G, 36u * gs);
+  const C half = C(-0.5);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      cx<C> s = mk<C>(0, 0);
-#pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        s = cjmadd(s, hmt[k][j], hma[k][i]);
-        s = cjmadd(s, hpa[k][j], hpt[k][i]);
-      }
-      s = scale(s, coef);
-      const uint32_t so = gbase + (i * 3 + j) * gs;
-      if (accumulate) s = s + bld<C, GE>(G, so, site);
-      bst<C, GE>(G, so, site, s);
+      const uint32_t so = ((uint32_t)mu * 9u + (uint32_t)(i * 3 + j)) * gs;
+      cx<C> v = scale(acc[i][j], half);
+      if (accumulate) v = v + bld<C, GE>(rg, so, site);
+      bst<C, GE>(rg, so, site, v);
     }
-}
-
-// G has the layout [4][3][3][V] (36 V elements of GE, < 4 GiB); a and t are single spinors
-template <class C, class SE, class GE>
-__global__ void __launch_bounds__(kBlock)
-    link_vjp_kernel(GE *G, const SE *a, const SE *t, Geom g, double coef, int a_g5,
-                    int accumulate, int remap) {
-  const int b = xcd_block(blockIdx.x, gridDim.x, remap);
-  const int site = b * kBlock + threadIdx.x;
-  if (site >= g.V) return;
-  int fwd[4], bwd[4];
-  neighbours(g, site, fwd, bwd);
-  const uint32_t cs = (uint32_t)g.V * elem_traits<SE>::bytes;
-  const uint32_t gs = (uint32_t)g.V * elem_traits<GE>::bytes;
-  const rsrc_t ra = make_rsrc(a, 12u * cs), rt = make_rsrc(t, 12u * cs);
-  const rsrc_t rg = make_rsrc(G, 36u * gs);
-  cx<C> au[2][3], ad[2][3], tu[2][3], td[2][3];
-  load_spinor<C, SE>(ra, cs, site, a_g5 != 0, au, ad);
-  load_spinor<C, SE>(rt, cs, site, false, tu, td);
-  const C cf = C(-0.5 * coef);
-  const bool acc = accumulate != 0, g5 = a_g5 != 0;
-  vjp_dir<0, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[0], g5, au, ad, tu, td, cf, acc);
-  vjp_dir<1, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[1], g5, au, ad, tu, td, cf, acc);
-  vjp_dir<2, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[2], g5, au, ad, tu, td, cf, acc);
-  vjp_dir<3, C, SE, GE>(rg, gs, ra, rt, cs, site, fwd[3], g5, au, ad, tu, td, cf, acc);
 }
 
 }  // namespace ovl

@@ -966,18 +966,26 @@ int ovl_defl_correct(const ovl_defl *d, void *inout, const double *c_dev, const 
 // link derivatives
 namespace {
 
-int launch_vjp(Prec prec, const ovl_gauge *g, void *G, const void *a, int a_g5, const void *t,
-               double coef, int accumulate, hipStream_t s) {
-  const dim3 grid(grid_blocks(g->g.V));
+// One launch accumulates len pairs (a_i, t_i) = (a0 + i * step, t0 + i * step) into G; the
+// first pair carries weight coef_first, the others coef_rest.
+int launch_vjp(Prec prec, const ovl_gauge *g, void *G, const void *a0, int a_g5, const void *t0,
+               size_t step_bytes, int len, double coef_first, double coef_rest, int accumulate,
+               hipStream_t s) {
+  if (len <= 0) return OVL_OK;
+  const dim3 grid((unsigned)((g->g.V + 63) / 64));
   switch (prec) {
     case P_F64:
-      link_vjp_kernel<double, double2, double2><<<grid, kBlock, 0, s>>>(
-          (double2 *)G, (const double2 *)a, (const double2 *)t, g->g, coef, a_g5, accumulate, 1);
+      link_vjp_kernel<double, double2, double2><<<grid, 256, 0, s>>>(
+          (double2 *)G, (const double2 *)a0, (int64_t)(step_bytes / sizeof(double2)),
+          (const double2 *)t0, (int64_t)(step_bytes / sizeof(double2)), len, coef_first,
+          coef_rest, g->g, a_g5, accumulate);
       break;
     case P_F32:
     case P_F32_BF16:
-      link_vjp_kernel<float, float2, float2><<<grid, kBlock, 0, s>>>(
-          (float2 *)G, (const float2 *)a, (const float2 *)t, g->g, coef, a_g5, accumulate, 1);
+      link_vjp_kernel<float, float2, float2><<<grid, 256, 0, s>>>(
+          (float2 *)G, (const float2 *)a0, (int64_t)(step_bytes / sizeof(float2)),
+          (const float2 *)t0, (int64_t)(step_bytes / sizeof(float2)), len, coef_first, coef_rest,
+          g->g, a_g5, accumulate);
       break;
     default:
       return fail(OVL_EDTYPE, "bad precision");
@@ -1000,7 +1008,7 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G, const void *chi, const void
   if (rc) return rc;
   if (!psi) return fail(OVL_EINVAL, "psi is NULL");
   if (!fits_u32(36ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "G exceeds 4 GiB");
-  return launch_vjp(prec, g, G, chi, 0, psi, 1.0, accumulate, as_stream(stream));
+  return launch_vjp(prec, g, G, chi, 0, psi, 0, 1, 1.0, 1.0, accumulate, as_stream(stream));
 }
 
 // dL = Re[<b_1, dX t_0> + 2 sum_{m=1}^{N-1} <b_{m+1}, dX t_m>] with b the Clenshaw vectors of chi
@@ -1031,16 +1039,18 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
   hipStream_t s = as_stream(stream);
   const size_t vec = (size_t)12 * g->g.V * elem_bytes(spin_dt);
   const size_t vecp = (vec + 255) / 256 * 256;
-  // checkpoints, segment buffer S (+1 spare), two b vectors
-  const size_t nvec = (size_t)nslot + (S + 1) + 2;
+  // checkpoints, segment buffer of S vectors (+1 spare), ring of S + 2 Clenshaw vectors
+  const int R = S + 2;
+  const size_t nvec = (size_t)nslot + (S + 1) + R;
   Scratch sc;
   rc = scratch_alloc(sc, nvec * vecp, s);
   if (rc) return rc;
   char *base = (char *)sc.p;
   auto ck = [&](int m) -> void * { return base + (size_t)slot_of[m] * vecp; };
   auto seg = [&](int i) -> void * { return base + ((size_t)nslot + i) * vecp; };
-  void *bA = base + ((size_t)nslot + S + 1) * vecp;
-  void *bB = base + ((size_t)nslot + S + 2) * vecp;
+  // b_k lives in ring slot k mod R: a segment touches b_{m0} .. b_{m1+2}, at most S + 2 vectors
+  char *ring = base + ((size_t)nslot + S + 1) * vecp;
+  auto bv = [&](int k) -> void * { return ring + (size_t)(k % R) * vecp; };
   const double kdiag = 4.0 - p->m_W;
   const double *al = p->alpha.data();
   // X applied: out = sx * X v + a * src + t * w
@@ -1085,13 +1095,9 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
   }
   // backward sweep, segments from the top
   HIP_TRY(hipMemsetAsync(G, 0, (size_t)36 * g->g.V * elem_bytes(spin_dt), s));
-  // b_{N+1} = 0, b_N = alpha_N chi: keep b_{k+1} in cur, b_{k+2} in prev
-  void *cur = bA, *prev = bB;
-  // b_N = alpha_N chi  (X applied to chi with factor 0 is avoided: use a scaled copy via a step
-  // with sx = 0 would still read neighbours; build it as a * src with a zero stencil input)
-  if ((rc = xstep(cur, chi, 0.0, chi, al[N], nullptr, 0.0))) return rc;
-  HIP_TRY(hipMemsetAsync(prev, 0, vec, s));
-  int k = N;  // cur holds b_k
+  // b_{N+1} = 0 and b_N = alpha_N chi (a step whose stencil term has weight zero)
+  HIP_TRY(hipMemsetAsync(bv(N + 1), 0, vec, s));
+  if ((rc = xstep(bv(N), chi, 0.0, chi, al[N], nullptr, 0.0))) return rc;
   for (int j = nseg - 1; j >= 0; --j) {
     const int m0 = j * S;
     const int m1 = std::min(N - 1, m0 + S - 1);
@@ -1100,19 +1106,22 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
     if (m1 >= m0 + 1) HIP_TRY(hipMemcpyAsync(seg(1), ck(m0 + 1), vec, hipMemcpyDeviceToDevice, s));
     for (int m = m0 + 2; m <= m1; ++m)
       if ((rc = xstep(seg(m - m0), seg(m - m0 - 1), 2.0, nullptr, 0.0, seg(m - m0 - 2), -1.0))) return rc;
-    for (int m = m1; m >= m0; --m) {
-      // need b_{m+1}: cur holds b_k with k = m + 1 (invariant)
-      const double coef = (m == 0 ? 1.0 : 2.0) / p->lmax;
-      if ((rc = launch_vjp(prec, g, G, cur, 1, seg(m - m0), coef, 1, s))) return rc;
-      if (m >= 1) {
-        // b_m = alpha_m chi + 2 X b_{m+1} - b_{m+2}  -> written over prev (holds b_{m+2})
-        if ((rc = xstep(prev, cur, 2.0, chi, al[m], prev, -1.0))) return rc;
-        std::swap(cur, prev);
-        --k;
-      }
+    // b_m = alpha_m chi + 2 X b_{m+1} - b_{m+2} for m = m1 .. max(m0, 1); b_{m1+1} and b_{m1+2}
+    // come from the segment above (or the start values)
+    for (int m = m1; m >= std::max(m0, 1); --m)
+      if ((rc = xstep(bv(m), bv(m + 1), 2.0, chi, al[m], bv(m + 2), -1.0))) return rc;
+    // pairs (b_{m+1}, t_m), m = m0 .. m1, in runs whose ring slots are consecutive
+    int m = m0;
+    while (m <= m1) {
+      const int slot = (m + 1) % R;
+      const int len = std::min(m1 - m + 1, R - slot);
+      const double cf = (m == 0 ? 1.0 : 2.0) / p->lmax;
+      if ((rc = launch_vjp(prec, g, G, bv(m + 1), 1, seg(m - m0), vecp, len, cf, 2.0 / p->lmax, 1,
+                           s)))
+        return rc;
+      m += len;
     }
   }
-  (void)k;
   return OVL_OK;
 }
 

@@ -99,6 +99,20 @@ __device__ __forceinline__ void quad_hop(cx<C> acc[12], rsrc_t v, uint32_t cs, r
   }
 }
 
+// h = projection of (u, d) by (1 - gamma_mu) (sgn = +1) or (1 + gamma_mu) (sgn = -1)
+template <class C>
+__device__ __forceinline__ void dir_project(const cx<C> u[2][3], const cx<C> d[2][3],
+                                            const DirCoef<C> &k, C sgn, cx<C> h[2][3]) {
+  const cx<C> z0 = scale(k.z0, sgn), z1 = scale(k.z1, sgn);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<C> dA = k.p ? d[1][c] : d[0][c];
+    const cx<C> dB = k.p ? d[0][c] : d[1][c];
+    h[0][c] = u[0][c] + zmul(z0, dA);
+    h[1][c] = u[1][c] + zmul(z1, dB);
+  }
+}
+
 // Extents, strides and coordinates as named scalars.  The direction-split kernel selects one of
 // four values per thread; with arrays the compiler turns those selects into dynamically indexed
 // private memory, so everything here is plain scalars.
