@@ -329,7 +329,8 @@ __global__ void __launch_bounds__(256)
   const bool arow = e < n_ev, bcol = r < nrhs;
   const int64_t k_begin = (int64_t)blockIdx.x * chunk;
   const int64_t k_end = k_begin + chunk < K ? k_begin + chunk : K;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  // the matrix core accumulates 16 products per lane group in FP32; the running sum is FP64
+  double acc64[4] = {0.0, 0.0, 0.0, 0.0};
   // Each step covers 4 waves x 4 lane groups x MT reals.  The loop bound is uniform over the wave:
   // an MFMA reads its operands from every lane regardless of the execution mask, so no lane may
   // leave the loop early; positions past the chunk are masked to zero instead.
@@ -349,15 +350,20 @@ __global__ void __launch_bounds__(256)
     }
     if (imcol) { bv[0] = y0; bv[1] = -x0; bv[2] = y1; bv[3] = -x1; }
     else { bv[0] = x0; bv[1] = y0; bv[2] = x1; bv[3] = y1; }
+    // the lane's A value belongs to row e and its B value to column col: separate masks
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < kMfmaT; ++t) {
-      const bool in = (k0 + t < k_end) && arow && bcol;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(in ? a[t] : 0.f, in ? bv[t] : 0.f, acc, 0, 0, 0);
+      const bool in = k0 + t < k_end;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32((in && arow) ? a[t] : 0.f,
+                                                 (in && bcol) ? bv[t] : 0.f, acc, 0, 0, 0);
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc64[q] += (double)acc[q];
   }
   // lane holds C[row = 4 g + q][col = i], q = 0..3
 #pragma unroll
-  for (int q = 0; q < 4; ++q) tile[wave][4 * g + q][i] = (double)acc[q];
+  for (int q = 0; q < 4; ++q) tile[wave][4 * g + q][i] = acc64[q];
   __syncthreads();
   if (threadIdx.x < 256) {
     const int row = threadIdx.x >> 4, c = threadIdx.x & 15;

@@ -234,16 +234,18 @@ def test_defl_project_correct(ovl, store):
         assert max_rel(out[r], ref) < tol
 
 
-def test_defl_project_mfma_tiles(ovl):
-    """FP32 projection on the matrix cores: more than 16 eigenvectors and 8 right-hand sides
-    (several MFMA tiles), a volume that leaves ragged chunks, FP64 oracle on the rounded data."""
+@pytest.mark.parametrize("n_ev,nrhs", [(20, 10), (12, 1), (3, 9), (16, 8)])
+def test_defl_project_mfma_tiles(ovl, n_ev, nrhs):
+    """FP32 projection on the matrix cores: partial and several MFMA tiles in both the
+    eigenvector and the right-hand-side direction, a volume that leaves ragged chunks, FP64
+    oracle on the rounded data."""
     dims = (5, 3, 4, 6)
-    phi, lam = random_basis(dims, 20, 55)
-    psi = latgen.gaussian_spinor(dims, 56, nrhs=10)
+    phi, lam = random_basis(dims, n_ev, 55)
+    psi = latgen.gaussian_spinor(dims, 56, nrhs=nrhs)
     d = ovl.Deflation(dev(phi), lam, "f32")
     c = host(ovl.defl_project(d, dev(psi, torch.complex64)))
     phi_r, psi_r = latgen.round_to_f32(phi), latgen.round_to_f32(psi)
-    for r in range(10):
+    for r in range(nrhs):
         ref = odefl.project(phi_r, psi_r[r])
         assert max_rel(c[r], ref) < 1e-6
 
