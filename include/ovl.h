@@ -202,10 +202,13 @@ const char *ovl_last_error(void);
  * Synchronises the device. */
 int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear);
 
-/* Kernel timing of the fused Chebyshev step: when enabled, HIP events are recorded on the call's
- * stream around every launch of that kernel by the calling thread; ovl_timing_read returns the
- * summed duration (ms) and launch count since the last reset (synchronising the recorded events)
- * and resets the counters. */
+/* Kernel timing of the fused Chebyshev step: when enabled, every sign evaluation (sign, overlap,
+ * batched sign) records one HIP event on its stream before its first plain recurrence step and
+ * one after its last (the steps k = N-1 .. 1 are consecutive launches of that kernel, so the
+ * interval divided by N - 1 is the kernel's average duration back to back, inter-launch gaps
+ * included).  ovl_timing_read returns the summed interval (ms) and the number of launches it
+ * covers since the last read (synchronising the recorded events) and resets both.  Evaluations
+ * of degree 1 record nothing. */
 int ovl_timing_enable(int on);
 int ovl_timing_read(double *total_ms, int64_t *launches);
 

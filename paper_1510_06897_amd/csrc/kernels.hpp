@@ -156,6 +156,32 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
   double nrm[2] = {0.0, 0.0};
   const rsrc_t v = make_rsrc(vec(p.v_role), vb);
   const bool vg5 = p.v_g5 != 0;
+  // After the LDS exchange the thread owns spin component q of its site.  Small launches
+  // (SPB < 64: few waves per CU, bound by memory latency) load the operands of that component's
+  // vector algebra before the stencil so the two latencies overlap; large launches load them
+  // after the exchange and keep the registers for occupancy.
+  constexpr bool kEarly = SPB < 64;
+  const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + site;  // element of component 3q
+  const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
+  cx<C> vx[3], srcx[3], wx[3];
+  auto load_ops = [&]() {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vx[c] = srcx[c] = wx[c] = mk<C>(0, 0);
+    if (!active) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vx[c] = bldv<C, SE>(v, e0 + c * V);
+    if (need_src) {
+      const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(sr, e0 + c * V);
+    }
+    if (p.w_role != ROLE_NONE) {
+      const rsrc_t w = make_rsrc(vec(p.w_role), vb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) wx[c] = bldv<C, SE>(w, e0 + c * V);
+    }
+  };
+  if (kEarly) load_ops();
   {
     cx<C> acc[12];
 #pragma unroll
@@ -173,6 +199,7 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
     for (int i = 0; i < 12; ++i) part[q][i][sl] = acc[i];
   }
   __syncthreads();
+  if (!kEarly) load_ops();
   if (active) {
     cx<C> hop[3];
 #pragma unroll
@@ -180,22 +207,13 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
       hop[c] = part[0][3 * q + c][sl] + part[1][3 * q + c][sl] + part[2][3 * q + c][sl] +
                part[3][3 * q + c][sl];
     const C kd = C(p.kd), kh = C(p.kh);
-    const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + site;  // element of component 3q
     cx<C> res[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      cx<C> vx = bldv<C, SE>(v, e0 + c * V);
-      if (vg5 && lower) vx = -vx;
-      cx<C> y = mk<C>(kd * vx.re + kh * hop[c].re, kd * vx.im + kh * hop[c].im);
+      const cx<C> x = (vg5 && lower) ? -vx[c] : vx[c];
+      cx<C> y = mk<C>(kd * x.re + kh * hop[c].re, kd * x.im + kh * hop[c].im);
       if (p.y_g5 && lower) y = -y;
       res[c] = y;
-    }
-    cx<C> srcx[3];
-    const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
-    if (need_src) {
-      const rsrc_t s = make_rsrc(vec(ROLE_PSI), vb);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(s, e0 + c * V);
     }
     if (p.a != 0.0) {
       const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
@@ -203,10 +221,9 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
       for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
     }
     if (p.w_role != ROLE_NONE) {
-      const rsrc_t w = make_rsrc(vec(p.w_role), vb);
       const C t = C(p.t);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(bldv<C, SE>(w, e0 + c * V), t);
+      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(wx[c], t);
     }
     if (p.mode >= MODE_SIGN) {
       for (int e = 0; e < I.n_ev; ++e) {
@@ -243,16 +260,21 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// final check of the recurrence: ||res||^2 <= bound2 ||src||^2 and finite, per right-hand side
-__global__ void norm_check_kernel(const double *partial, int nblk, int nrhs, double bound2,
-                                  uint32_t *flags, double *norms_out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  double so = 0.0, si = 0.0;
-  for (int b = 0; b < nblk; ++b) {
-    so += partial[((int64_t)b * nrhs + r) * 2 + 0];
-    si += partial[((int64_t)b * nrhs + r) * 2 + 1];
+// final check of the recurrence: ||res||^2 <= bound2 ||src||^2 and finite, per right-hand side.
+// One workgroup per right-hand side sums the step kernel's block partials (fixed order).
+__global__ void __launch_bounds__(kBlock)
+    norm_check_kernel(const double *partial, int nblk, int nrhs, double bound2, uint32_t *flags,
+                      double *norms_out) {
+  __shared__ double lds[2 * 16];
+  const int r = blockIdx.x;
+  double v[2] = {0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kBlock) {
+    v[0] += partial[((int64_t)b * nrhs + r) * 2 + 0];
+    v[1] += partial[((int64_t)b * nrhs + r) * 2 + 1];
   }
+  block_sum<2>(v, lds);
+  if (threadIdx.x != 0) return;
+  const double so = v[0], si = v[1];
   if (norms_out != nullptr) {
     norms_out[2 * r + 0] = so;
     norms_out[2 * r + 1] = si;
@@ -380,18 +402,24 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// pass 2: c[r][i] = sum_b partial[b][r][i] in block order (deterministic)
-__global__ void project_reduce_kernel(const double2 *__restrict__ partial, int nblk, int count,
-                                      double2 *__restrict__ c) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= count) return;
+// pass 2: c[r][i] = sum_b partial[b][r][i]; one wave per output, lane l sums blocks l, l + 64, ...
+// and the wave adds the lanes in a fixed butterfly (deterministic)
+__global__ void __launch_bounds__(64)
+    project_reduce_kernel(const double2 *__restrict__ partial, int nblk, int count,
+                          double2 *__restrict__ c) {
+  const int k = blockIdx.x;
   double re = 0.0, im = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += 64) {
     const double2 v = partial[(int64_t)b * count + k];
     re += v.x;
     im += v.y;
   }
-  c[k] = make_double2(re, im);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (threadIdx.x == 0) c[k] = make_double2(re, im);
 }
 
 // inout_r += sum_i phi_i (wscale * w_i * c[r][i])   (w == null -> w_i = 1)

@@ -84,10 +84,15 @@ int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s) {
   return OVL_OK;
 }
 
-// kernel timing of the fused Chebyshev step (see ovl_timing_enable)
+// kernel timing of the fused Chebyshev step (see ovl_timing_enable): one event pair brackets the
+// n consecutive plain step launches of one sign evaluation
+struct TimedRun {
+  hipEvent_t e0, e1;
+  int n;
+};
 std::atomic<int> g_timing{0};
 std::mutex g_timing_mu;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timing_events;
+std::vector<TimedRun> g_timing_events;
 std::vector<hipEvent_t> g_event_pool;
 
 hipEvent_t pool_event() {
@@ -274,46 +279,34 @@ int64_t items_work(const StepItem *items, int n) {
 // launch one step; a single-problem launch plans its item here, a table launch was planned when
 // its table was written (p.total_blocks, spb)
 template <class C, class SE, class LE, bool TABLE>
-int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool timed) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    e0 = pool_event();
-    e1 = pool_event();
-  }
-  if (e0 && e1) HIP_TRY(hipEventRecord(e0, s));
+int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s) {
   if (spb == 64)
     step_kernel<C, SE, LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
   else
     step_kernel<C, SE, LE, 16, TABLE><<<p.total_blocks, 64, 0, s>>>(p);
   HIP_TRY(hipGetLastError());
-  if (e0 && e1) {
-    HIP_TRY(hipEventRecord(e1, s));
-    std::lock_guard<std::mutex> lk(g_timing_mu);
-    g_timing_events.emplace_back(e0, e1);
-  }
   return OVL_OK;
 }
 
 template <bool TABLE>
-int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s, bool timed) {
+int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s) {
   switch (prec) {
-    case P_F64: return launch_step<double, double2, double2, TABLE>(p, spb, s, timed);
-    case P_F32: return launch_step<float, float2, float2, TABLE>(p, spb, s, timed);
-    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, spb, s, timed);
+    case P_F64: return launch_step<double, double2, double2, TABLE>(p, spb, s);
+    case P_F32: return launch_step<float, float2, float2, TABLE>(p, spb, s);
+    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, spb, s);
     default: return fail(OVL_EDTYPE, "bad precision");
   }
 }
 
 // single problem: plan its item with the tuned (or default) configuration, then launch
-int dispatch_cfg(Prec prec, StepArgs<false> &p, const LaunchCfg &cfg, hipStream_t s, bool timed) {
+int dispatch_cfg(Prec prec, StepArgs<false> &p, const LaunchCfg &cfg, hipStream_t s) {
   p.total_blocks = plan_items(&p.item, 1, cfg, site_bytes_of(prec));
   p.remap = cfg.remap;
-  return dispatch_step(prec, p, cfg.spb, s, timed);
+  return dispatch_step(prec, p, cfg.spb, s);
 }
-int dispatch_single(Prec prec, StepArgs<false> &p, hipStream_t s, bool timed = false) {
+int dispatch_single(Prec prec, StepArgs<false> &p, hipStream_t s) {
   const LaunchCfg cfg = lookup_cfg(p.item.g, prec, p.item.nrhs, items_work(&p.item, 1));
-  return dispatch_cfg(prec, p, cfg, s, timed);
+  return dispatch_cfg(prec, p, cfg, s);
 }
 
 void fill_item(StepItem &it, const ovl_gauge *g, int nrhs) {
@@ -345,14 +338,22 @@ StepArgs<false> single_args(const ovl_gauge *g, int nrhs) {
 
 // c[r][i] = phi_i^+ psi_r (FP64 result), scratch `partial` of n_blocks * nrhs * n_ev double2.
 // FP64 storage: VALU kernel with FP64 products; FP32 storage: FP32 matrix-core kernel.
+// workgroups of the two projection kernels; the partial buffer holds project_blocks(V) of either
+int project_blocks_valu(int V) { return std::min(grid_blocks(V), 1024); }
+int project_blocks_mfma(int V) {  // about 1024 reals per workgroup: many short FP32 sums
+  return (int)std::min<int64_t>(((int64_t)24 * V + 1023) / 1024, 2048);
+}
+int project_blocks(int V) { return std::max(project_blocks_valu(V), project_blocks_mfma(V)); }
+
 int project(const double2 *phi, int n_ev, const double2 *psi, int psi_g5, int nrhs, int V,
             double2 *partial, int nblk, double2 *c, hipStream_t s) {
   constexpr int CH = 8;
+  nblk = std::min(nblk, project_blocks_valu(V));
   dim3 grid(nblk, (n_ev + CH - 1) / CH, nrhs);
   project_partial_kernel<double2, CH><<<grid, kBlock, 0, s>>>(phi, n_ev, psi, psi_g5, V, partial);
   HIP_TRY(hipGetLastError());
   const int count = nrhs * n_ev;
-  project_reduce_kernel<<<(count + 127) / 128, 128, 0, s>>>(partial, nblk, count, c);
+  project_reduce_kernel<<<count, 64, 0, s>>>(partial, nblk, count, c);
   HIP_TRY(hipGetLastError());
   return OVL_OK;
 }
@@ -362,6 +363,7 @@ int project(const float2 *phi, int n_ev, const float2 *psi, int psi_g5, int nrhs
   if (!fits_u32(12ull * V * nrhs, OVL_F32))
     return fail(OVL_EDIMS, "%d right-hand sides of %d sites exceed 4 GiB", nrhs, V);
   const int64_t K = (int64_t)24 * V;
+  nblk = std::min(nblk, project_blocks_mfma(V));
   // reals per workgroup: a multiple of 64 (4 waves x 4 lane groups x 4 reals)
   int64_t chunk = (K + nblk - 1) / nblk;
   chunk = (chunk + 63) / 64 * 64;
@@ -371,12 +373,10 @@ int project(const float2 *phi, int n_ev, const float2 *psi, int psi_g5, int nrhs
                                            psi_g5, V, (int)chunk, partial);
   HIP_TRY(hipGetLastError());
   const int count = nrhs * n_ev;
-  project_reduce_kernel<<<(count + 127) / 128, 128, 0, s>>>(partial, blocks, count, c);
+  project_reduce_kernel<<<count, 64, 0, s>>>(partial, blocks, count, c);
   HIP_TRY(hipGetLastError());
   return OVL_OK;
 }
-
-int project_blocks(int V) { return std::min(grid_blocks(V), 1024); }
 
 // make sure d->w_dev holds w_i = sign(lambda_i) - p(lambda_i / lmax) for this polynomial
 int defl_weights(ovl_defl *d, const ovl_poly *p, hipStream_t s) {
@@ -489,8 +489,15 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   auto role = [](int k) { return (k % 2 == 0) ? ROLE_B0 : ROLE_B1; };
   const double *al = p->alpha.data();
   const double kdiag = 4.0 - p->m_W;
-  const bool timed = g_timing.load() != 0;
+  // timing: one event pair around the plain steps k = N-1 .. 1 (consecutive launches)
+  TimedRun run{nullptr, nullptr, N - 1};
+  if (g_timing.load() != 0 && N >= 2) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    run.e0 = pool_event();
+    run.e1 = pool_event();
+  }
   for (int k = N - 1; k >= 0; --k) {
+    if (k == N - 1 && run.e0) HIP_TRY(hipEventRecord(run.e0, s));
     double sfac = (k == 0) ? 1.0 : 2.0;
     double a = al[k];
     if (k + 1 == N) {
@@ -519,8 +526,13 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     args.out_role = role(k);
     args.mode = (k == 0) ? mode : MODE_STEP;
     args.mu = mu;
-    rc = dispatch_step(prec, args, spb, s, timed && k > 0);
+    rc = dispatch_step(prec, args, spb, s);
     if (rc) return rc;
+    if (k == 1 && run.e0 && run.e1) {
+      HIP_TRY(hipEventRecord(run.e1, s));
+      std::lock_guard<std::mutex> lk(g_timing_mu);
+      g_timing_events.push_back(run);
+    }
   }
   for (int j = 0; j < nj; ++j) {
     const SignJob &J = jobs[j];
@@ -530,7 +542,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
       for (double w : J.d->w_host) m = std::max(m, std::fabs(w));
       bound += m;
     }
-    norm_check_kernel<<<(J.nrhs + 255) / 256, 256, 0, s>>>(
+    norm_check_kernel<<<J.nrhs, kBlock, 0, s>>>(
         items[j].norm_partial, item_blocks(J.g->g.V, spb), J.nrhs, bound * bound, J.g->flags,
         nullptr);
     HIP_TRY(hipGetLastError());
@@ -1162,9 +1174,9 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
           step_tile(g->g, spb, sb, ty, tz);
           if (ty == 0) continue;
         }
-        for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s, false);
+        for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
         if (rc == OVL_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
-        for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s, false);
+        for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
         if (rc == OVL_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
         float ms = 0.f;
         if (rc == OVL_OK && (hipEventSynchronize(e1) != hipSuccess ||
@@ -1242,15 +1254,17 @@ int ovl_timing_read(double *total_ms, int64_t *launches) {
   if (!total_ms || !launches) return fail(OVL_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(g_timing_mu);
   double tot = 0.0;
-  for (auto &pr : g_timing_events) {
-    HIP_TRY(hipEventSynchronize(pr.second));
+  int64_t n = 0;
+  for (auto &run : g_timing_events) {
+    HIP_TRY(hipEventSynchronize(run.e1));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    HIP_TRY(hipEventElapsedTime(&ms, run.e0, run.e1));
     tot += ms;
-    g_event_pool.push_back(pr.first);
-    g_event_pool.push_back(pr.second);
+    n += run.n;
+    g_event_pool.push_back(run.e0);
+    g_event_pool.push_back(run.e1);
   }
-  *launches = (int64_t)g_timing_events.size();
+  *launches = n;
   *total_ms = tot;
   g_timing_events.clear();
   return OVL_OK;
