@@ -70,8 +70,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile", action="store_true",
-                    help="run only the timed mixed-precision loop (for rocprofv3 runs)")
+    ap.add_argument("--profile", nargs="?", const="c2", choices=["c2", "dw", "proj"],
+                    help="run one part only, for rocprofv3 runs: c2 = the timed FP32 overlap "
+                         "loop (default), dw = K at 24^3x48 in FP64/FP32/BF16, proj = the FP32 "
+                         "matrix-core deflation projection at 16^3x32 with 24 vectors")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched, BF16/24-mode and force measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -208,6 +210,40 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
     return out
 
 
+def dw_inputs(latgen, torch, dev):
+    u = latgen.random_su3_field(DIMS_DW, latgen.seed_for("gauge", 5))
+    psi = latgen.gaussian_spinor(DIMS_DW, latgen.seed_for("spinor", 5))
+    return torch.from_numpy(u).to(dev), torch.from_numpy(psi).to(dev)
+
+
+def profile_dw(ovl, latgen, torch, dev, reps):
+    """K applications at 24^3x48 in the three storage precisions (the bench's D_W figures)."""
+    d_ub, d_pb = dw_inputs(latgen, torch, dev)
+    for store in ("f64", "f32", "bf16"):
+        gb = ovl.GaugeField(d_ub, store)
+        x = d_pb if store == "f64" else d_pb.to(torch.complex64)
+        y = torch.empty_like(x)
+        for _ in range(reps):
+            ovl.kernel_apply(gb, x, out=y)
+        torch.cuda.synchronize()
+        log(f"profile dw {store}: {reps} applies")
+        gb.close()
+
+
+def profile_proj(ovl, torch, dev, reps):
+    """FP32 matrix-core projection c = Phi^+ psi: 24 vectors of 16^3x32 (random basis)."""
+    dims = (16, 16, 16, 32)
+    gen = torch.Generator(device=dev).manual_seed(7)
+    shape = (24, 4, 3) + tuple(reversed(dims))
+    phi = torch.randn(shape, dtype=torch.complex128, device=dev, generator=gen)
+    psi = torch.randn(shape[1:], dtype=torch.complex64, device=dev, generator=gen)
+    d = ovl.Deflation(phi, np.linspace(-0.5, 0.5, 24), "f32")
+    for _ in range(reps):
+        ovl.defl_project(d, psi)
+    torch.cuda.synchronize()
+    log(f"profile proj: {reps} projections")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -233,6 +269,12 @@ def main():
     ovl.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.profile == "dw":
+        profile_dw(ovl, latgen, torch, dev, args.steps)
+        return
+    if args.profile == "proj":
+        profile_proj(ovl, torch, dev, args.steps)
+        return
 
     # ---------------- inputs (untimed set-up) ----------------
     t0 = time.time()
@@ -313,12 +355,8 @@ def main():
 
     # ---------------- D_W (K) at 24^3x48 ----------------
     t0 = time.time()
-    u_big = latgen.random_su3_field(DIMS_DW, latgen.seed_for("gauge", 5))
-    psi_big = latgen.gaussian_spinor(DIMS_DW, latgen.seed_for("spinor", 5))
+    d_ub, d_pb = dw_inputs(latgen, torch, dev)
     log(f"24^3x48 inputs {time.time() - t0:.1f}s")
-    d_ub = torch.from_numpy(u_big).to(dev)
-    d_pb = torch.from_numpy(psi_big).to(dev)
-    del u_big, psi_big
     vol_b = int(np.prod(DIMS_DW))
     dw = {}
     for store in ("f64", "f32", "bf16"):

@@ -179,7 +179,7 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const voi
 /* ---- launch tuning ------------------------------------------------------------------------ */
 
 /* Measure the fused stencil kernel on this gauge field for nrhs right-hand sides of spin_dt over
- * its launch configurations (sites per workgroup 16 or 64; t-streaming tile order or memory
+ * its launch configurations (sites per workgroup 16, 64 or 128; t-streaming tile order or memory
  * order; XCD-contiguous workgroup remap on or off), keep the fastest for every later call with the
  * same extents, precision and nrhs, and append it to the text file cache_path when not NULL
  * (one line: Lx Ly Lz Lt precision nrhs spb tiles remap microseconds).  *best_us (nullable)
@@ -190,7 +190,10 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
 /* Load configurations written by ovl_autotune; returns the number of entries read (>= 0) or
  * OVL_EINVAL when the file cannot be opened. */
 int ovl_autotune_load(const char *cache_path);
-/* The configuration the library will use: cfg_out = {sites per workgroup, tile order, remap}. */
+/* The configuration the library will use: cfg_out = {sites per workgroup, tile order, remap}.
+ * Sites per workgroup: 16 (one wave, one site per lane), 64 (four waves, one site per lane) or
+ * 128 (four waves, two x-adjacent sites per lane: FP32 spinors, even Lx, 16-byte aligned
+ * vectors; a call whose vectors are not aligned runs with 64). */
 int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]);
 
 /* ---- diagnostics ------------------------------------------------------------------------- */

@@ -260,6 +260,479 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// The same fused step with two x-adjacent sites (x even, x + 1) per lane, for FP32 spinors with
+// FP32 or BF16 links and an even Lx.  Every spinor, link and output access of a pair is one
+// 16-byte (links in BF16: 8-byte) lane access, which halves the vector-memory instructions per
+// site; the x direction needs the own pair plus the single sites x + 2 and x - 1.  SPB pairs per
+// workgroup, 4 * SPB threads; with SPB = 64 each wave works on one direction.
+template <class SE>
+__device__ __forceinline__ void load_spinor_pair(rsrc_t v, uint32_t cs, uint32_t s0, bool g5,
+                                                 cx<float> u0[2][3], cx<float> d0[2][3],
+                                                 cx<float> u1[2][3], cx<float> d1[2][3]) {
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      bld2<SE>(v, (sp * 3 + c) * cs, s0, u0[sp][c], u1[sp][c]);
+      cx<float> x0, x1;
+      bld2<SE>(v, ((sp + 2) * 3 + c) * cs, s0, x0, x1);
+      d0[sp][c] = g5 ? -x0 : x0;
+      d1[sp][c] = g5 ? -x1 : x1;
+    }
+}
+
+template <class LE>
+__device__ __forceinline__ void load_link_pair(rsrc_t U, uint32_t ls, uint32_t l0,
+                                               cx<float> m0[3][3], cx<float> m1[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) bld2<LE>(U, (a * 3 + b) * ls, l0, m0[a][b], m1[a][b]);
+}
+
+template <class C, class LE>
+__device__ __forceinline__ void load_link_c(rsrc_t U, uint32_t ls, uint32_t l, cx<C> m[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(U, (a * 3 + b) * ls, l);
+}
+
+template <class LE>
+__device__ __forceinline__ void load_link(rsrc_t U, uint32_t ls, uint32_t l, cx<float> m[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) m[a][b] = bld<float, LE>(U, (a * 3 + b) * ls, l);
+}
+
+template <class LE, int SPB, bool TABLE>
+__global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
+  using C = float;
+  using SE = float2;
+  __shared__ double lds[2 * 16];
+  __shared__ cx<C> part[4][12][2 * SPB];  // directional partial sums, two sites per pair
+  const int gb = xcd_block(blockIdx.x, gridDim.x, p.remap);
+  int it = 0;
+  if (TABLE)
+    for (int i = 1; i < p.n_items; ++i)
+      if (p.table[i].blk0 <= gb) it = i;
+  const StepItem &I = TABLE ? p.table[it] : p.item;
+  const Ext4 ex = ext_of(I.g);
+  const int nrhs = I.nrhs;
+  const int lb = gb - I.blk0;
+  const int r = lb % nrhs;
+  const int b = lb / nrhs;
+  const int q = threadIdx.x / SPB;
+  const int sl = threadIdx.x % SPB;
+  Coord4 c4;
+  int s0;  // first site of the pair (x even)
+  bool active;
+  if (I.ty > 0) {
+    const int slice = ex.lx * I.ty * I.tz;
+    const int nsub = slice / (2 * SPB);
+    int tb = b;
+    const int sub = tb % nsub;
+    tb /= nsub;
+    c4.t = tb % ex.lt;
+    const int tile = tb / ex.lt;
+    const int nty = ex.ly / I.ty;
+    const int local = 2 * (sub * SPB + sl);
+    c4.x = local % ex.lx;
+    const int rr = local / ex.lx;
+    c4.y = (tile % nty) * I.ty + rr % I.ty;
+    c4.z = (tile / nty) * I.tz + rr / I.ty;
+    s0 = c4.x + ex.sy * c4.y + ex.sz * c4.z + ex.st * c4.t;
+    active = true;
+  } else {
+    s0 = 2 * (b * SPB + sl);
+    active = s0 < ex.V;
+    c4 = coords_of(ex, active ? s0 : 0);
+  }
+  const int V = ex.V;
+  const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;
+  const uint32_t vb = 12u * cs;
+  const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
+  const int64_t base = (int64_t)r * 12 * V;
+  const bool lower = q >= 2;
+  auto vec = [&](int role) -> const SE * {
+    const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
+    return reinterpret_cast<const SE *>(ptr) + base;
+  };
+  double nrm[2] = {0.0, 0.0};
+  const rsrc_t v = make_rsrc(vec(p.v_role), vb);
+  const bool vg5 = p.v_g5 != 0;
+  {
+    cx<C> accA[12], accB[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) accA[i] = accB[i] = mk<C>(0, 0);
+    if (active) {
+      const rsrc_t U = make_rsrc(I.U, 36u * ls);
+      const DirCoef<C> k = dir_coef<C>(q);
+      const uint32_t ll = (uint32_t)q * 9u * (uint32_t)I.lstride;
+      if (q == 0) {
+        const int xn = (c4.x + 2 == ex.lx) ? s0 + 2 - ex.lx : s0 + 2;  // site x + 2
+        const int xp = (c4.x == 0) ? s0 + ex.lx - 1 : s0 - 1;          // site x - 1
+        {
+          cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
+          load_spinor_pair<SE>(v, cs, s0, vg5, u0, d0, u1, d1);
+          load_link_pair<LE>(U, ls, ll + s0, m0, m1);
+          hop_apply<C, false>(accA, u1, d1, m0, k, C(1));  // x:     psi(x + 1), U(x)
+          hop_apply<C, true>(accB, u0, d0, m0, k, C(-1));  // x + 1: psi(x), U(x)^+
+          cx<C> un[2][3], dn[2][3];
+          load_spinor<C, SE>(v, cs, xn, vg5, un, dn);
+          hop_apply<C, false>(accB, un, dn, m1, k, C(1));  // x + 1: psi(x + 2), U(x + 1)
+        }
+        {
+          cx<C> up[2][3], dp[2][3], mp[3][3];
+          load_spinor<C, SE>(v, cs, xp, vg5, up, dp);
+          load_link<LE>(U, ls, ll + xp, mp);
+          hop_apply<C, true>(accA, up, dp, mp, k, C(-1));  // x: psi(x - 1), U(x - 1)^+
+        }
+      } else {
+        int fwd, bwd;
+        dir_neighbours(ex, c4, s0, q, fwd, bwd);
+        {
+          cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
+          load_spinor_pair<SE>(v, cs, fwd, vg5, u0, d0, u1, d1);
+          load_link_pair<LE>(U, ls, ll + s0, m0, m1);
+          hop_apply<C, false>(accA, u0, d0, m0, k, C(1));
+          hop_apply<C, false>(accB, u1, d1, m1, k, C(1));
+        }
+        {
+          cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
+          load_spinor_pair<SE>(v, cs, bwd, vg5, u0, d0, u1, d1);
+          load_link_pair<LE>(U, ls, ll + bwd, m0, m1);
+          hop_apply<C, true>(accA, u0, d0, m0, k, C(-1));
+          hop_apply<C, true>(accB, u1, d1, m1, k, C(-1));
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      part[q][i][2 * sl] = accA[i];
+      part[q][i][2 * sl + 1] = accB[i];
+    }
+  }
+  __syncthreads();
+  if (active) {
+    cx<C> hop[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        hop[j][c] = part[0][3 * q + c][2 * sl + j] + part[1][3 * q + c][2 * sl + j] +
+                    part[2][3 * q + c][2 * sl + j] + part[3][3 * q + c][2 * sl + j];
+    const C kd = C(p.kd), kh = C(p.kh);
+    const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + s0;  // even
+    cx<C> res[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cx<C> vx[2];
+      bldv2<SE>(v, e0 + c * V, vx[0], vx[1]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const cx<C> x = (vg5 && lower) ? -vx[j] : vx[j];
+        cx<C> y = mk<C>(kd * x.re + kh * hop[j][c].re, kd * x.im + kh * hop[j][c].im);
+        if (p.y_g5 && lower) y = -y;
+        res[j][c] = y;
+      }
+    }
+    cx<C> srcx[2][3];
+    const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
+    if (need_src) {
+      const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bldv2<SE>(sr, e0 + c * V, srcx[0][c], srcx[1][c]);
+    }
+    if (p.a != 0.0) {
+      const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[j][c] = res[j][c] + scale(srcx[j][c], a);
+    }
+    if (p.w_role != ROLE_NONE) {
+      const rsrc_t w = make_rsrc(vec(p.w_role), vb);
+      const C t = C(p.t);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        cx<C> w0, w1;
+        bldv2<SE>(w, e0 + c * V, w0, w1);
+        res[0][c] = res[0][c] + scale(w0, t);
+        res[1][c] = res[1][c] + scale(w1, t);
+      }
+    }
+    if (p.mode >= MODE_SIGN) {
+      for (int e = 0; e < I.n_ev; ++e) {
+        const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(I.phi) + (int64_t)e * 12 * V, vb);
+        const double2 ce = I.c[r * I.n_ev + e];
+        const double we = I.wdefl[e];
+        const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          cx<C> f0, f1;
+          bldv2<SE>(ph, e0 + c * V, f0, f1);
+          res[0][c] = cmadd(res[0][c], f0, d);
+          res[1][c] = cmadd(res[1][c], f1, d);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          nrm[0] += double(res[j][c].re) * double(res[j][c].re) +
+                    double(res[j][c].im) * double(res[j][c].im);
+          nrm[1] += double(srcx[j][c].re) * double(srcx[j][c].re) +
+                    double(srcx[j][c].im) * double(srcx[j][c].im);
+        }
+      if (p.mode == MODE_OVERLAP || p.mode == MODE_OVERLAP_DAG) {
+        const C hp = C(0.5 * (1.0 + p.mu));
+        const C hm = (p.mode == MODE_OVERLAP && lower) ? C(-0.5 * (1.0 - p.mu)) : C(0.5 * (1.0 - p.mu));
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) res[j][c] = scale(srcx[j][c], hp) + scale(res[j][c], hm);
+      }
+    }
+    const rsrc_t o = make_rsrc(vec(p.out_role), vb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bstv2<SE>(o, e0 + c * V, res[0][c], res[1][c]);
+  }
+  if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
+    block_sum<2>(nrm, lds);
+    if (threadIdx.x == 0) {
+      I.norm_partial[(int64_t)lb * 2 + 0] = nrm[0];
+      I.norm_partial[(int64_t)lb * 2 + 1] = nrm[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Slab form of the fused step for large lattices.  A workgroup covers the slab of whole x lines
+// y0 .. y0 + ny - 1 at one (z, t), SPB = 64 NW = Lx ny sites, 4 SPB threads (NW waves per
+// direction).  The slab's spinors and the two neighbouring rows y0 - 1 and y0 + ny (periodic)
+// are staged in LDS once, so the x and y neighbours and the site's own value come from LDS
+// instead of four separate global reads; the x links are shared through LDS for the backward x
+// hop.  The z and t directions read global memory as in the one-site form.  The directional
+// partial sums are combined in a fixed order, ((x + z) + (y + t)).  Dynamic LDS:
+//   stage  [12][(ny + 2) Lx] complex,  slots [2][12][SPB] complex,  xlink [9][SPB] complex.
+template <class C>
+__host__ __device__ constexpr int slab_lds_bytes(int spb, int lx) {
+  return (12 * (spb + 2 * lx) + 2 * 12 * spb + 9 * spb) * (int)sizeof(cx<C>);
+}
+
+template <class C, class SE, class LE, int NW, bool TABLE>
+__global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) {
+  constexpr int SPB = 64 * NW;
+  extern __shared__ __align__(16) unsigned char slab_smem[];
+  __shared__ double lds[2 * 16];
+  const int gb = xcd_block(blockIdx.x, gridDim.x, p.remap);
+  int it = 0;
+  if (TABLE)
+    for (int i = 1; i < p.n_items; ++i)
+      if (p.table[i].blk0 <= gb) it = i;
+  const StepItem &I = TABLE ? p.table[it] : p.item;
+  const Ext4 ex = ext_of(I.g);
+  const int nrhs = I.nrhs;
+  const int lb = gb - I.blk0;
+  const int r = lb % nrhs;
+  int b = lb / nrhs;
+  const int ny = SPB / ex.lx;
+  const int nstage = SPB + 2 * ex.lx;
+  cx<C> *stage = reinterpret_cast<cx<C> *>(slab_smem);  // [12][nstage]
+  cx<C> *slots = stage + 12 * nstage;                     // [2][12][SPB]
+  cx<C> *xlink = slots + 2 * 12 * SPB;                    // [9][SPB]
+  // slab order: t fastest, then z, then the y block
+  Coord4 c4;
+  c4.t = b % ex.lt;
+  b /= ex.lt;
+  c4.z = b % ex.lz;
+  const int y0 = (b / ex.lz) * ny;
+  const int q = threadIdx.x / SPB;
+  const int sl = threadIdx.x % SPB;
+  const int row = sl / ex.lx;  // 0 .. ny - 1
+  c4.x = sl % ex.lx;
+  c4.y = y0 + row;
+  const int site = c4.x + ex.sy * c4.y + ex.sz * c4.z + ex.st * c4.t;
+  const int V = ex.V;
+  const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;
+  const uint32_t vb = 12u * cs;
+  const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
+  const int64_t base = (int64_t)r * 12 * V;
+  const bool lower = q >= 2;
+  auto vec = [&](int role) -> const SE * {
+    const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
+    return reinterpret_cast<const SE *>(ptr) + base;
+  };
+  double nrm[2] = {0.0, 0.0};
+  const rsrc_t v = make_rsrc(vec(p.v_role), vb);
+  const bool vg5 = p.v_g5 != 0;
+  const rsrc_t U = make_rsrc(I.U, 36u * ls);
+  const DirCoef<C> k = dir_coef<C>(q);
+  // 1. stage rows y0 - 1 .. y0 + ny of this (z, t), all 12 components (raw, gamma5 on use);
+  //    consecutive threads read consecutive sites of a row
+  {
+    const int plane = ex.sz * c4.z + ex.st * c4.t;
+    for (int e = threadIdx.x; e < 12 * nstage; e += 4 * SPB) {
+      const int comp = e / nstage, j = e - comp * nstage;
+      const int rr = j / ex.lx, xx = j - rr * ex.lx;
+      int ys = y0 - 1 + rr;
+      ys = ys < 0 ? ys + ex.ly : (ys >= ex.ly ? ys - ex.ly : ys);
+      stage[comp * nstage + j] = bld<C, SE>(v, (uint32_t)comp * cs, (uint32_t)(xx + ex.sy * ys + plane));
+    }
+  }
+  cx<C> mf[3][3];  // forward link of this thread's direction
+  load_link_c<C, LE>(U, ls, (uint32_t)q * 9u * (uint32_t)I.lstride + site, mf);
+  if (q == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xlink[(a * 3 + c) * SPB + sl] = mf[a][c];
+  }
+  __syncthreads();
+  cx<C> acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
+  const uint32_t ll = (uint32_t)q * 9u * (uint32_t)I.lstride;
+  if (q < 2) {
+    // x or y: neighbours from the staged slab
+    int jf, jb;  // staged indices of the forward and backward neighbour
+    const int jc = (row + 1) * ex.lx + c4.x;
+    if (q == 0) {
+      jf = (row + 1) * ex.lx + (c4.x + 1 == ex.lx ? 0 : c4.x + 1);
+      jb = (row + 1) * ex.lx + (c4.x == 0 ? ex.lx - 1 : c4.x - 1);
+    } else {
+      jf = jc + ex.lx;
+      jb = jc - ex.lx;
+    }
+    cx<C> u[2][3], d[2][3];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        u[sp][c] = stage[(sp * 3 + c) * nstage + jf];
+        const cx<C> x = stage[((sp + 2) * 3 + c) * nstage + jf];
+        d[sp][c] = vg5 ? -x : x;
+      }
+    hop_apply<C, false>(acc, u, d, mf, k, C(1));
+    cx<C> mb[3][3];
+    if (q == 0) {
+      const int sb = row * ex.lx + (c4.x == 0 ? ex.lx - 1 : c4.x - 1);  // slab index of x - 1
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mb[a][c] = xlink[(a * 3 + c) * SPB + sb];
+    } else {
+      const int bwd = c4.y == 0 ? site + (ex.ly - 1) * ex.sy : site - ex.sy;
+      load_link_c<C, LE>(U, ls, ll + bwd, mb);
+    }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        u[sp][c] = stage[(sp * 3 + c) * nstage + jb];
+        const cx<C> x = stage[((sp + 2) * 3 + c) * nstage + jb];
+        d[sp][c] = vg5 ? -x : x;
+      }
+    hop_apply<C, true>(acc, u, d, mb, k, C(-1));
+  } else {
+    int fwd, bwd;
+    dir_neighbours(ex, c4, site, q, fwd, bwd);
+    cx<C> u[2][3], d[2][3];
+    load_spinor<C, SE>(v, cs, fwd, vg5, u, d);
+    hop_apply<C, false>(acc, u, d, mf, k, C(1));
+    cx<C> mb[3][3];
+    load_link_c<C, LE>(U, ls, ll + bwd, mb);
+    load_spinor<C, SE>(v, cs, bwd, vg5, u, d);
+    hop_apply<C, true>(acc, u, d, mb, k, C(-1));
+  }
+  // 2. ((x + z) + (y + t)) in a fixed order
+  if (q < 2) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) slots[(q * 12 + i) * SPB + sl] = acc[i];
+  }
+  __syncthreads();
+  if (q >= 2) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const int ix = ((q - 2) * 12 + i) * SPB + sl;
+      slots[ix] = slots[ix] + acc[i];
+    }
+  }
+  __syncthreads();
+  {
+    cx<C> hop[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      hop[c] = slots[(3 * q + c) * SPB + sl] + slots[(12 + 3 * q + c) * SPB + sl];
+    const C kd = C(p.kd), kh = C(p.kh);
+    const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + site;
+    const int jc = (row + 1) * ex.lx + c4.x;
+    cx<C> res[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const cx<C> vx = stage[(3 * q + c) * nstage + jc];
+      const cx<C> x = (vg5 && lower) ? -vx : vx;
+      cx<C> y = mk<C>(kd * x.re + kh * hop[c].re, kd * x.im + kh * hop[c].im);
+      if (p.y_g5 && lower) y = -y;
+      res[c] = y;
+    }
+    cx<C> srcx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) srcx[c] = mk<C>(0, 0);
+    const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
+    if (need_src) {
+      const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(sr, e0 + c * V);
+    }
+    if (p.a != 0.0) {
+      const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
+    }
+    if (p.w_role != ROLE_NONE) {
+      const rsrc_t w = make_rsrc(vec(p.w_role), vb);
+      const C t = C(p.t);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(bldv<C, SE>(w, e0 + c * V), t);
+    }
+    if (p.mode >= MODE_SIGN) {
+      for (int e = 0; e < I.n_ev; ++e) {
+        const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(I.phi) + (int64_t)e * 12 * V, vb);
+        const double2 ce = I.c[r * I.n_ev + e];
+        const double we = I.wdefl[e];
+        const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[c] = cmadd(res[c], bldv<C, SE>(ph, e0 + c * V), d);
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        nrm[0] += double(res[c].re) * double(res[c].re) + double(res[c].im) * double(res[c].im);
+        nrm[1] += double(srcx[c].re) * double(srcx[c].re) + double(srcx[c].im) * double(srcx[c].im);
+      }
+      if (p.mode == MODE_OVERLAP || p.mode == MODE_OVERLAP_DAG) {
+        const C hp = C(0.5 * (1.0 + p.mu));
+        const C hm = (p.mode == MODE_OVERLAP && lower) ? C(-0.5 * (1.0 - p.mu)) : C(0.5 * (1.0 - p.mu));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[c] = scale(srcx[c], hp) + scale(res[c], hm);
+      }
+    }
+    const rsrc_t o = make_rsrc(vec(p.out_role), vb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bstv<C, SE>(o, e0 + c * V, res[c]);
+  }
+  if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
+    block_sum<2>(nrm, lds);
+    if (threadIdx.x == 0) {
+      I.norm_partial[(int64_t)lb * 2 + 0] = nrm[0];
+      I.norm_partial[(int64_t)lb * 2 + 1] = nrm[1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // final check of the recurrence: ||res||^2 <= bound2 ||src||^2 and finite, per right-hand side.
 // One workgroup per right-hand side sums the step kernel's block partials (fixed order).
 __global__ void __launch_bounds__(kBlock)

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -204,19 +205,19 @@ int check_spinor_call(const ovl_gauge *g, const void *out, const void *in, int n
 
 int grid_blocks(int V) { return (V + kBlock - 1) / kBlock; }
 
-// Fused step kernel launch shape: 4 threads per site, SPB sites per workgroup.  Launches that
-// cover fewer than 64K site-right-hand-sides get one-wave workgroups (SPB 16) so that the work
-// spreads over more compute units.
+// Fused step kernel launch shape, as sites per workgroup: 16 (one wave, one site per lane) for
+// launches under 64K site-right-hand-sides so that the work spreads over more compute units,
+// else 64 (four waves, one site per lane); from 512K site-right-hand-sides with FP32 links 128
+// (four waves, two x-adjacent sites per lane; even Lx, 16-byte aligned vectors), which measured
+// 5-7% faster there and slower for smaller lattices and BF16 links.
 int launch_spb(int64_t site_rhs) { return site_rhs >= 64 * 1024 ? 64 : 16; }
 int item_blocks(int V, int spb) { return (V + spb - 1) / spb; }
-// workgroups (over all right-hand sides) of a single-problem launch
-int single_blocks(int V, int nrhs) { return item_blocks(V, launch_spb((int64_t)V * nrhs)) * nrhs; }
 
 // t-streaming tile (ty, tz) of the step kernel's workgroup order: the largest candidate whose
 // slice Lx ty tz splits into whole workgroups and holds at most 1.25 MB of links and spinor data
 void step_tile(const Geom &g, int spb, int site_bytes, int &ty, int &tz) {
   ty = tz = 0;
-  if (spb != 64 || g.V < 64 * 1024) return;
+  if (spb < 64 || g.V < 64 * 1024) return;
   static const int cand[][2] = {{8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}};
   for (const auto &c : cand) {
     const int64_t slice = (int64_t)g.L[0] * c[0] * c[1];
@@ -244,13 +245,46 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, LaunchCfg> g_tuned;
 
-LaunchCfg default_cfg(int64_t work) { return LaunchCfg{launch_spb(work), 1, 1}; }
+LaunchCfg default_cfg(int64_t work, int prec = P_F64) {
+  const int spb = (prec == P_F32 && work >= 512 * 1024) ? 128 : launch_spb(work);
+  return LaunchCfg{spb, 1, 1};
+}
 
 LaunchCfg lookup_cfg(const Geom &g, int prec, int nrhs, int64_t work) {
   TuneKey k{{g.L[0], g.L[1], g.L[2], g.L[3]}, prec, nrhs};
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tuned.find(k);
-  return it == g_tuned.end() ? default_cfg(work) : it->second;
+  return it == g_tuned.end() ? default_cfg(work, prec) : it->second;
+}
+
+// two sites per lane need FP32 spinors, an even Lx (pairs never straddle an x line) and 16-byte
+// aligned vectors
+bool aligned16(const void *ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+bool pairs_ok(Prec prec, const StepItem *items, int n) {
+  if (prec == P_F64) return false;
+  for (int i = 0; i < n; ++i) {
+    const StepItem &it = items[i];
+    if (it.g.L[0] % 2 || !aligned16(it.psi) || !aligned16(it.phi)) return false;
+    for (int k = 0; k < 3; ++k)
+      if (!aligned16(it.buf[k])) return false;
+  }
+  return true;
+}
+LaunchCfg fit_cfg(LaunchCfg c, bool pairs) {
+  if (c.spb == 128 && !pairs && c.tiles != 2) c.spb = 64;
+  return c;
+}
+
+// slab order (tiles == 2): whole x lines, SPB = 64 NW sites = Lx ny with ny | Ly, NW = 1..4,
+// single problems only
+bool slab_ok(const Geom &g, int spb, Prec prec) {
+  if (spb % 64 || spb < 64 || spb > 256 || spb % g.L[0] || g.L[1] % (spb / g.L[0])) return false;
+  const int bytes = prec == P_F64 ? slab_lds_bytes<double>(spb, g.L[0]) : slab_lds_bytes<float>(spb, g.L[0]);
+  return bytes <= 160 * 1024 - 512;
+}
+LaunchCfg fit_slab(LaunchCfg c, const Geom &g, Prec prec, int64_t work, bool pairs) {
+  if (c.tiles == 2 && !slab_ok(g, c.spb, prec)) return fit_cfg(default_cfg(work, prec), pairs);
+  return c;
 }
 
 // workgroup order and first workgroup of every item; returns the launch's workgroup count
@@ -260,7 +294,7 @@ int plan_items(StepItem *items, int n, const LaunchCfg &cfg, int site_bytes) {
     StepItem &it = items[i];
     it.blk0 = total;
     it.ty = it.tz = 0;
-    if (cfg.tiles) step_tile(it.g, cfg.spb, site_bytes, it.ty, it.tz);
+    if (cfg.tiles == 1) step_tile(it.g, cfg.spb, site_bytes, it.ty, it.tz);
     total += item_blocks(it.g.V, cfg.spb) * it.nrhs;
   }
   return total;
@@ -278,22 +312,60 @@ int64_t items_work(const StepItem *items, int n) {
 
 // launch one step; a single-problem launch plans its item here, a table launch was planned when
 // its table was written (p.total_blocks, spb)
+template <class C, class SE, class LE, int NW>
+int launch_slab(StepArgs<false> &p, hipStream_t s) {
+  const int bytes = slab_lds_bytes<C>(64 * NW, p.item.g.L[0]);
+  static std::once_flag once;
+  static hipError_t attr = hipSuccess;
+  std::call_once(once, [] {
+    attr = hipFuncSetAttribute((const void *)step_slab_kernel<C, SE, LE, NW, false>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 512);
+  });
+  HIP_TRY(attr);
+  step_slab_kernel<C, SE, LE, NW, false><<<p.total_blocks, 256 * NW, bytes, s>>>(p);
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
+
 template <class C, class SE, class LE, bool TABLE>
-int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s) {
-  if (spb == 64)
+int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
+  if (slab) {
+    if constexpr (TABLE) {
+      return fail(OVL_EINVAL, "the slab order takes single problems");
+    } else {
+      switch (spb) {
+        case 64: return launch_slab<C, SE, LE, 1>(p, s);
+        case 128: return launch_slab<C, SE, LE, 2>(p, s);
+        case 192: return launch_slab<C, SE, LE, 3>(p, s);
+        case 256:
+          if constexpr (sizeof(C) == 4) return launch_slab<C, SE, LE, 4>(p, s);
+          return fail(OVL_EINVAL, "FP64 slab of 256 sites does not fit the LDS");
+        default: return fail(OVL_EINVAL, "slab of %d sites", spb);
+      }
+    }
+  }
+  if (spb == 128) {
+    if constexpr (std::is_same<SE, float2>::value)
+      step2_kernel<LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
+    else
+      return fail(OVL_EINVAL, "two sites per lane need FP32 spinors");
+  } else if (spb == 64) {
     step_kernel<C, SE, LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
-  else
+  } else if (spb == 16) {
     step_kernel<C, SE, LE, 16, TABLE><<<p.total_blocks, 64, 0, s>>>(p);
+  } else {
+    return fail(OVL_EINVAL, "no step kernel for %d sites per workgroup", spb);
+  }
   HIP_TRY(hipGetLastError());
   return OVL_OK;
 }
 
 template <bool TABLE>
-int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s) {
+int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
   switch (prec) {
-    case P_F64: return launch_step<double, double2, double2, TABLE>(p, spb, s);
-    case P_F32: return launch_step<float, float2, float2, TABLE>(p, spb, s);
-    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, spb, s);
+    case P_F64: return launch_step<double, double2, double2, TABLE>(p, spb, s, slab);
+    case P_F32: return launch_step<float, float2, float2, TABLE>(p, spb, s, slab);
+    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, spb, s, slab);
     default: return fail(OVL_EDTYPE, "bad precision");
   }
 }
@@ -302,10 +374,13 @@ int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s) {
 int dispatch_cfg(Prec prec, StepArgs<false> &p, const LaunchCfg &cfg, hipStream_t s) {
   p.total_blocks = plan_items(&p.item, 1, cfg, site_bytes_of(prec));
   p.remap = cfg.remap;
-  return dispatch_step(prec, p, cfg.spb, s);
+  return dispatch_step(prec, p, cfg.spb, s, cfg.tiles == 2);
 }
 int dispatch_single(Prec prec, StepArgs<false> &p, hipStream_t s) {
-  const LaunchCfg cfg = lookup_cfg(p.item.g, prec, p.item.nrhs, items_work(&p.item, 1));
+  const int64_t work = items_work(&p.item, 1);
+  const bool pairs = pairs_ok(prec, &p.item, 1);
+  const LaunchCfg cfg = fit_slab(fit_cfg(lookup_cfg(p.item.g, prec, p.item.nrhs, work), pairs),
+                                 p.item.g, prec, work, pairs);
   return dispatch_cfg(prec, p, cfg, s);
 }
 
@@ -416,8 +491,16 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   const int N = (int)p->alpha.size() - 1;
   int64_t work = 0;
   for (int j = 0; j < nj; ++j) work += (int64_t)jobs[j].g->g.V * jobs[j].nrhs;
-  const LaunchCfg cfg = TABLE ? default_cfg(work) : lookup_cfg(jobs[0].g->g, prec, jobs[0].nrhs, work);
+  bool pairs = prec != P_F64;
+  for (int j = 0; j < nj; ++j)
+    pairs = pairs && jobs[j].g->g.L[0] % 2 == 0 && aligned16(jobs[j].in) && aligned16(jobs[j].out) &&
+            (!jobs[j].d || aligned16(jobs[j].d->phi_store));
+  LaunchCfg cfg = fit_cfg(
+      TABLE ? default_cfg(work, prec) : lookup_cfg(jobs[0].g->g, prec, jobs[0].nrhs, work), pairs);
+  cfg = TABLE ? (cfg.tiles == 2 ? fit_cfg(default_cfg(work, prec), pairs) : cfg)
+              : fit_slab(cfg, jobs[0].g->g, prec, work, pairs);
   const int spb = cfg.spb;
+  const bool slab = cfg.tiles == 2;
   // scratch: [item table] then per job [vector][norm partials][projection partials][c]
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t off[kMaxBatch][4];
@@ -526,7 +609,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     args.out_role = role(k);
     args.mode = (k == 0) ? mode : MODE_STEP;
     args.mu = mu;
-    rc = dispatch_step(prec, args, spb, s);
+    rc = dispatch_step(prec, args, spb, s, slab);
     if (rc) return rc;
     if (k == 1 && run.e0 && run.e1) {
       HIP_TRY(hipEventRecord(run.e1, s));
@@ -1165,29 +1248,37 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
   LaunchCfg best{0, 0, 0};
   float best_ms = 1e30f;
   const int sb = site_bytes_of(prec);
-  for (int spb : {64, 16})
+  const bool pairs = pairs_ok(prec, &args.item, 1);
+  std::vector<LaunchCfg> cands;
+  for (int spb : {128, 64, 16})
     for (int tiles : {1, 0})
       for (int remap : {1, 0}) {
-        const LaunchCfg cfg{spb, tiles, remap};
+        if (spb == 128 && !pairs) continue;
         if (tiles) {
           int ty, tz;
           step_tile(g->g, spb, sb, ty, tz);
           if (ty == 0) continue;
         }
-        for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
-        if (rc == OVL_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
-        for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
-        if (rc == OVL_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
-        float ms = 0.f;
-        if (rc == OVL_OK && (hipEventSynchronize(e1) != hipSuccess ||
-                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-          rc = fail(OVL_EHIP, "event timing");
-        if (rc) break;
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = cfg;
-        }
+        cands.push_back(LaunchCfg{spb, tiles, remap});
       }
+  for (int spb : {64, 128, 192, 256})
+    if (slab_ok(g->g, spb, prec))
+      for (int remap : {1, 0}) cands.push_back(LaunchCfg{spb, 2, remap});
+  for (const LaunchCfg &cfg : cands) {
+    for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
+    if (rc == OVL_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
+    for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
+    if (rc == OVL_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
+    float ms = 0.f;
+    if (rc == OVL_OK && (hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(OVL_EHIP, "event timing");
+    if (rc) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
@@ -1217,9 +1308,11 @@ int ovl_autotune_load(const char *cache_path) {
   int n = 0;
   while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &L[0], &L[1], &L[2], &L[3], &prec,
                      &nrhs, &spb, &tiles, &remap, &us) == 10) {
-    if ((spb != 16 && spb != 64) || prec < 0 || prec > 2 || nrhs < 1) continue;
+    const bool ok_spb = tiles == 2 ? (spb == 64 || spb == 128 || spb == 192 || spb == 256)
+                                   : (spb == 16 || spb == 64 || spb == 128);
+    if (!ok_spb || tiles < 0 || tiles > 2 || prec < 0 || prec > 2 || nrhs < 1) continue;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{{L[0], L[1], L[2], L[3]}, prec, nrhs}] = LaunchCfg{spb, tiles != 0, remap != 0};
+    g_tuned[TuneKey{{L[0], L[1], L[2], L[3]}, prec, nrhs}] = LaunchCfg{spb, tiles, remap != 0};
     ++n;
   }
   std::fclose(f);
@@ -1230,7 +1323,10 @@ int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3])
   if (!g || !cfg_out) return fail(OVL_EINVAL, "NULL argument");
   const Prec prec = precision(spin_dt, g->store_dt);
   if (prec == P_BAD) return fail(OVL_EDTYPE, "spinor dtype %d with link storage %d", spin_dt, g->store_dt);
-  const LaunchCfg c = lookup_cfg(g->g, prec, nrhs, (int64_t)g->g.V * nrhs);
+  // vectors are taken as 16-byte aligned (torch allocations are)
+  const int64_t work = (int64_t)g->g.V * nrhs;
+  const bool pairs = prec != P_F64 && g->g.L[0] % 2 == 0;
+  const LaunchCfg c = fit_slab(fit_cfg(lookup_cfg(g->g, prec, nrhs, work), pairs), g->g, prec, work, pairs);
   cfg_out[0] = c.spb;
   cfg_out[1] = c.tiles;
   cfg_out[2] = c.remap;

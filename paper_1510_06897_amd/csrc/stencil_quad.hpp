@@ -42,6 +42,10 @@ __device__ __forceinline__ cx<C> zmul(cx<C> z, cx<C> d) {
   return mk<C>(z.re * d.re - z.im * d.im, z.re * d.im + z.im * d.re);
 }
 
+template <class C, bool DAG>
+__device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], const cx<C> d[2][3],
+                                          const cx<C> m[3][3], const DirCoef<C> &k, C sgn);
+
 // one hop: acc += (1 -+ gamma_mu) M h, M = U (forward) or U^+ (backward), neighbour at `nb`,
 // link read at `ls_site`; sgn = +1 for (1 - gamma_mu), -1 for (1 + gamma_mu)
 template <class C, class SE, class LE, bool DAG>
@@ -62,6 +66,13 @@ __device__ __forceinline__ void quad_hop(cx<C> acc[12], rsrc_t v, uint32_t cs, r
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(Um, (a * 3 + b) * ls, lsite);
+  hop_apply<C, DAG>(acc, u, d, m, k, sgn);
+}
+
+// the arithmetic of one hop on loaded data: acc += (1 -+ gamma_mu) M h
+template <class C, bool DAG>
+__device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], const cx<C> d[2][3],
+                                          const cx<C> m[3][3], const DirCoef<C> &k, C sgn) {
   const cx<C> z0 = scale(k.z0, sgn), z1 = scale(k.z1, sgn);
   const cx<C> w0 = scale(k.w0, sgn), w1 = scale(k.w1, sgn);
   cx<C> h[2][3];

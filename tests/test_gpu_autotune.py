@@ -25,7 +25,7 @@ def test_autotune_and_results(tmp_path):
         us = ovl.autotune(g, nrhs=2, cache_path=cache)
         assert us > 0
         cfg = ovl.launch_config(g, nrhs=2)
-        assert cfg[0] in (16, 64)
+        assert cfg[0] in (16, 64, 128)
         assert ovl.autotune_load(cache) == 1
         got = ovl.kernel_apply(g, torch.from_numpy(psi).cuda().to(cdt)).cpu().numpy()
         for r in range(2):

@@ -95,6 +95,125 @@ def test_kernel_mixed(ovl, dims, store):
         assert end_to_end < (1e-6 if store == "f32" else 1e-2)   # includes link rounding
 
 
+@pytest.mark.parametrize("dims,spw", [((20, 12, 12, 24), 128), ((16, 16, 16, 16), 128),
+                                      ((15, 8, 8, 72), 64)])
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_kernel_pairs(ovl, tmp_path, dims, spw, store):
+    """Two x-adjacent sites per lane (selected through a tuning-cache entry): memory order (no
+    tile divides 20 x 12 x 12), the tile order (16^4), and the one-site kernel for an odd Lx."""
+    prec = {"f32": 1, "bf16": 2}[store]
+    cache = tmp_path / "pairs.txt"
+    cache.write_text(" ".join(map(str, dims)) + f" {prec} 1 128 1 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.random_su3_field(dims, 10160, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20160)
+    u_r = latgen.round_to_f32(u) if store == "f32" else latgen.round_to_bf16(u)
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.launch_config(g, 1)[0] == spw
+    got = host(ovl.kernel_apply(g, dev(psi, torch.complex64)))
+    assert max_rel(got, ow.kop(u_r, latgen.round_to_f32(psi))) < 1e-6
+
+
+def test_kernel_pairs_unaligned_vectors(ovl, tmp_path):
+    """Vectors that are not 16-byte aligned fall back to one site per lane, same result."""
+    dims = (16, 16, 16, 16)
+    cache = tmp_path / "pairs.txt"
+    cache.write_text(" ".join(map(str, dims)) + " 1 1 128 1 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.random_su3_field(dims, 10161)
+    psi = latgen.gaussian_spinor(dims, 20161)
+    g = ovl.GaugeField(dev(u), "f32")
+    n = psi.size
+    buf = torch.zeros(2 * n + 1, dtype=torch.complex64, device="cuda")
+    x = buf[1:n + 1].view(psi.shape)
+    x.copy_(dev(psi, torch.complex64))
+    y = buf[n + 1:].view(psi.shape)
+    ovl.kernel_apply(g, x, out=y)
+    ref = ow.kop(latgen.round_to_f32(u), latgen.round_to_f32(psi))
+    assert max_rel(host(y), ref) < 1e-6
+    assert max_rel(host(ovl.kernel_apply(g, x)), ref) < 1e-6
+
+
+def test_sign_overlap_pairs_deflated(ovl, tmp_path):
+    """The final fused step (deflation, norms, overlap combine) in the two-sites-per-lane form,
+    both D and D^dagger, against the oracle."""
+    dims = (16, 16, 8, 32)
+    cache = tmp_path / "pairs.txt"
+    cache.write_text(" ".join(map(str, dims)) + " 1 1 128 1 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.smeared_field(dims, 10162, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20162)
+    phi, lam = random_basis(dims, 5, 20163)
+    alpha = och.coeffs_sign_interp(21, 0.1)
+    g = ovl.GaugeField(dev(u), "f32")
+    assert ovl.launch_config(g, 1)[0] == 128
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    x = dev(psi, torch.complex64)
+    s = host(ovl.sign_apply(g, p, x, defl=d))
+    assert rel_err(s, och.sign_apply(u, psi, alpha, LMAX, phi, lam)) < 1e-6
+    o = host(ovl.overlap_apply(g, p, x, 0.05, defl=d))
+    assert rel_err(o, oov.overlap_apply(u, psi, 0.05, alpha, LMAX, phi, lam)) < 1e-6
+    od = host(ovl.overlap_apply(g, p, x, 0.05, defl=d, dagger=True))
+    assert rel_err(od, oov.overlap_dagger_apply(u, psi, 0.05, alpha, LMAX, phi, lam)) < 1e-6
+    assert g.flags() == 0
+
+
+SLAB_CASES = [((16, 8, 4, 6), 64), ((16, 8, 6, 4), 128), ((24, 16, 2, 4), 192), ((8, 8, 4, 6), 64)]
+
+
+@pytest.mark.parametrize("dims,spb", SLAB_CASES)
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+def test_kernel_slab(ovl, tmp_path, dims, spb, store):
+    """The slab order (whole x lines staged in LDS with the periodic y halo rows), forced through
+    a tuning-cache entry, against the oracle; two right-hand sides."""
+    prec = {"f64": 0, "f32": 1, "bf16": 2}[store]
+    if store == "f64" and spb == 192:
+        pytest.skip("covered by the FP32 and BF16 cases")
+    cache = tmp_path / "slab.txt"
+    cache.write_text(" ".join(map(str, dims)) + f" {prec} 2 {spb} 2 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.random_su3_field(dims, 10170, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20170, nrhs=2)
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.launch_config(g, 2) == (spb, 2, 1)
+    if store == "f64":
+        got = host(ovl.kernel_apply(g, dev(psi)))
+        for r in range(2):
+            assert max_rel(got[r], ow.kop(u, psi[r])) < 1e-14
+        return
+    u_r = latgen.round_to_f32(u) if store == "f32" else latgen.round_to_bf16(u)
+    got = host(ovl.kernel_apply(g, dev(psi, torch.complex64)))
+    for r in range(2):
+        assert max_rel(got[r], ow.kop(u_r, latgen.round_to_f32(psi[r]))) < 1e-6
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_sign_overlap_slab_deflated(ovl, tmp_path, store):
+    """Every step of a deflated sign and overlap evaluation in the slab order."""
+    dims = (16, 8, 6, 6)
+    prec = {"f64": 0, "f32": 1}[store]
+    cache = tmp_path / "slab.txt"
+    cache.write_text(" ".join(map(str, dims)) + f" {prec} 1 128 2 1 0\n")
+    ovl.autotune_load(str(cache))
+    u = latgen.smeared_field(dims, 10171, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20171)
+    phi, lam = random_basis(dims, 4, 20172)
+    alpha = och.coeffs_sign_interp(31, 0.1)
+    cdt = torch.complex128 if store == "f64" else torch.complex64
+    tol = 1e-12 if store == "f64" else 1e-6
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.launch_config(g, 1) == (128, 2, 1)
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, store)
+    x = dev(psi, cdt)
+    s = host(ovl.sign_apply(g, p, x, defl=d))
+    assert rel_err(s, och.sign_apply(u, psi, alpha, LMAX, phi, lam)) < tol
+    o = host(ovl.overlap_apply(g, p, x, 0.05, defl=d, dagger=True))
+    assert rel_err(o, oov.overlap_dagger_apply(u, psi, 0.05, alpha, LMAX, phi, lam)) < tol
+    assert g.flags() == 0
+
+
 def c1_inputs():
     dims = (4, 4, 4, 4)
     u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 1))
