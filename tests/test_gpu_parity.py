@@ -214,6 +214,41 @@ def test_sign_overlap_slab_deflated(ovl, tmp_path, store):
     assert g.flags() == 0
 
 
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_kernel_many_rhs(ovl, store):
+    """Nine right-hand sides on 8^3x16 in one launch (four waves per workgroup, one site per
+    lane, right-hand side fastest in the workgroup order)."""
+    dims = (8, 8, 8, 16)
+    u = latgen.random_su3_field(dims, 10180, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20180, nrhs=9)
+    u_r = latgen.round_to_f32(u) if store == "f32" else latgen.round_to_bf16(u)
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.launch_config(g, 9)[0] == 64
+    got = host(ovl.kernel_apply(g, dev(psi, torch.complex64)))
+    for r in range(9):
+        assert max_rel(got[r], ow.kop(u_r, latgen.round_to_f32(psi[r]))) < 1e-6
+
+
+def test_sign_overlap_many_rhs_deflated(ovl):
+    """Six right-hand sides through a deflated sign and overlap evaluation in one launch per
+    step (per-right-hand-side projections, norms and flags)."""
+    dims = (8, 8, 8, 24)
+    u = latgen.smeared_field(dims, 10181, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20181, nrhs=6)
+    phi, lam = random_basis(dims, 3, 20182)
+    alpha = och.coeffs_sign_interp(21, 0.1)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    x = dev(psi, torch.complex64)
+    s = host(ovl.sign_apply(g, p, x, defl=d))
+    o = host(ovl.overlap_apply(g, p, x, 0.01, defl=d))
+    for r in range(6):
+        assert rel_err(s[r], och.sign_apply(u, psi[r], alpha, LMAX, phi, lam)) < 1e-6
+        assert rel_err(o[r], oov.overlap_apply(u, psi[r], 0.01, alpha, LMAX, phi, lam)) < 1e-6
+    assert g.flags() == 0
+
+
 def c1_inputs():
     dims = (4, 4, 4, 4)
     u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 1))
