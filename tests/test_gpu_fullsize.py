@@ -1,0 +1,95 @@
+"""Parity at the full sizes of the measured workloads, in the launch configurations the benchmark
+times.  The oracle cannot run the benchmark's Chebyshev degrees at these volumes in a test, so the
+polynomial degree is lowered: every launch is the same kernel in the same configuration as in the
+benchmark (the degree only sets how many steps run), and every output element is compared with
+the FP64 oracle on the same rounded inputs."""
+import numpy as np
+import pytest
+
+import latgen
+from oracle import chebyshev as och
+from oracle import deflation as odefl
+from oracle import force as oforce
+from tests.conftest import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+LMAX = 6.5
+
+
+@pytest.fixture(scope="module")
+def ovl():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    import paper_1510_06897_amd as m
+    m.load()
+    return m
+
+
+def dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to("cpu", torch.complex128).numpy()
+
+
+def test_bf16_links_24_modes_16x16x16x32(ovl):
+    """16^3x32 stout-smeared links stored in BF16, FP32 spinors, 24 deflated vectors through the
+    FP32 matrix-core projection; degree 9 instead of 399."""
+    dims = (16, 16, 16, 32)
+    u = latgen.smeared_field(dims, latgen.seed_for("gauge", 3))
+    psi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 3))
+    phi = odefl.cgs2(latgen.gaussian_spinor(dims, 30301, nrhs=24))
+    lam = np.linspace(-0.5, 0.5, 24) + 0.004
+    lmax = LMAX * (1 + 2.0 ** -6)
+    alpha = och.coeffs_sign_interp(9, 0.08)
+    g = ovl.GaugeField(dev(u), "bf16")
+    p = ovl.Polynomial(alpha, lmax)
+    d = ovl.Deflation(dev(phi), lam, "f32")
+    got = host(ovl.sign_apply(g, p, dev(psi, torch.complex64), defl=d))
+    ref = och.sign_apply(latgen.round_to_bf16(u), latgen.round_to_f32(psi), alpha, lmax,
+                         latgen.round_to_f32(phi), lam)
+    assert rel_err(got, ref) < 1e-6
+    assert g.flags() == 0
+
+
+def test_batched_mixed_volumes_full_size(ovl):
+    """12 point sources on 16^3x32 with 4 x 8^3x16 and 2 x 12^3x24 in one launch per step, FP32;
+    degree 3 instead of 299."""
+    alpha = och.coeffs_sign_interp(3, 0.05)
+    p = ovl.Polynomial(alpha, LMAX)
+    shapes = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
+    fields, probs = [], []
+    for i, (dims, nrhs) in enumerate(shapes):
+        u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 4, i))
+        if nrhs == 12:
+            src = np.stack([latgen.point_source(dims, s, c) for s in range(4) for c in range(3)])
+        else:
+            src = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 4, i), nrhs=1)
+        fields.append((u, src))
+        probs.append((ovl.GaugeField(dev(u), "f32"), dev(src, torch.complex64)))
+    outs = ovl.batch_sign_apply(p, probs)
+    for (u, src), out in zip(fields, outs):
+        got = host(out)
+        u_r, s_r = latgen.round_to_f32(u), latgen.round_to_f32(src)
+        for r in range(src.shape[0]):
+            assert rel_err(got[r], och.sign_apply(u_r, s_r[r], alpha, LMAX)) < 1e-6
+
+
+def test_force_24x24x24x48(ovl):
+    """d Re<chi, p(X) psi>/dU on 24^3x48 in FP32 with the checkpointed reverse recurrence
+    (stride ceil(sqrt 5) = 3: two segments, a partial one); degree 5 instead of 299."""
+    dims = (24, 24, 24, 48)
+    u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 5))
+    psi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5))
+    chi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5, 1))
+    alpha = och.coeffs_sign_interp(5, 0.05)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    got = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64)))
+    ref = oforce.sign_force(latgen.round_to_f32(u), latgen.round_to_f32(chi),
+                            latgen.round_to_f32(psi), alpha, LMAX)
+    assert rel_err(got, ref) < 1e-5
