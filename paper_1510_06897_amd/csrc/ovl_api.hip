@@ -1167,15 +1167,19 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
     return dispatch_single(prec, sp, s);
   };
   // forward sweep: t_0 = psi, t_1 = X psi, t_{m+1} = 2 X t_m - t_{m-1}, keeping the checkpoint
-  // vectors; the others rotate through seg(0), seg(1) (never the buffer read as stencil input)
+  // vectors; the others rotate through seg(0), seg(1) (never the buffer read as stencil input).
+  // It stops at the last checkpoint: the top segment is regenerated by the backward sweep.
+  int last_ck = 0;
+  for (int m = 0; m <= N - 1; ++m)
+    if (slot_of[m] >= 0) last_ck = m;
   HIP_TRY(hipMemcpyAsync(ck(0), psi, vec, hipMemcpyDeviceToDevice, s));
-  if (N - 1 >= 1) {
+  if (last_ck >= 1) {
     void *t1 = slot_of[1] >= 0 ? ck(1) : seg(0);
     if ((rc = xstep(t1, psi, 1.0, nullptr, 0.0, nullptr, 0.0))) return rc;
     const void *tm1 = ck(0);
     const void *tm = t1;
     int which = (t1 == seg(0)) ? 1 : 0;
-    for (int m = 1; m + 1 <= N - 1; ++m) {  // produce t_{m+1} up to t_{N-1}
+    for (int m = 1; m + 1 <= last_ck; ++m) {  // produce t_{m+1} up to the last checkpoint
       void *dst;
       if (slot_of[m + 1] >= 0) {
         dst = ck(m + 1);
