@@ -33,16 +33,6 @@ template <class T>
 __host__ __device__ __forceinline__ cx<T> scale(cx<T> a, T s) {
   return cx<T>{a.re * s, a.im * s};
 }
-// i * a
-template <class T>
-__host__ __device__ __forceinline__ cx<T> mul_i(cx<T> a) {
-  return cx<T>{-a.im, a.re};
-}
-// -i * a
-template <class T>
-__host__ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) {
-  return cx<T>{a.im, -a.re};
-}
 // acc + a * b
 template <class T>
 __host__ __device__ __forceinline__ cx<T> cmadd(cx<T> acc, cx<T> a, cx<T> b) {
@@ -60,11 +50,6 @@ __host__ __device__ __forceinline__ cx<T> cjmadd(cx<T> acc, cx<T> a, cx<T> b) {
   acc.im = fma(a.re, b.im, acc.im);
   acc.im = fma(-a.im, b.re, acc.im);
   return acc;
-}
-// a * b
-template <class T>
-__host__ __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-  return cmadd(cx<T>{T(0), T(0)}, a, b);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -275,28 +260,6 @@ struct Geom {
   int stride[4];
   int V;
 };
-
-__host__ __device__ __forceinline__ void site_coords(const Geom &g, int s, int c[4]) {
-  c[0] = s % g.L[0];
-  int r = s / g.L[0];
-  c[1] = r % g.L[1];
-  r /= g.L[1];
-  c[2] = r % g.L[2];
-  c[3] = r / g.L[2];
-}
-
-// forward and backward neighbour site indices in all four directions (periodic)
-__host__ __device__ __forceinline__ void neighbours(const Geom &g, int s, int fwd[4], int bwd[4]) {
-  int c[4];
-  site_coords(g, s, c);
-#pragma unroll
-  for (int mu = 0; mu < 4; ++mu) {
-    const int st = g.stride[mu];
-    const int wrap = (g.L[mu] - 1) * st;
-    fwd[mu] = (c[mu] + 1 == g.L[mu]) ? s - wrap : s + st;
-    bwd[mu] = (c[mu] == 0) ? s + wrap : s - st;
-  }
-}
 
 // map a workgroup id so that each of the 8 XCDs (which receive workgroups round robin) works on
 // a contiguous range of logical blocks, keeping stencil neighbours in the same L2

@@ -8,7 +8,6 @@
 
 #include "common.hpp"
 #include "stencil.hpp"
-#include "stencil_quad.hpp"
 
 namespace ovl {
 
