@@ -205,6 +205,19 @@ const char *ovl_last_error(void);
  * Synchronises the device. */
 int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear);
 
+/* Step graphs (on by default).  A sign or overlap evaluation of one problem small enough for
+ * one-wave workgroups (fewer than 64K site-right-hand-sides) and of degree >= 3 is bound by the
+ * launch rate.  The second time the same evaluation is requested (same gauge handle, polynomial
+ * handle, source and output pointers, right-hand-side count, precision, gamma5 on the source
+ * and launch configuration) its plain recurrence steps are captured into a HIP graph, which is
+ * replayed from then on; the deflation projection, the final fused step and the norm check
+ * stay direct launches.  The library keeps up to 8 such graphs, each with its own work vector
+ * (one right-hand-side set of spinors); evicting one synchronises the device.  Two calls that
+ * overlap in time and share a graph race on its work vector, as they would on their shared
+ * output.  on = 0 turns the mechanism off for later calls (cached graphs are kept).  Results
+ * are bitwise identical either way. */
+int ovl_graph_enable(int on);
+
 /* Kernel timing of the fused Chebyshev step: when enabled, every sign evaluation (sign, overlap,
  * batched sign) records one HIP event on its stream before its first plain recurrence step and
  * one after its last (the steps k = N-1 .. 1 are consecutive launches of that kernel, so the

@@ -46,6 +46,7 @@ SIGNATURES = {
     "ovl_launch_config": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
     "ovl_last_error": (ctypes.c_char_p, []),
     "ovl_status_flags": (_i, [_vp, ctypes.POINTER(ctypes.c_uint32), _i]),
+    "ovl_graph_enable": (_i, [_i]),
     "ovl_timing_enable": (_i, [_i]),
     "ovl_timing_read": (_i, [_dp, ctypes.POINTER(ctypes.c_int64)]),
     "ovl_version": (ctypes.c_char_p, []),

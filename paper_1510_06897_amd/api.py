@@ -341,6 +341,12 @@ def launch_config(g: GaugeField, nrhs: int = 1, dtype=None):
     return tuple(out)
 
 
+def graph_enable(on: bool = True):
+    """Replay the plain recurrence steps of repeated small sign evaluations from cached HIP
+    graphs (on by default; results are bitwise the same either way)."""
+    call("ovl_graph_enable", 1 if on else 0)
+
+
 def timing_enable(on: bool = True):
     call("ovl_timing_enable", 1 if on else 0)
 

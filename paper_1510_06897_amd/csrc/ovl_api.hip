@@ -115,6 +115,7 @@ struct ovl_gauge {
   Geom g;
   int store_dt;
   int device;
+  uint64_t serial;    // unique per handle (keys the step-graph cache)
   int lstride;        // elements between link components (padded, see link_stride)
   void *links;        // [4][3][3][lstride] complex in store_dt
   uint32_t *flags;    // sticky device flags
@@ -480,6 +481,86 @@ struct SignJob {
 
 constexpr int kMaxBatch = 16;
 
+// ---------------------------------------------------------------------------------------------
+// Step graphs.  A small single-problem evaluation is bound by the launch rate (its steps take a
+// few microseconds each), and a HIP graph replays a sequence of kernels faster than the same
+// launches made one by one.  The plain recurrence steps k = N-1 .. 1 of a repeated evaluation
+// (same gauge field, polynomial, source and output buffers, precision, source gamma5 and launch
+// configuration) are captured on its second occurrence and replayed from then on; the graph
+// owns the one work vector the steps use, so no allocation or memset is captured.  The deflation
+// projection, the final fused step and the norm check are launched directly around it.
+std::atomic<int> g_graphs{1};
+
+struct GraphKey {
+  int device;
+  uint64_t g_serial, p_serial;
+  const void *in;
+  void *out;
+  int nrhs, prec, src_g5, spb, tiles, remap;
+  bool operator==(const GraphKey &o) const {
+    return device == o.device && g_serial == o.g_serial && p_serial == o.p_serial && in == o.in &&
+           out == o.out && nrhs == o.nrhs && prec == o.prec && src_g5 == o.src_g5 &&
+           spb == o.spb && tiles == o.tiles && remap == o.remap;
+  }
+};
+struct GraphEntry {
+  GraphKey key;
+  void *work = nullptr;  // the odd-k recurrence vector
+  hipGraphExec_t exec = nullptr;
+  int uses = 0;
+  bool failed = false;  // capture or instantiation failed: launch directly
+  uint64_t stamp = 0;
+};
+constexpr int kGraphCache = 8;
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graph_cache;
+uint64_t g_graph_clock = 0;
+
+void graph_release(GraphEntry &e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.work) (void)hipFree(e.work);  // synchronises the device: eviction only
+  e.exec = nullptr;
+  e.work = nullptr;
+}
+
+// the cache entry for `key` (created with its work vector when absent, evicting the least
+// recently used); nullptr when the work vector cannot be allocated
+GraphEntry *graph_entry(const GraphKey &key, size_t work_bytes) {
+  for (auto &e : g_graph_cache)
+    if (e.key == key) {
+      e.stamp = ++g_graph_clock;
+      return &e;
+    }
+  if ((int)g_graph_cache.size() >= kGraphCache) {
+    auto lru = std::min_element(g_graph_cache.begin(), g_graph_cache.end(),
+                                [](const GraphEntry &a, const GraphEntry &b) { return a.stamp < b.stamp; });
+    graph_release(*lru);
+    g_graph_cache.erase(lru);
+  }
+  GraphEntry e;
+  e.key = key;
+  if (hipMalloc(&e.work, work_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  e.stamp = ++g_graph_clock;
+  g_graph_cache.push_back(e);
+  return &g_graph_cache.back();
+}
+
+// a private stream per device on which step sequences are captured (capture executes nothing)
+hipStream_t capture_stream(int device) {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(device);
+  if (it != streams.end()) return it->second;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  streams[device] = cs;
+  return cs;
+}
+
 // Clenshaw evaluation of sum_m alpha_m T_m(X) in + deflation, final combine by `mode`, for up to
 // NI problems that share the polynomial, in one launch per K application.
 // b_k = alpha_k src + 2 X b_{k+1} - b_{k+2}, k = N-1 .. 1 (b_N = alpha_N src and b_{N+1} = 0
@@ -526,6 +607,16 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   int rc = scratch_alloc(sc, total, s);
   if (rc) return rc;
   char *base = (char *)sc.p;
+  // step graph for a small single problem (the graph lock is held until its launch is enqueued)
+  std::unique_lock<std::mutex> glk(g_graph_mu, std::defer_lock);
+  GraphEntry *ge = nullptr;
+  if (!TABLE && N >= 3 && spb == 16 && g_graphs.load() != 0) {
+    GraphKey key{jobs[0].g->device, jobs[0].g->serial, p->serial, jobs[0].in, jobs[0].out,
+                 jobs[0].nrhs, (int)prec, src_g5, cfg.spb, cfg.tiles, cfg.remap};
+    glk.lock();
+    ge = graph_entry(key, (size_t)jobs[0].nrhs * 12 * jobs[0].g->g.V * elem_bytes(spin_dt));
+    if (!ge) glk.unlock();
+  }
 
   StepItem items[kMaxBatch];
   for (int j = 0; j < nj; ++j) {
@@ -534,7 +625,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     fill_item(it, J.g, J.nrhs);
     it.psi = J.in;
     it.buf[0] = J.out;
-    it.buf[1] = base + off[j][0];
+    it.buf[1] = ge ? ge->work : base + off[j][0];
     it.norm_partial = (double *)(base + off[j][1]);
     if (J.d) {
       const int V = J.g->g.V;
@@ -579,8 +670,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     run.e0 = pool_event();
     run.e1 = pool_event();
   }
-  for (int k = N - 1; k >= 0; --k) {
-    if (k == N - 1 && run.e0) HIP_TRY(hipEventRecord(run.e0, s));
+  auto set_step = [&](int k) {
     double sfac = (k == 0) ? 1.0 : 2.0;
     double a = al[k];
     if (k + 1 == N) {
@@ -609,14 +699,48 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     args.out_role = role(k);
     args.mode = (k == 0) ? mode : MODE_STEP;
     args.mu = mu;
-    rc = dispatch_step(prec, args, spb, s, slab);
-    if (rc) return rc;
-    if (k == 1 && run.e0 && run.e1) {
-      HIP_TRY(hipEventRecord(run.e1, s));
-      std::lock_guard<std::mutex> lk(g_timing_mu);
-      g_timing_events.push_back(run);
+  };
+  // plain steps k = N-1 .. 1
+  if (run.e0) HIP_TRY(hipEventRecord(run.e0, s));
+  if (ge && !ge->exec && !ge->failed && ge->uses >= 1) {
+    // second occurrence: capture the plain steps once
+    hipStream_t cs = capture_stream(jobs[0].g->device);
+    if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      for (int k = N - 1; k >= 1 && rc == OVL_OK; --k) {
+        set_step(k);
+        rc = dispatch_step(prec, args, spb, cs, slab);
+      }
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(cs, &graph);
+      if (rc == OVL_OK && ec == hipSuccess && graph &&
+          hipGraphInstantiate(&ge->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        ge->exec = nullptr;
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      if (rc) return rc;
+    }
+    if (!ge->exec) ge->failed = true;
+  }
+  if (ge) ++ge->uses;
+  if (ge && ge->exec) {
+    HIP_TRY(hipGraphLaunch(ge->exec, s));
+  } else {
+    for (int k = N - 1; k >= 1; --k) {
+      set_step(k);
+      rc = dispatch_step(prec, args, spb, s, slab);
+      if (rc) return rc;
     }
   }
+  if (glk.owns_lock()) glk.unlock();
+  if (run.e0 && run.e1) {
+    HIP_TRY(hipEventRecord(run.e1, s));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_events.push_back(run);
+  }
+  // final step: deflation correction, combine, norm partials
+  set_step(0);
+  rc = dispatch_step(prec, args, spb, s, slab);
+  if (rc) return rc;
   for (int j = 0; j < nj; ++j) {
     const SignJob &J = jobs[j];
     double bound = p->bound;
@@ -685,6 +809,7 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
   g->links = nullptr;
   g->flags = nullptr;
   g->lstride = lstride;
+  g->serial = g_poly_serial.fetch_add(1);
   hipError_t e = hipGetDevice(&g->device);
   const int64_t n = (int64_t)36 * geo.V;
   if (e == hipSuccess) e = hipMalloc(&g->links, (int64_t)36 * lstride * elem_bytes(store_dt));
@@ -1342,6 +1467,11 @@ int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear) {
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemcpy(flags, g->flags, sizeof(uint32_t), hipMemcpyDeviceToHost));
   if (clear) HIP_TRY(hipMemset(g->flags, 0, sizeof(uint32_t)));
+  return OVL_OK;
+}
+
+int ovl_graph_enable(int on) {
+  g_graphs.store(on ? 1 : 0);
   return OVL_OK;
 }
 
