@@ -54,7 +54,7 @@ enum : int { ROLE_NONE = -1, ROLE_PSI = 0, ROLE_B0 = 1, ROLE_B1 = 2, ROLE_B2 = 3
 // One lattice problem of a step launch.  A launch covers up to NI problems (different gauge
 // fields, volumes and right-hand-side counts) that share the step's coefficients.
 struct StepItem {
-  const void *U;          // packed links [36][lstride] (link storage)
+  const void *U;          // packed links, blocks of 64 sites: [V / 64][36][64] (link storage)
   const void *psi;        // source [nrhs][12][V]: the alpha_k term and the overlap combine
   void *buf[3];           // vectors addressed by role
   const void *phi;        // deflation basis [n_ev][12][V] (spinor storage), final modes
@@ -62,7 +62,7 @@ struct StepItem {
   const double *wdefl;    // [n_ev] weights
   double *norm_partial;   // [nblk * nrhs][2] or null
   Geom g;
-  int lstride;            // elements between consecutive link components (>= V, padded)
+  int lstride;            // elements between consecutive link components inside a block (64)
   // Workgroup order.  ty > 0: the (x, y, z) volume is cut into tiles of Lx x ty x tz sites
   // (whole x lines); consecutive workgroups cover one t-slice of a tile, then the same tile at
   // t + 1, ... through all t, then the next tile.  The t-, z- and y-neighbours a workgroup reads
@@ -186,13 +186,13 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
 #pragma unroll
     for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
     if (active) {
-      const rsrc_t U = make_rsrc(I.U, 36u * ls);
+      const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
       int fwd, bwd;
       dir_neighbours(ex, c4, site, q, fwd, bwd);
       const DirCoef<C> k = dir_coef<C>(q);
       const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)I.lstride;
-      quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + site, k, C(1), vg5);
-      quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + bwd, k, C(-1), vg5);
+      quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + link_lane(site), k, C(1), vg5);
+      quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + link_lane(bwd), k, C(-1), vg5);
     }
 #pragma unroll
     for (int i = 0; i < 12; ++i) part[q][i][sl] = acc[i];
@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
 #pragma unroll
     for (int i = 0; i < 12; ++i) accA[i] = accB[i] = mk<C>(0, 0);
     if (active) {
-      const rsrc_t U = make_rsrc(I.U, 36u * ls);
+      const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
       const DirCoef<C> k = dir_coef<C>(q);
       const uint32_t ll = (uint32_t)q * 9u * (uint32_t)I.lstride;
       if (q == 0) {
@@ -375,7 +375,7 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
         {
           cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
           load_spinor_pair<SE>(v, cs, s0, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + s0, m0, m1);
+          load_link_pair<LE>(U, ls, ll + link_lane(s0), m0, m1);
           hop_apply<C, false>(accA, u1, d1, m0, k, C(1));  // x:     psi(x + 1), U(x)
           hop_apply<C, true>(accB, u0, d0, m0, k, C(-1));  // x + 1: psi(x), U(x)^+
           cx<C> un[2][3], dn[2][3];
@@ -385,7 +385,7 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
         {
           cx<C> up[2][3], dp[2][3], mp[3][3];
           load_spinor<C, SE>(v, cs, xp, vg5, up, dp);
-          load_link<LE>(U, ls, ll + xp, mp);
+          load_link<LE>(U, ls, ll + link_lane(xp), mp);
           hop_apply<C, true>(accA, up, dp, mp, k, C(-1));  // x: psi(x - 1), U(x - 1)^+
         }
       } else {
@@ -394,14 +394,14 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
         {
           cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
           load_spinor_pair<SE>(v, cs, fwd, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + s0, m0, m1);
+          load_link_pair<LE>(U, ls, ll + link_lane(s0), m0, m1);
           hop_apply<C, false>(accA, u0, d0, m0, k, C(1));
           hop_apply<C, false>(accB, u1, d1, m1, k, C(1));
         }
         {
           cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
           load_spinor_pair<SE>(v, cs, bwd, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + bwd, m0, m1);
+          load_link_pair<LE>(U, ls, ll + link_lane(bwd), m0, m1);
           hop_apply<C, true>(accA, u0, d0, m0, k, C(-1));
           hop_apply<C, true>(accB, u1, d1, m1, k, C(-1));
         }
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
   double nrm[2] = {0.0, 0.0};
   const rsrc_t v = make_rsrc(vec(p.v_role), vb);
   const bool vg5 = p.v_g5 != 0;
-  const rsrc_t U = make_rsrc(I.U, 36u * ls);
+  const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
   const DirCoef<C> k = dir_coef<C>(q);
   // 1. stage rows y0 - 1 .. y0 + ny of this (z, t), all 12 components (raw, gamma5 on use);
   //    consecutive threads read consecutive sites of a row
@@ -582,7 +582,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
     }
   }
   cx<C> mf[3][3];  // forward link of this thread's direction
-  load_link_c<C, LE>(U, ls, (uint32_t)q * 9u * (uint32_t)I.lstride + site, mf);
+  load_link_c<C, LE>(U, ls, (uint32_t)q * 9u * (uint32_t)I.lstride + link_lane(site), mf);
   if (q == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -624,7 +624,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
         for (int c = 0; c < 3; ++c) mb[a][c] = xlink[(a * 3 + c) * SPB + sb];
     } else {
       const int bwd = c4.y == 0 ? site + (ex.ly - 1) * ex.sy : site - ex.sy;
-      load_link_c<C, LE>(U, ls, ll + bwd, mb);
+      load_link_c<C, LE>(U, ls, ll + link_lane(bwd), mb);
     }
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -642,7 +642,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
     load_spinor<C, SE>(v, cs, fwd, vg5, u, d);
     hop_apply<C, false>(acc, u, d, mf, k, C(1));
     cx<C> mb[3][3];
-    load_link_c<C, LE>(U, ls, ll + bwd, mb);
+    load_link_c<C, LE>(U, ls, ll + link_lane(bwd), mb);
     load_spinor<C, SE>(v, cs, bwd, vg5, u, d);
     hop_apply<C, true>(acc, u, d, mb, k, C(-1));
   }
@@ -954,14 +954,13 @@ __global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, i
   if (k < n) cvt(src[k], dst[k]);
 }
 
-// links [36][V] (caller layout) -> [36][lstride] in the storage format
+// links [36][V] (caller layout) -> blocks [V / 64][36][64] in the storage format
 template <class S, class D>
-__global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst, int V,
-                                  int lstride) {
+__global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst, int V) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (int64_t)36 * V) return;
   const int64_t comp = k / V, site = k - comp * V;
-  cvt(src[k], dst[comp * lstride + site]);
+  cvt(src[k], dst[(int64_t)link_lane((uint32_t)site) + comp * 64]);
 }
 
 // ---------------------------------------------------------------------------------------------

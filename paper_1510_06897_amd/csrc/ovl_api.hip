@@ -116,8 +116,8 @@ struct ovl_gauge {
   int store_dt;
   int device;
   uint64_t serial;    // unique per handle (keys the step-graph cache)
-  int lstride;        // elements between link components (padded, see link_stride)
-  void *links;        // [4][3][3][lstride] complex in store_dt
+  int lstride;        // elements between link components inside a block (kLinkBlock)
+  void *links;        // [ceil(V / 64)][4 * 3 * 3][64] complex in store_dt
   uint32_t *flags;    // sticky device flags
 };
 
@@ -171,15 +171,8 @@ Prec precision(int spin_dt, int store_dt) {
   return P_BAD;
 }
 
-// Component stride of the packed links: at least V elements, rounded so that the stride in bytes
-// is an odd multiple of 256.  With a stride of V elements the 36 components of one site sit a
-// multiple of a large power of two apart (V = 2^17 for 16^3x32) and compete for the same L2 sets;
-// the odd multiple spreads them over channels and sets.
-int link_stride(int V, int esize) {
-  int64_t bytes = ((int64_t)V * esize + 255) / 256 * 256;
-  if ((bytes / 256) % 2 == 0) bytes += 256;
-  return (int)(bytes / esize);
-}
+// Elements between consecutive link components inside a 64-site block (see link_lane).
+constexpr int kLinkBlock = 64;
 
 // every array a kernel addresses through one buffer resource must span < 4 GiB
 bool fits_u32(uint64_t n_elems, int dt) { return n_elems * (uint64_t)elem_bytes(dt) < (1ull << 32); }
@@ -798,8 +791,9 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
   if (in_dt != OVL_F64 && in_dt != OVL_F32) return fail(OVL_EDTYPE, "link input dtype %d", in_dt);
   if (store_dt != OVL_F64 && store_dt != OVL_F32 && store_dt != OVL_BF16)
     return fail(OVL_EDTYPE, "link storage dtype %d", store_dt);
-  const int lstride = link_stride(geo.V, elem_bytes(store_dt));
-  if (!fits_u32(36ull * lstride, store_dt))
+  const int lstride = kLinkBlock;
+  const int64_t nlink = (int64_t)(geo.V + 63) / 64 * 36 * 64;  // elements, whole blocks
+  if (!fits_u32((uint64_t)nlink, store_dt))
     return fail(OVL_EDIMS, "links of %d sites exceed 4 GiB", geo.V);
   hipStream_t s = as_stream(stream);
   ovl_gauge *g = new (std::nothrow) ovl_gauge();
@@ -812,7 +806,7 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
   g->serial = g_poly_serial.fetch_add(1);
   hipError_t e = hipGetDevice(&g->device);
   const int64_t n = (int64_t)36 * geo.V;
-  if (e == hipSuccess) e = hipMalloc(&g->links, (int64_t)36 * lstride * elem_bytes(store_dt));
+  if (e == hipSuccess) e = hipMalloc(&g->links, nlink * elem_bytes(store_dt));
   if (e == hipSuccess) e = hipMalloc((void **)&g->flags, 256);
   if (e == hipSuccess) e = hipMemsetAsync(g->flags, 0, 256, s);
   if (e == hipSuccess) {
@@ -821,14 +815,14 @@ int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, 
     const int V = geo.V;
     if (in_dt == OVL_F64) {
       const double2 *src = (const double2 *)U_dev;
-      if (store_dt == OVL_F64) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, V, lstride);
-      else if (store_dt == OVL_F32) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, V, lstride);
-      else pack_links_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, V, lstride);
+      if (store_dt == OVL_F64) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, V);
+      else if (store_dt == OVL_F32) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, V);
+      else pack_links_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, V);
     } else {
       const float2 *src = (const float2 *)U_dev;
-      if (store_dt == OVL_F64) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, V, lstride);
-      else if (store_dt == OVL_F32) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, V, lstride);
-      else pack_links_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, V, lstride);
+      if (store_dt == OVL_F64) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (double2 *)g->links, V);
+      else if (store_dt == OVL_F32) pack_links_kernel<<<blocks, threads, 0, s>>>(src, (float2 *)g->links, V);
+      else pack_links_kernel<<<blocks, threads, 0, s>>>(src, (bf16c *)g->links, V);
     }
     e = hipGetLastError();
   }
