@@ -12,7 +12,9 @@ literal NumPy implementation in complex128 of what the paper defines:
 * ``overlap``    -- D[mu] = 1/2 (1 + mu + (1 - mu) gamma5 sign(K)) (Sec. 2, eq. 1) and its adjoint;
 * ``force``      -- the gauge-link derivative of Re<chi, p(K/lmax) psi> (reverse mode through the
                     forward recurrence) and the D_W link vector-Jacobian product;
-* ``eigen``      -- low eigenpairs of K (dense for tiny lattices, ARPACK otherwise).
+* ``eigen``      -- low eigenpairs of K (dense for tiny lattices, ARPACK otherwise);
+* ``solver``     -- D[mu] x = b by conjugate gradients on the normal equations, and the dense
+                    matrix of D[mu] for tiny lattices.
 
 Array conventions are those of ``latgen``: ``U[mu, a, b, t, z, y, x]`` and
 ``psi[..., s, c, t, z, y, x]``, periodic boundaries in all four directions, chiral gamma basis.
