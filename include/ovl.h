@@ -176,6 +176,29 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G_dev, const void *chi, const 
 int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const void *chi,
                    const void *psi, int ckpt_stride, int spin_dt, void *stream);
 
+/* ---- overlap inversion ---------------------------------------------------------------------- */
+
+/* Solve D[mu] x = b for one FP64 vector (Sec. 2: the overlap operator exists to be inverted; the
+ * paper's solver timings are Table 5).  Method: defect correction in FP64 around conjugate
+ * gradients on the normal equations D^+ D dx = D^+ r.  The inner CG runs in the precision of
+ * (g_in, d_in) -- FP32 spinors with FP32 or BF16 links -- or, when g_in is NULL, in FP64 with
+ * (g, d); each outer pass recomputes the true residual r = b - D x with (g, d) in FP64.
+ *   g      gauge handle with FP64 link storage; p polynomial; d deflation (nullable, FP64);
+ *   x, b   device [4][3][T][Z][Y][X] complex FP64; x is overwritten (starts from 0); x != b;
+ *   g_in   nullable gauge handle of the same field in FP32 or BF16 storage; d_in its deflation
+ *          (nullable, FP32 storage);
+ *   tol    target ||b - D x|| / ||b|| (> 0); max_iter bound on inner CG iterations (each two
+ *          overlap applications);
+ *   iters_out, resid_out (nullable) receive the inner iterations used and the final relative
+ *          residual.
+ * Synchronises the stream at every inner iteration (the CG scalars are formed on the host);
+ * allocates 2 FP64 and 6 inner-precision vectors of work space.  Errors: EINVAL, EDIMS, EDTYPE,
+ * EALIAS, ENONFINITE, ENOMEM, EHIP; EDIVERGED if the residual target is not reached within
+ * max_iter (x then holds the last iterate) or CG loses positivity. */
+int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                      void *x, const void *b, const ovl_gauge *g_in, const ovl_defl *d_in,
+                      double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
+
 /* ---- launch tuning ------------------------------------------------------------------------ */
 
 /* Measure the fused stencil kernel on this gauge field for nrhs right-hand sides of spin_dt over

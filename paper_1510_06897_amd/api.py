@@ -220,6 +220,25 @@ def overlap_apply(g: GaugeField, poly: Polynomial, psi, mu: float, defl: Deflati
     return out
 
 
+def overlap_solve(g: GaugeField, poly: Polynomial, b, mu: float, defl: Deflation = None,
+                  g_inner: GaugeField = None, defl_inner: Deflation = None, tol: float = 1e-10,
+                  max_iter: int = 10000, out=None):
+    """x with D[mu] x = b (FP64): FP64 defect correction around CG on the normal equations, the
+    CG in the precision of g_inner (FP32 or BF16 links) when given.  Returns (x, iterations,
+    relative residual); raises OvlError (OVL_EDIVERGED) if tol is not reached."""
+    if b.dtype != torch.complex128:
+        raise TypeError("b must be complex128")
+    _check_spinor(b, g.dims)
+    x = _out_like(b, out)
+    it = ctypes.c_int(0)
+    res = ctypes.c_double(0)
+    call("ovl_overlap_solve", g.handle, poly._h, defl._h if defl is not None else None, float(mu),
+         _ptr(x), _ptr(b), g_inner.handle if g_inner is not None else None,
+         defl_inner._h if defl_inner is not None else None, float(tol), int(max_iter),
+         ctypes.byref(it), ctypes.byref(res), _stream())
+    return x, it.value, res.value
+
+
 def batch_sign_apply(poly: Polynomial, problems, outs=None):
     """sum_m alpha_m T_m(X_i) psi_i for a list of (GaugeField, psi) problems in one launch per
     K application (Sec. 2, eq. 3 without deflation).  Returns the list of outputs."""

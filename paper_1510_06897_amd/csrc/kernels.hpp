@@ -954,6 +954,36 @@ __global__ void convert_kernel(const S *__restrict__ src, D *__restrict__ dst, i
   if (k < n) cvt(src[k], dst[k]);
 }
 
+// vector algebra of the overlap solver, n complex elements:
+//   out = a x + b y  (complex a, b; a null x or y drops its term; out may alias x or y)
+template <class C, class SE>
+__global__ void axpby_kernel(const SE *x, double2 a, const SE *y, double2 b, SE *out, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  cx<C> r = mk<C>(0, 0);
+  if (x) r = cmadd(r, mk<C>(C(a.x), C(a.y)), load_c<C>(x, k));
+  if (y) r = cmadd(r, mk<C>(C(b.x), C(b.y)), load_c<C>(y, k));
+  store_c<C>(out, k, r);
+}
+//   dst = s src  (real s, converting between FP64 and FP32)
+template <class S, class D>
+__global__ void scale_convert_kernel(const S *__restrict__ src, D *__restrict__ dst, double s,
+                                     int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const cx<double> v = load_c<double>(src, k);
+  store_c<double>(dst, k, mk<double>(v.re * s, v.im * s));
+}
+//   x += s d  (x FP64, d FP64 or FP32)
+template <class S>
+__global__ void accumulate_kernel(double2 *__restrict__ x, const S *__restrict__ d, double s,
+                                  int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const cx<double> v = load_c<double>(d, k);
+  x[k] = make_double2(x[k].x + s * v.re, x[k].y + s * v.im);
+}
+
 // links [36][V] (caller layout) -> blocks [V / 64][36][64] in the storage format
 template <class S, class D>
 __global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst, int V) {

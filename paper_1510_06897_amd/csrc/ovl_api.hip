@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <type_traits>
@@ -1088,6 +1089,170 @@ int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
   // D^+ psi = 1/2 ((1 + mu) psi + (1 - mu) sign(K) gamma5 psi)
   return run_sign(g, p, const_cast<ovl_defl *>(d), dagger ? MODE_OVERLAP_DAG : MODE_OVERLAP, mu,
                   dagger ? 1 : 0, out, in, nrhs, spin_dt, prec, as_stream(stream));
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// overlap inversion
+namespace {
+
+// vectors of one solve: FP64 (double2) or FP32 (float2) complex, 12 V elements
+struct SolveVecs {
+  bool f64;
+  int64_t n;  // complex elements
+  hipStream_t s;
+  double2 *partial;  // projection scratch (dot products)
+  int nblk;
+  double2 *cdev;
+};
+
+unsigned vec_blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+int vaxpby(const SolveVecs &w, const void *x, std::complex<double> a, const void *y,
+           std::complex<double> b, void *out) {
+  const double2 aa = make_double2(a.real(), a.imag()), bb = make_double2(b.real(), b.imag());
+  if (w.f64)
+    axpby_kernel<double, double2><<<vec_blocks(w.n), 256, 0, w.s>>>(
+        (const double2 *)x, aa, (const double2 *)y, bb, (double2 *)out, w.n);
+  else
+    axpby_kernel<float, float2><<<vec_blocks(w.n), 256, 0, w.s>>>(
+        (const float2 *)x, aa, (const float2 *)y, bb, (float2 *)out, w.n);
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
+
+// <a, b> = a^+ b with FP64 accumulation, returned to the host (synchronises the stream)
+int vdot(const SolveVecs &w, const void *a, const void *b, int V, std::complex<double> &out) {
+  int rc = w.f64 ? project((const double2 *)a, 1, (const double2 *)b, 0, 1, V, w.partial, w.nblk,
+                           w.cdev, w.s)
+                 : project((const float2 *)a, 1, (const float2 *)b, 0, 1, V, w.partial, w.nblk,
+                           w.cdev, w.s);
+  if (rc) return rc;
+  double2 h;
+  HIP_TRY(hipMemcpyAsync(&h, w.cdev, sizeof(double2), hipMemcpyDeviceToHost, w.s));
+  HIP_TRY(hipStreamSynchronize(w.s));
+  out = std::complex<double>(h.x, h.y);
+  return OVL_OK;
+}
+
+// CG on D^+ D x = D^+ rhs (x = 0 on entry) in the precision of (g, d); stops when
+// ||D^+ (rhs - D x)|| <= tol ||D^+ rhs|| or after max_iter iterations (each two overlap applies)
+int cgnr(const SolveVecs &w, const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+         int dt, void *x, const void *rhs, void *r, void *pv, void *q, void *t, double tol,
+         int max_iter, int &iters, void *stream) {
+  iters = 0;
+  const int V = g->g.V;
+  int rc = ovl_overlap_apply(g, p, d, mu, 1, r, rhs, 1, dt, stream);  // r = c = D^+ rhs
+  if (rc) return rc;
+  if ((rc = vaxpby(w, nullptr, 0.0, nullptr, 0.0, x))) return rc;  // x = 0
+  if ((rc = vaxpby(w, r, 1.0, nullptr, 0.0, pv))) return rc;      // p = r
+  std::complex<double> z;
+  if ((rc = vdot(w, r, r, V, z))) return rc;
+  double rr = z.real();
+  const double stop = tol * tol * rr;
+  while (rr > stop && iters < max_iter) {
+    if ((rc = ovl_overlap_apply(g, p, d, mu, 0, t, pv, 1, dt, stream))) return rc;  // t = D p
+    if ((rc = ovl_overlap_apply(g, p, d, mu, 1, q, t, 1, dt, stream))) return rc;   // q = D^+ t
+    if ((rc = vdot(w, pv, q, V, z))) return rc;
+    if (!(z.real() > 0.0) || !std::isfinite(z.real()))
+      return fail(OVL_EDIVERGED, "CG lost positivity (<p, D^+ D p> = %g)", z.real());
+    const double a = rr / z.real();
+    if ((rc = vaxpby(w, x, 1.0, pv, a, x))) return rc;   // x += a p
+    if ((rc = vaxpby(w, r, 1.0, q, -a, r))) return rc;   // r -= a q
+    if ((rc = vdot(w, r, r, V, z))) return rc;
+    const double rr_new = z.real();
+    if ((rc = vaxpby(w, r, 1.0, pv, rr_new / rr, pv))) return rc;  // p = r + beta p
+    rr = rr_new;
+    ++iters;
+  }
+  return OVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// D[mu] x = b for one FP64 vector: defect correction in FP64 around CG on the normal equations,
+// run in the precision of (g_in, d_in) (FP32 or BF16-link storage) or of (g, d) when g_in is NULL
+int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                      void *x, const void *b, const ovl_gauge *g_in, const ovl_defl *d_in,
+                      double tol, int max_iter, int *iters_out, double *resid_out, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, x, b, 1, OVL_F64, prec);
+  if (rc) return rc;
+  if (prec != P_F64) return fail(OVL_EDTYPE, "the outer gauge handle must store FP64 links");
+  if ((rc = check_poly(p)) || (rc = check_defl(g, d, prec))) return rc;
+  if (!std::isfinite(mu)) return fail(OVL_ENONFINITE, "mu is not finite");
+  if (!(tol > 0.0) || max_iter < 1) return fail(OVL_EINVAL, "tol must be > 0 and max_iter >= 1");
+  const ovl_gauge *gi = g_in ? g_in : g;
+  const ovl_defl *di = g_in ? d_in : d;
+  if (g_in) {
+    if (std::memcmp(g_in->g.L, g->g.L, sizeof(g->g.L)) != 0)
+      return fail(OVL_EDIMS, "inner gauge handle has other extents");
+    if (g_in->store_dt == OVL_F64) return fail(OVL_EDTYPE, "inner gauge handle stores FP64 links");
+    if ((rc = check_defl(g_in, d_in, P_F32))) return rc;
+  }
+  const bool in64 = gi->store_dt == OVL_F64;
+  const int dt_in = in64 ? OVL_F64 : OVL_F32;
+  hipStream_t s = as_stream(stream);
+  const int V = g->g.V;
+  const int64_t n = (int64_t)12 * V;
+  const size_t v64 = ((size_t)n * 16 + 255) / 256 * 256;
+  const size_t vin = ((size_t)n * (in64 ? 16 : 8) + 255) / 256 * 256;
+  const int nblk = project_blocks(V);
+  const size_t part = ((size_t)nblk * sizeof(double2) + 255) / 256 * 256;
+  Scratch sc;
+  if ((rc = scratch_alloc(sc, 2 * v64 + 6 * vin + part + 256, s))) return rc;
+  char *base = (char *)sc.p;
+  void *r64 = base, *t64 = base + v64;
+  char *ib = base + 2 * v64;
+  void *rhs = ib, *dx = ib + vin, *r = ib + 2 * vin, *pv = ib + 3 * vin, *q = ib + 4 * vin,
+       *t = ib + 5 * vin;
+  SolveVecs w64{true, n, s, (double2 *)(ib + 6 * vin), nblk, (double2 *)(ib + 6 * vin + part)};
+  SolveVecs wi = w64;
+  wi.f64 = in64;
+  std::complex<double> z;
+  if ((rc = vdot(w64, b, b, V, z))) return rc;
+  const double nb = std::sqrt(z.real());
+  if ((rc = vaxpby(w64, nullptr, 0.0, nullptr, 0.0, x))) return rc;
+  int total = 0;
+  double resid = nb > 0.0 ? 1.0 : 0.0;
+  for (int outer = 0; nb > 0.0; ++outer) {
+    if (outer == 0) {
+      if ((rc = vaxpby(w64, b, 1.0, nullptr, 0.0, r64))) return rc;  // r = b (x = 0)
+    } else {
+      if ((rc = ovl_overlap_apply(g, p, d, mu, 0, t64, x, 1, OVL_F64, stream))) return rc;
+      if ((rc = vaxpby(w64, b, 1.0, t64, -1.0, r64))) return rc;  // r = b - D x
+    }
+    if ((rc = vdot(w64, r64, r64, V, z))) return rc;
+    const double rn = std::sqrt(z.real());
+    resid = rn / nb;
+    if (resid <= tol || total >= max_iter || outer >= 40) break;
+    // inner solve of D dx = r / |r| in the inner precision
+    if (in64)
+      scale_convert_kernel<double2, double2><<<vec_blocks(n), 256, 0, s>>>((const double2 *)r64, (double2 *)rhs, 1.0 / rn, n);
+    else
+      scale_convert_kernel<double2, float2><<<vec_blocks(n), 256, 0, s>>>((const double2 *)r64, (float2 *)rhs, 1.0 / rn, n);
+    HIP_TRY(hipGetLastError());
+    const double floor = in64 ? 1e-14 : 1e-5;
+    const double tol_in = std::min(0.1, std::max(0.5 * tol / resid, floor));
+    int its = 0;
+    if ((rc = cgnr(wi, gi, p, di, mu, dt_in, dx, rhs, r, pv, q, t, tol_in, max_iter - total, its,
+                   stream)))
+      return rc;
+    total += its;
+    if (in64)
+      accumulate_kernel<double2><<<vec_blocks(n), 256, 0, s>>>((double2 *)x, (const double2 *)dx, rn, n);
+    else
+      accumulate_kernel<float2><<<vec_blocks(n), 256, 0, s>>>((double2 *)x, (const float2 *)dx, rn, n);
+    HIP_TRY(hipGetLastError());
+  }
+  if (iters_out) *iters_out = total;
+  if (resid_out) *resid_out = resid;
+  if (!(resid <= tol)) return fail(OVL_EDIVERGED, "relative residual %.3e > %.3e after %d iterations", resid, tol, total);
+  return OVL_OK;
 }
 
 int ovl_batch_sign_apply(const ovl_batch_item *items, int n_items, const ovl_poly *p,
