@@ -354,6 +354,20 @@ def main():
     ms12 = gpu_ms(torch, lambda: ovl.overlap_apply(g32, poly, psi12, MUS[0], defl=defl32,
                                                    out=out12), max(3, args.steps // 4))
     log(f"FP32 overlap (C2), 12 sources per call: {ms12:.3f} ms/call")
+
+    # D[mu] x = psi to 1e-10 on the same operator: FP64 CG, and FP32 CG inside FP64 correction
+    solves = {}
+    if not args.no_extra:
+        for label, gi, di in (("f64", None, None), ("f32_inner", g32, defl32)):
+            for mu in (MUS[1],):
+                torch.cuda.synchronize()
+                t0s = time.perf_counter()
+                _, its, sres = ovl.overlap_solve(g64, poly, psi64, mu, defl=defl64, g_inner=gi,
+                                                 defl_inner=di, tol=1e-10)
+                torch.cuda.synchronize()
+                solves[f"{label}_mu{mu}"] = {"s": round(time.perf_counter() - t0s, 4),
+                                             "cg_iterations": its, "rel_residual": sres}
+        log(f"solves: {solves}")
     vol = int(np.prod(DIMS_C2))
     k_bytes = BYTES_STEP["f32"] * vol
     k_gbps = k_bytes / (k_avg_us * 1e-6) / 1e9
@@ -467,6 +481,7 @@ def main():
         "fp64_plain": {"value": round(1e3 / ms64, 2), "ms_per_step": round(ms64, 4),
                        "speedup_f32_over_f64": round(ms64 / ms32, 3)},
         "rel_err": {"f32_vs_f64_gpu": err_32_vs_64, "vs_oracle": err_vs_oracle},
+        "c2_solve_1e-10": solves,
         "c2_12_sources": {"ms_per_call": round(ms12, 4),
                           "rhs_applies_per_s": round(12e3 / ms12, 2),
                           "note": "same operator, polynomial and deflation, 12 Gaussian sources "
