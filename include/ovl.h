@@ -125,6 +125,16 @@ int ovl_wilson_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, in
 int ovl_kernel_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, int spin_dt,
                      double m_W, void *stream);
 
+/* out = c K in + a src + b w for nrhs right-hand sides, K = gamma5 (D_W - m_W) (Sec. 2): one
+ * fused stencil launch, the building block of polynomial filters and Krylov updates.  src and w
+ * are nullable (their term is dropped); out must not overlap in (the stencil reads neighbours),
+ * and src and w must not be in; out may be src or w (each element is read before it is
+ * written).  Same layouts, dtypes and errors as ovl_kernel_apply, plus ENONFINITE for a
+ * non-finite coefficient. */
+int ovl_kernel_axpby(const ovl_gauge *g, void *out, const void *in, double c, const void *src,
+                     double a, const void *w, double b, int nrhs, int spin_dt, double m_W,
+                     void *stream);
+
 /* out = sum_m alpha_m T_m(X) in + [d != NULL] sum_i phi_i w_i phi_i^+ in  (Sec. 2, eq. 3),
  * evaluated by the Clenshaw recurrence b_k = alpha_k in + 2 X b_{k+1} - b_{k+2}, one fused
  * stencil + polynomial kernel per K application.  n_alpha - 1 K applications. */

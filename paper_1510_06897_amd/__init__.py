@@ -8,6 +8,7 @@ from ._lib import OvlError, load  # noqa: F401
 from .api import (  # noqa: F401
     M_W, Deflation, GaugeField, Polynomial, SignFunction, autotune, autotune_load,
     batch_sign_apply, cheb_sign_coeffs, defl_correct, defl_project, graph_enable, kernel_apply,
+    kernel_axpby,
     launch_config, overlap_apply, overlap_solve, sign_apply, sign_force, timing_enable,
     timing_read, wilson_apply, wilson_link_vjp,
 )

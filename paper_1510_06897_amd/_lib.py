@@ -34,6 +34,7 @@ SIGNATURES = {
     "ovl_defl_basis": (_i, [_vp, _vp, _vp]),
     "ovl_wilson_apply": (_i, [_vp, _vp, _vp, _i, _i, _d, _i, _vp]),
     "ovl_kernel_apply": (_i, [_vp, _vp, _vp, _i, _i, _d, _vp]),
+    "ovl_kernel_axpby": (_i, [_vp, _vp, _vp, _d, _vp, _d, _vp, _d, _i, _i, _d, _vp]),
     "ovl_sign_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_overlap_apply": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
     "ovl_batch_sign_apply": (_i, [_vp, _i, _vp, _i, _vp]),

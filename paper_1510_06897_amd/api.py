@@ -201,6 +201,20 @@ def kernel_apply(g: GaugeField, psi, m_w: float = M_W, out=None):
     return out
 
 
+def kernel_axpby(g: GaugeField, psi, c: float, src=None, a: float = 0.0, w=None, b: float = 0.0,
+                 m_w: float = M_W, out=None):
+    """out = c K psi + a src + b w in one fused launch (src, w optional; out may be src or w)."""
+    nrhs = _check_spinor(psi, g.dims)
+    for t in (src, w):
+        if t is not None and (t.shape != psi.shape or t.dtype != psi.dtype or not t.is_contiguous()):
+            raise ValueError("src and w must match psi in shape and dtype and be contiguous")
+    out = _out_like(psi, out)
+    call("ovl_kernel_axpby", g.handle, _ptr(out), _ptr(psi), float(c),
+         _ptr(src) if src is not None else None, float(a), _ptr(w) if w is not None else None,
+         float(b), nrhs, _spin_dtype(psi), float(m_w), _stream())
+    return out
+
+
 def sign_apply(g: GaugeField, poly: Polynomial, psi, defl: Deflation = None, out=None):
     """sum_m alpha_m T_m(X) psi + sum_i phi_i w_i phi_i^+ psi (Sec. 2, eq. 3)."""
     nrhs = _check_spinor(psi, g.dims)

@@ -1067,6 +1067,32 @@ int ovl_kernel_apply(const ovl_gauge *g, void *out, const void *in, int nrhs, in
   return dispatch_single(prec, p, as_stream(stream));
 }
 
+int ovl_kernel_axpby(const ovl_gauge *g, void *out, const void *in, double c, const void *src,
+                     double a, const void *w, double b, int nrhs, int spin_dt, double m_W,
+                     void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if (!std::isfinite(m_W) || !std::isfinite(c) || !std::isfinite(a) || !std::isfinite(b))
+    return fail(OVL_ENONFINITE, "non-finite coefficient");
+  if (src == in || w == in) return fail(OVL_EALIAS, "src or w is the stencil input");
+  StepArgs<false> p = single_args(g, nrhs);
+  p.item.psi = src;
+  p.item.buf[0] = const_cast<void *>(in);
+  p.item.buf[1] = const_cast<void *>(w);
+  p.item.buf[2] = out;
+  p.v_role = ROLE_B0;
+  p.w_role = w ? ROLE_B1 : ROLE_NONE;
+  p.out_role = ROLE_B2;
+  p.y_g5 = 1;
+  p.kd = c * (4.0 - m_W);
+  p.kh = -0.5 * c;
+  p.a = src ? a : 0.0;
+  p.t = w ? b : 0.0;
+  return dispatch_single(prec, p, as_stream(stream));
+}
+
 int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, void *out,
                    const void *in, int nrhs, int spin_dt, void *stream) {
   g_err[0] = 0;

@@ -4,18 +4,42 @@ The paper precomputes the lowest eigenpairs of K once per gauge field with a pol
 preconditioned implicitly restarted Lanczos method, at negligible cost compared with the sign
 function (Sec. 2).  This set-up routine plays that role on the device: Chebyshev-filtered
 subspace iteration (filter polynomial of K^2, block Rayleigh-Ritz with K itself so that +lambda
-and -lambda separate).  Every K application runs in the library's multi-right-hand-side kernel;
-the small dense steps of the set-up (block QR, the Rayleigh-Ritz eigenproblem) use torch's linear
+and -lambda separate).  Every K application runs in the library's multi-right-hand-side kernel,
+each filter step as one plain and one fused K launch (``kernel_axpby``); the small dense steps of
+the set-up (Gram-matrix orthonormalisation, the Rayleigh-Ritz eigenproblem) use torch's linear
 algebra on the device.  It is not part of the timed operator.
 """
 import numpy as np
 import torch
 
-from .api import M_W, GaugeField, kernel_apply
+from .api import M_W, GaugeField, kernel_apply, kernel_axpby
 
 
-def _kop(g, v, m_w):
-    return kernel_apply(g, v, m_w=m_w)
+def _kop(g, v, m_w, out=None):
+    return kernel_apply(g, v, m_w=m_w, out=out)
+
+
+def _orthonormalize(v, gen, passes=2):
+    """Rows of v (m x n) made orthonormal from their Gram matrix G = Q diag(l) Q^+ (singular
+    value QB, two passes): v <- diag(l)^(-1/2) Q^T v.  Rows in directions with a negligible Gram
+    eigenvalue (numerically dependent after the filter) are replaced by random rows first."""
+    done = 0
+    for _ in range(passes + 3):
+        gram = v.conj() @ v.T
+        lam, q = torch.linalg.eigh(0.5 * (gram + gram.conj().T))
+        weak = lam <= 1e-12 * lam[-1]
+        if bool(weak.any()):
+            k = int(weak.sum())
+            fresh = torch.complex(
+                torch.randn((k, v.shape[1]), generator=gen, dtype=torch.float64, device=v.device),
+                torch.randn((k, v.shape[1]), generator=gen, dtype=torch.float64, device=v.device))
+            v = torch.cat([q[:, k:].T @ v, fresh], dim=0)
+            continue
+        v = (q.T @ v) / torch.sqrt(lam)[:, None]
+        done += 1
+        if done == passes:
+            break
+    return v.contiguous()
 
 
 def low_modes(g: GaugeField, n_ev: int, lmax: float, block: int = None, degree: int = 60,
@@ -41,13 +65,12 @@ def low_modes(g: GaugeField, n_ev: int, lmax: float, block: int = None, degree: 
     gen = torch.Generator(device="cpu").manual_seed(seed)
     v = torch.complex(torch.randn((m, n), generator=gen, dtype=torch.float64),
                       torch.randn((m, n), generator=gen, dtype=torch.float64)).to(g.device)
+    gen_dev = torch.Generator(device=g.device).manual_seed(seed + 1)
     b = lmax * lmax
     a = cut * cut
     lam = res = None
     for it in range(iters):
-        # block orthonormalisation (columns of v^T)
-        q, _ = torch.linalg.qr(v.T)
-        v = q.T.contiguous()
+        v = _orthonormalize(v, gen_dev)
         # Rayleigh-Ritz with K
         kv = _kop(g, v.reshape((m,) + shape), m_w).reshape(m, n)
         h = v.conj() @ kv.T
@@ -64,15 +87,19 @@ def low_modes(g: GaugeField, n_ev: int, lmax: float, block: int = None, degree: 
         res = r.cpu().numpy()
         if res[:n_ev].max() < tol or it == iters - 1:
             break
+        # T_j of Z = (2 K^2 - (a + b)) / (b - a): Z x = c1 K (K x) + c0 x, one plain and one
+        # fused K launch per step, t_{j+1} = 2 Z t_j - t_{j-1} written over t_{j-1}
+        c1, c0 = 2.0 / (b - a), -(a + b) / (b - a)
         vs = v.reshape((m,) + shape)
-
-        def zop(x):
-            kx = _kop(g, x, m_w)
-            return (2.0 * _kop(g, kx, m_w) - (a + b) * x) / (b - a)
-
-        t_prev, t_cur = vs, zop(vs)
+        y = _kop(g, vs, m_w)
+        t_prev = vs
+        t_cur = kernel_axpby(g, y, c1, src=vs, a=c0, m_w=m_w)
         for _ in range(2, degree + 1):
-            t_prev, t_cur = t_cur, 2.0 * zop(t_cur) - t_prev
+            _kop(g, t_cur, m_w, out=y)
+            kernel_axpby(g, y, 2.0 * c1, src=t_cur, a=2.0 * c0, w=t_prev, b=-1.0, m_w=m_w,
+                         out=t_prev)
+            t_prev, t_cur = t_cur, t_prev
+        del y, t_prev
         # rescale so the block stays representable
         nrm = torch.linalg.vector_norm(t_cur.reshape(m, n), dim=1, keepdim=True)
         v = (t_cur.reshape(m, n) / nrm).contiguous()

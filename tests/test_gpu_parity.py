@@ -249,6 +249,31 @@ def test_sign_overlap_many_rhs_deflated(ovl):
     assert g.flags() == 0
 
 
+@pytest.mark.parametrize("store,cdt,tol", [("f64", torch.complex128, 1e-14),
+                                           ("f32", torch.complex64, 1e-6)])
+def test_kernel_axpby(ovl, store, cdt, tol):
+    """out = c K psi + a src + b w in one launch, also in place over w and over src."""
+    dims = (4, 6, 2, 8)
+    u = latgen.random_su3_field(dims, 10195)
+    psi, src, w = (latgen.gaussian_spinor(dims, 20195 + i, nrhs=2) for i in range(3))
+    if store == "f32":
+        u, psi, src, w = (latgen.round_to_f32(a) for a in (u, psi, src, w))
+    g = ovl.GaugeField(dev(u), store)
+    c, a, b = 0.37, -1.25, 0.5
+    ref = np.stack([c * ow.kop(u, psi[r]) + a * src[r] + b * w[r] for r in range(2)])
+    got = host(ovl.kernel_axpby(g, dev(psi, cdt), c, src=dev(src, cdt), a=a, w=dev(w, cdt), b=b))
+    assert max_rel(got, ref) < tol
+    wd = dev(w, cdt)
+    ovl.kernel_axpby(g, dev(psi, cdt), c, src=dev(src, cdt), a=a, w=wd, b=b, out=wd)
+    assert max_rel(host(wd), ref) < tol
+    sd = dev(src, cdt)
+    ovl.kernel_axpby(g, dev(psi, cdt), c, src=sd, a=a, out=sd)
+    ref2 = np.stack([c * ow.kop(u, psi[r]) + a * src[r] for r in range(2)])
+    assert max_rel(host(sd), ref2) < tol
+    ref3 = np.stack([c * ow.kop(u, psi[r]) for r in range(2)])
+    assert max_rel(host(ovl.kernel_axpby(g, dev(psi, cdt), c)), ref3) < tol
+
+
 def c1_inputs():
     dims = (4, 4, 4, 4)
     u = latgen.random_su3_field(dims, latgen.seed_for("gauge", 1))
