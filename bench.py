@@ -151,7 +151,8 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
     psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 3))).to(dev)
     g64 = ovl.GaugeField(u, "f64")
     gbf = ovl.GaugeField(u, "bf16")
-    lam, phi, res, eps = low_modes(g64, 24, LMAX, block=64, cut=1.0)
+    # a 128-vector block holds the 48-mode doubler cluster around the 24th eigenvalue whole
+    lam, phi, res, eps = low_modes(g64, 24, LMAX, block=128, cut=1.0)
     alpha = ovl.cheb_sign_coeffs(400, eps)
     lmax_bf = LMAX * (1 + 2.0 ** -6)
     pbf = ovl.Polynomial(alpha, lmax_bf)
