@@ -212,21 +212,26 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
 /* ---- launch tuning ------------------------------------------------------------------------ */
 
 /* Measure the fused stencil kernel on this gauge field for nrhs right-hand sides of spin_dt over
- * its launch configurations (sites per workgroup 16, 64 or 128; t-streaming tile order or memory
- * order; XCD-contiguous workgroup remap on or off), keep the fastest for every later call with the
- * same extents, precision and nrhs, and append it to the text file cache_path when not NULL
- * (one line: Lx Ly Lz Lt precision nrhs spb tiles remap microseconds).  *best_us (nullable)
- * receives the winner's time per K application.  Synchronises the stream; allocates two
- * temporary vectors.  Errors: EINVAL, EDTYPE, EDIMS, ENOMEM, EHIP. */
+ * its launch configurations and keep the fastest for every later call with the same extents,
+ * precision and nrhs.  A configuration is (spb, order, remap): order 1 = t-streaming tile order
+ * and 0 = memory order, with spb = 16, 64 (one site per lane) or 128 (two x-adjacent sites per
+ * lane); order 2 = LDS slab of whole x lines with spb = 64, 128, 192 or 256 sites (single
+ * problems; spb a multiple of Lx dividing Lx Ly); remap = XCD-contiguous workgroup ranges on or
+ * off.  The winner is appended to the text file cache_path when not NULL (one line: Lx Ly Lz Lt
+ * precision nrhs spb order remap microseconds).  *best_us (nullable) receives the winner's time
+ * per K application.  Synchronises the stream; allocates two temporary vectors.
+ * Errors: EINVAL, EDTYPE, EDIMS, ENOMEM, EHIP. */
 int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_path,
                  double *best_us, void *stream);
 /* Load configurations written by ovl_autotune; returns the number of entries read (>= 0) or
  * OVL_EINVAL when the file cannot be opened. */
 int ovl_autotune_load(const char *cache_path);
-/* The configuration the library will use: cfg_out = {sites per workgroup, tile order, remap}.
- * Sites per workgroup: 16 (one wave, one site per lane), 64 (four waves, one site per lane) or
- * 128 (four waves, two x-adjacent sites per lane: FP32 spinors, even Lx, 16-byte aligned
- * vectors; a call whose vectors are not aligned runs with 64). */
+/* The configuration the library will use: cfg_out = {sites per workgroup, order, remap}
+ * (see ovl_autotune).  Defaults: 16 sites per workgroup below 64K site-right-hand-sides, else 64
+ * in tile order, with 128 (two sites per lane) for FP32 links from 512K site-right-hand-sides
+ * when fewer than 4 right-hand sides share a lattice; remap on.  Two sites per lane need FP32
+ * spinors, an even Lx and 16-byte aligned vectors (a call whose vectors are not aligned runs
+ * with 64); a slab entry that does not fit the lattice falls back to the default. */
 int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]);
 
 /* ---- diagnostics ------------------------------------------------------------------------- */
