@@ -70,10 +70,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile", nargs="?", const="c2", choices=["c2", "dw", "proj"],
+    ap.add_argument("--profile", nargs="?", const="c2", choices=["c2", "dw", "proj", "force"],
                     help="run one part only, for rocprofv3 runs: c2 = the timed FP32 overlap "
                          "loop (default), dw = K at 24^3x48 in FP64/FP32/BF16, proj = the FP32 "
-                         "matrix-core deflation projection at 16^3x32 with 24 vectors")
+                         "matrix-core deflation projection at 16^3x32 with 24 vectors, force = "
+                         "the FP32 force at 24^3x48, degree 299")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the batched, BF16/24-mode and force measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -248,6 +249,22 @@ def profile_proj(ovl, torch, dev, reps):
     log(f"profile proj: {reps} projections")
 
 
+def profile_force(ovl, latgen, torch, dev, reps):
+    """The FP32 force d Re<chi, p(X) psi>/dU at 24^3x48, degree 299 (the bench's force figure)."""
+    dims = (24, 24, 24, 48)
+    u = torch.from_numpy(latgen.random_su3_field(dims, latgen.seed_for("gauge", 5))).to(dev)
+    psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5))).to(dev)
+    chi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5, 1))).to(dev)
+    g32 = ovl.GaugeField(u, "f32")
+    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(300, 0.05), LMAX)
+    G = torch.empty((4, 3, 3) + tuple(psi.shape[-4:]), dtype=torch.complex64, device=dev)
+    x32, c32 = psi.to(torch.complex64), chi.to(torch.complex64)
+    for _ in range(reps):
+        ovl.sign_force(g32, pf, c32, x32, out=G)
+    torch.cuda.synchronize()
+    log(f"profile force: {reps} forces")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -278,6 +295,9 @@ def main():
         return
     if args.profile == "proj":
         profile_proj(ovl, torch, dev, args.steps)
+        return
+    if args.profile == "force":
+        profile_force(ovl, latgen, torch, dev, args.steps)
         return
 
     # ---------------- inputs (untimed set-up) ----------------

@@ -1002,7 +1002,11 @@ __global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst
 // ((1 -+ gamma_mu)/2 are Hermitian projectors, so the 4-spin sums reduce to half-spinor sums.)
 // Pair i uses a_i = a0 + i * a_step and t_i = t0 + i * t_step (elements), coef = coef_first for
 // i = 0 and coef_rest otherwise.  Thread (site, mu) owns link G_mu(x): it accumulates the whole
-// segment in registers and reads and writes G once (gather only, no atomics).
+// segment in registers and reads and writes G once (gather only, no atomics).  The four
+// direction waves of a workgroup share the 64 sites: a(x) and t(x) are read from HBM once per
+// workgroup (wave mu loads spin-colour components 3 mu .. 3 mu + 2) and handed over in LDS,
+// double-buffered so that one barrier per pair suffices; the forward neighbours a(x+mu),
+// t(x+mu) are read per thread, issued before the barrier.
 template <class C, class SE, class GE>
 __global__ void __launch_bounds__(256)
     link_vjp_kernel(GE *G, const SE *a0, int64_t a_step, const SE *t0, int64_t t_step, int len,
@@ -1010,43 +1014,80 @@ __global__ void __launch_bounds__(256)
   const int mu = threadIdx.x >> 6, sl = threadIdx.x & 63;
   const int site = blockIdx.x * 64 + sl;
   const Ext4 ex = ext_of(geo);
-  if (site >= ex.V) return;
-  const Coord4 c4 = coords_of(ex, site);
+  // no early return: every thread reaches the barriers; inactive lanes load and store nothing
+  const bool active = site < ex.V;
+  const int s_site = active ? site : 0;
+  const Coord4 c4 = coords_of(ex, s_site);
   int fwd, bwd;
-  dir_neighbours(ex, c4, site, mu, fwd, bwd);
+  dir_neighbours(ex, c4, s_site, mu, fwd, bwd);
   const DirCoef<C> k = dir_coef<C>(mu);
   const uint32_t cs = (uint32_t)ex.V * elem_traits<SE>::bytes;
+  // own-site spinors of the 64 sites: [buffer][a, t][component][site]
+  __shared__ cx<C> own[2][2][12][64];
   cx<C> acc[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[i][j] = mk<C>(0, 0);
   for (int pi = 0; pi < len; ++pi) {
+    const int b = pi & 1;
     const rsrc_t ra = make_rsrc(a0 + pi * a_step, 12u * cs);
     const rsrc_t rt = make_rsrc(t0 + pi * t_step, 12u * cs);
-    cx<C> u[2][3], d[2][3], hma[2][3], hmt[2][3], hpt[2][3], hpa[2][3];
-    load_spinor<C, SE>(ra, cs, site, a_g5 != 0, u, d);
-    dir_project(u, d, k, C(1), hma);
-    load_spinor<C, SE>(rt, cs, fwd, false, u, d);
-    dir_project(u, d, k, C(1), hmt);
-    load_spinor<C, SE>(rt, cs, site, false, u, d);
-    dir_project(u, d, k, C(-1), hpt);
-    load_spinor<C, SE>(ra, cs, fwd, a_g5 != 0, u, d);
-    dir_project(u, d, k, C(-1), hpa);
-    const C cf = C(pi == 0 ? coef_first : coef_rest);
+    cx<C> hmt[2][3], hpa[2][3];
+    if (active) {
+      cx<C> u[2][3], d[2][3], xa[3], xt[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        cx<C> s = mk<C>(0, 0);
-#pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-          s = cjmadd(s, hmt[kk][j], hma[kk][i]);
-          s = cjmadd(s, hpa[kk][j], hpt[kk][i]);
-        }
-        acc[i][j] = acc[i][j] + scale(s, cf);
+      for (int c = 0; c < 3; ++c) {
+        const int comp = mu * 3 + c;
+        xa[c] = bld<C, SE>(ra, comp * cs, site);
+        xt[c] = bld<C, SE>(rt, comp * cs, site);
       }
+      load_spinor<C, SE>(rt, cs, fwd, false, u, d);
+      dir_project(u, d, k, C(1), hmt);
+      load_spinor<C, SE>(ra, cs, fwd, a_g5 != 0, u, d);
+      dir_project(u, d, k, C(-1), hpa);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int comp = mu * 3 + c;
+        own[b][0][comp][sl] = (a_g5 != 0 && mu >= 2) ? -xa[c] : xa[c];
+        own[b][1][comp][sl] = xt[c];
+      }
+    }
+    __syncthreads();
+    if (active) {
+      cx<C> hma[2][3], hpt[2][3], ou[2][3], od[2][3];
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ou[s2][c] = own[b][0][s2 * 3 + c][sl];
+          od[s2][c] = own[b][0][(s2 + 2) * 3 + c][sl];
+        }
+      dir_project(ou, od, k, C(1), hma);
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          ou[s2][c] = own[b][1][s2 * 3 + c][sl];
+          od[s2][c] = own[b][1][(s2 + 2) * 3 + c][sl];
+        }
+      dir_project(ou, od, k, C(-1), hpt);
+      const C cf = C(pi == 0 ? coef_first : coef_rest);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          cx<C> s = mk<C>(0, 0);
+#pragma unroll
+          for (int kk = 0; kk < 2; ++kk) {
+            s = cjmadd(s, hmt[kk][j], hma[kk][i]);
+            s = cjmadd(s, hpa[kk][j], hpt[kk][i]);
+          }
+          acc[i][j] = acc[i][j] + scale(s, cf);
+        }
+    }
   }
+  if (!active) return;
   const uint32_t gs = (uint32_t)ex.V * elem_traits<GE>::bytes;
   const rsrc_t rg = make_rsrc(G, 36u * gs);
   const C half = C(-0.5);
