@@ -213,13 +213,14 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
 
 /* Measure the fused stencil kernel on this gauge field for nrhs right-hand sides of spin_dt over
  * its launch configurations and keep the fastest for every later call with the same extents,
- * precision and nrhs.  A configuration is (spb, order, remap): order 1 = t-streaming tile order
- * and 0 = memory order, with spb = 16, 64 (one site per lane) or 128 (two x-adjacent sites per
- * lane); order 2 = LDS slab of whole x lines with spb = 64, 128, 192 or 256 sites (single
- * problems; spb a multiple of Lx dividing Lx Ly); remap = XCD-contiguous workgroup ranges on or
- * off.  The winner is appended to the text file cache_path when not NULL (one line: Lx Ly Lz Lt
- * precision nrhs spb order remap microseconds).  *best_us (nullable) receives the winner's time
- * per K application.  Synchronises the stream; allocates two temporary vectors.
+ * precision and nrhs.  A configuration is (spb, order, remap).  Order 1 = t-streaming tile order,
+ * 0 = memory order, with spb = 8 (eight threads per site: forward and backward hops on separate
+ * threads), 16 or 64 (four threads per site) or 128 (two x-adjacent sites per lane).  Order 2 =
+ * LDS slab of whole x lines with spb = 64, 128, 192 or 256 sites (single problems; spb a multiple
+ * of Lx dividing Lx Ly).  Remap = XCD-contiguous workgroup ranges on or off.  The winner is
+ * appended to the text file cache_path when not NULL (one line: Lx Ly Lz Lt precision nrhs spb
+ * order remap microseconds).  *best_us (nullable) receives the winner's time per K application.
+ * Synchronises the stream; allocates two temporary vectors.
  * Errors: EINVAL, EDTYPE, EDIMS, ENOMEM, EHIP. */
 int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_path,
                  double *best_us, void *stream);
@@ -227,11 +228,11 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
  * OVL_EINVAL when the file cannot be opened. */
 int ovl_autotune_load(const char *cache_path);
 /* The configuration the library will use: cfg_out = {sites per workgroup, order, remap}
- * (see ovl_autotune).  Defaults: 16 sites per workgroup below 64K site-right-hand-sides, else 64
- * in tile order, with 128 (two sites per lane) for FP32 links from 512K site-right-hand-sides
- * when fewer than 4 right-hand sides share a lattice; remap on.  Two sites per lane need FP32
- * spinors, an even Lx and 16-byte aligned vectors (a call whose vectors are not aligned runs
- * with 64); a slab entry that does not fit the lattice falls back to the default. */
+ * (see ovl_autotune).  Defaults: 8 sites per workgroup below 4K site-right-hand-sides, 16 below
+ * 64K, else 64 in tile order, with 128 (two sites per lane) for FP32 links from 512K
+ * site-right-hand-sides; remap on.  Two sites per lane need FP32 spinors, an even Lx and 16-byte
+ * aligned vectors (a call whose vectors are not aligned runs with 64); a slab entry that does not
+ * fit the lattice falls back to the default. */
 int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]);
 
 /* ---- diagnostics ------------------------------------------------------------------------- */

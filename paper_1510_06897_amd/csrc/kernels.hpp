@@ -97,14 +97,18 @@ __global__ void write_item_kernel(StepItem it, StepItem *dst) {
 // final modes add the deflation correction sum_i phi_i w_i c_i and combine into the overlap
 // operator; they also emit FP64 block partials of ||res||^2 and ||psi||^2.
 //
-// 4 * SPB threads cover SPB sites; thread (q = threadIdx.x / SPB, sl = threadIdx.x % SPB) owns
-// direction q for the hopping sum and spin component q for everything after the LDS reduction.
-// Within an item the right-hand side is the fastest logical index, so the workgroups that read
-// the same links run together and share them through L2.
-template <class C, class SE, class LE, int SPB, bool TABLE>
-__global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
+// NQ * SPB threads cover SPB sites.  NQ = 4: thread (q = threadIdx.x / SPB, sl = threadIdx.x %
+// SPB) owns direction q (both hops) for the hopping sum and spin component q for everything after
+// the LDS reduction.  NQ = 8 (small launches, bound by one wave's latency chain): threads q and
+// q + 4 take the forward and the backward hop of direction q, which halves the loads and the
+// arithmetic on each thread's path; threads q < 4 own the spin components afterwards.  Within
+// an item the right-hand side is the fastest logical index, so the workgroups that read the same
+// links run together and share them through L2.
+template <class C, class SE, class LE, int SPB, bool TABLE, int NQ = 4>
+__global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
+  static_assert(NQ == 4 || NQ == 8, "4 or 8 threads per site");
   __shared__ double lds[2 * 16];
-  __shared__ cx<C> part[4][12][SPB];  // directional partial sums
+  __shared__ cx<C> part[NQ][12][SPB];  // directional partial sums
   const int gb = xcd_block(blockIdx.x, gridDim.x, p.remap);
   int it = 0;
   if (TABLE)
@@ -118,6 +122,8 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
   const int b = lb / nrhs;
   const int q = threadIdx.x / SPB;
   const int sl = threadIdx.x % SPB;
+  const int dq = q & 3;       // direction of the thread's hop(s)
+  const bool owner = q < 4;   // owns spin component q after the exchange
   Coord4 c4;
   int site;
   bool active;
@@ -166,7 +172,7 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
   auto load_ops = [&]() {
 #pragma unroll
     for (int c = 0; c < 3; ++c) vx[c] = srcx[c] = wx[c] = mk<C>(0, 0);
-    if (!active) return;
+    if (!active || !owner) return;
 #pragma unroll
     for (int c = 0; c < 3; ++c) vx[c] = bldv<C, SE>(v, e0 + c * V);
     if (need_src) {
@@ -188,23 +194,35 @@ __global__ void __launch_bounds__(4 * SPB) step_kernel(StepArgs<TABLE> p) {
     if (active) {
       const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
       int fwd, bwd;
-      dir_neighbours(ex, c4, site, q, fwd, bwd);
-      const DirCoef<C> k = dir_coef<C>(q);
-      const uint32_t lane_links = (uint32_t)q * 9u * (uint32_t)I.lstride;
-      quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + link_lane(site), k, C(1), vg5);
-      quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + link_lane(bwd), k, C(-1), vg5);
+      dir_neighbours(ex, c4, site, dq, fwd, bwd);
+      const DirCoef<C> k = dir_coef<C>(dq);
+      const uint32_t lane_links = (uint32_t)dq * 9u * (uint32_t)I.lstride;
+      if (NQ == 4) {
+        quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + link_lane(site), k, C(1),
+                                   vg5);
+        quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + link_lane(bwd), k, C(-1),
+                                  vg5);
+      } else {
+        const bool bw = q >= 4;
+        quad_hop_sel<C, SE, LE>(acc, v, cs, U, ls, bw ? bwd : fwd,
+                                lane_links + link_lane(bw ? bwd : site), k, bw, vg5);
+      }
     }
 #pragma unroll
     for (int i = 0; i < 12; ++i) part[q][i][sl] = acc[i];
   }
   __syncthreads();
   if (!kEarly) load_ops();
-  if (active) {
+  if (active && owner) {
     cx<C> hop[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
       hop[c] = part[0][3 * q + c][sl] + part[1][3 * q + c][sl] + part[2][3 * q + c][sl] +
                part[3][3 * q + c][sl];
+      if (NQ == 8)
+        hop[c] = hop[c] + (part[4][3 * q + c][sl] + part[5][3 * q + c][sl] +
+                           part[6][3 * q + c][sl] + part[7][3 * q + c][sl]);
+    }
     const C kd = C(p.kd), kh = C(p.kh);
     cx<C> res[3];
 #pragma unroll

@@ -200,12 +200,16 @@ int check_spinor_call(const ovl_gauge *g, const void *out, const void *in, int n
 
 int grid_blocks(int V) { return (V + kBlock - 1) / kBlock; }
 
-// Fused step kernel launch shape, as sites per workgroup: 16 (one wave, one site per lane) for
-// launches under 64K site-right-hand-sides so that the work spreads over more compute units,
-// else 64 (four waves, one site per lane); from 512K site-right-hand-sides with FP32 links 128
-// (four waves, two x-adjacent sites per lane; even Lx, 16-byte aligned vectors), which measured
-// 5-7% faster there and slower for smaller lattices and BF16 links.
-int launch_spb(int64_t site_rhs) { return site_rhs >= 64 * 1024 ? 64 : 16; }
+// Fused step kernel launch shape, as sites per workgroup: 8 (one wave, eight threads per site:
+// the forward and backward hops on separate threads) under 4K site-right-hand-sides, where one
+// wave's latency chain is the step (8% faster than 16 at 4^4, no faster at 8^3 x 16, slower at
+// 12^3 x 24); 16 (one wave, four threads per site) under 64K so that the work spreads over more
+// compute units, else 64 (four waves, one site per lane); from 512K site-right-hand-sides with
+// FP32 links 128 (four waves, two x-adjacent sites per lane; even Lx, 16-byte aligned vectors),
+// which measured 5-7% faster there and slower for smaller lattices and BF16 links.
+int launch_spb(int64_t site_rhs) {
+  return site_rhs >= 64 * 1024 ? 64 : site_rhs >= 4 * 1024 ? 16 : 8;
+}
 int item_blocks(int V, int spb) { return (V + spb - 1) / spb; }
 
 // t-streaming tile (ty, tz) of the step kernel's workgroup order: the largest candidate whose
@@ -348,6 +352,8 @@ int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
     step_kernel<C, SE, LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
   } else if (spb == 16) {
     step_kernel<C, SE, LE, 16, TABLE><<<p.total_blocks, 64, 0, s>>>(p);
+  } else if (spb == 8) {
+    step_kernel<C, SE, LE, 8, TABLE, 8><<<p.total_blocks, 64, 0, s>>>(p);
   } else {
     return fail(OVL_EINVAL, "no step kernel for %d sites per workgroup", spb);
   }
@@ -604,7 +610,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   // step graph for a small single problem (the graph lock is held until its launch is enqueued)
   std::unique_lock<std::mutex> glk(g_graph_mu, std::defer_lock);
   GraphEntry *ge = nullptr;
-  if (!TABLE && N >= 3 && spb == 16 && g_graphs.load() != 0) {
+  if (!TABLE && N >= 3 && spb < 64 && !slab && g_graphs.load() != 0) {
     GraphKey key{jobs[0].g->device, jobs[0].g->serial, p->serial, jobs[0].in, jobs[0].out,
                  jobs[0].nrhs, (int)prec, src_g5, cfg.spb, cfg.tiles, cfg.remap};
     glk.lock();
@@ -1564,7 +1570,7 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
   const int sb = site_bytes_of(prec);
   const bool pairs = pairs_ok(prec, &args.item, 1);
   std::vector<LaunchCfg> cands;
-  for (int spb : {128, 64, 16})
+  for (int spb : {128, 64, 16, 8})
     for (int tiles : {1, 0})
       for (int remap : {1, 0}) {
         if (spb == 128 && !pairs) continue;
@@ -1623,7 +1629,7 @@ int ovl_autotune_load(const char *cache_path) {
   while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &L[0], &L[1], &L[2], &L[3], &prec,
                      &nrhs, &spb, &tiles, &remap, &us) == 10) {
     const bool ok_spb = tiles == 2 ? (spb == 64 || spb == 128 || spb == 192 || spb == 256)
-                                   : (spb == 16 || spb == 64 || spb == 128);
+                                   : (spb == 8 || spb == 16 || spb == 64 || spb == 128);
     if (!ok_spb || tiles < 0 || tiles > 2 || prec < 0 || prec > 2 || nrhs < 1) continue;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[TuneKey{{L[0], L[1], L[2], L[3]}, prec, nrhs}] = LaunchCfg{spb, tiles, remap != 0};

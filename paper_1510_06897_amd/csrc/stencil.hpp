@@ -110,6 +110,33 @@ __device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], co
   }
 }
 
+// one hop whose direction is chosen per lane (dag = backward: M = U^+, sgn = -1), so that the
+// forward and the backward hops of a wave run the same instructions
+template <class C, class SE, class LE>
+__device__ __forceinline__ void quad_hop_sel(cx<C> acc[12], rsrc_t v, uint32_t cs, rsrc_t Um,
+                                             uint32_t ls, uint32_t nb, uint32_t lsite,
+                                             const DirCoef<C> &k, bool dag, bool g5) {
+  cx<C> u[2][3], d[2][3];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      u[s][c] = bld<C, SE>(v, (s * 3 + c) * cs, nb);
+      cx<C> x = bld<C, SE>(v, ((s + 2) * 3 + c) * cs, nb);
+      d[s][c] = g5 ? -x : x;
+    }
+  cx<C> m[3][3], mm[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(Um, (a * 3 + b) * ls, lsite);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) mm[a][b] = dag ? mk<C>(m[b][a].re, -m[b][a].im) : m[a][b];
+  hop_apply<C, false>(acc, u, d, mm, k, dag ? C(-1) : C(1));
+}
+
 // h = projection of (u, d) by (1 - gamma_mu) (sgn = +1) or (1 + gamma_mu) (sgn = -1)
 template <class C>
 __device__ __forceinline__ void dir_project(const cx<C> u[2][3], const cx<C> d[2][3],

@@ -159,6 +159,61 @@ def test_sign_overlap_pairs_deflated(ovl, tmp_path):
     assert g.flags() == 0
 
 
+@pytest.mark.parametrize("dims", [(3, 3, 3, 3), (2, 3, 4, 5), (6, 4, 2, 4)])
+@pytest.mark.parametrize("spb", [8, 16])
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+def test_kernel_small_launch_forms(ovl, tmp_path, dims, spb, store):
+    """Eight threads per site (forward and backward hops on separate threads, 8 sites per
+    workgroup) and four (16 sites), forced through a tuning-cache entry, on volumes that leave a
+    ragged last workgroup; two right-hand sides."""
+    prec = {"f64": 0, "f32": 1, "bf16": 2}[store]
+    cache = tmp_path / "small.txt"
+    cache.write_text(" ".join(map(str, dims)) + f" {prec} 2 {spb} 0 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.random_su3_field(dims, 10175, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20175, nrhs=2)
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.launch_config(g, 2) == (spb, 0, 1)
+    if store == "f64":
+        got = host(ovl.kernel_apply(g, dev(psi)))
+        for r in range(2):
+            assert max_rel(got[r], ow.kop(u, psi[r])) < 1e-14
+        return
+    u_r = latgen.round_to_f32(u) if store == "f32" else latgen.round_to_bf16(u)
+    got = host(ovl.kernel_apply(g, dev(psi, torch.complex64)))
+    for r in range(2):
+        assert max_rel(got[r], ow.kop(u_r, latgen.round_to_f32(psi[r]))) < 1e-6
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_sign_overlap_eight_threads_deflated(ovl, tmp_path, store):
+    """Every step of a deflated sign and overlap evaluation with eight threads per site, on a
+    volume (225 sites) that leaves a ragged last workgroup."""
+    dims = (5, 5, 3, 3)
+    prec = {"f64": 0, "f32": 1}[store]
+    cache = tmp_path / "small.txt"
+    cache.write_text(" ".join(map(str, dims)) + f" {prec} 1 8 0 1 0\n")
+    ovl.autotune_load(str(cache))
+    u = latgen.smeared_field(dims, 10176, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20176)
+    phi, lam = random_basis(dims, 4, 20177)
+    alpha = och.coeffs_sign_interp(31, 0.1)
+    cdt = torch.complex128 if store == "f64" else torch.complex64
+    tol = 1e-12 if store == "f64" else 1e-6
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.launch_config(g, 1) == (8, 0, 1)
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, store)
+    x = dev(psi, cdt)
+    s = host(ovl.sign_apply(g, p, x, defl=d))
+    assert rel_err(s, och.sign_apply(u, psi, alpha, LMAX, phi, lam)) < tol
+    o = host(ovl.overlap_apply(g, p, x, 0.05, defl=d))
+    assert rel_err(o, oov.overlap_apply(u, psi, 0.05, alpha, LMAX, phi, lam)) < tol
+    od = host(ovl.overlap_apply(g, p, x, 0.05, defl=d, dagger=True))
+    assert rel_err(od, oov.overlap_dagger_apply(u, psi, 0.05, alpha, LMAX, phi, lam)) < tol
+    assert g.flags() == 0
+
+
 SLAB_CASES = [((16, 8, 4, 6), 64), ((16, 8, 6, 4), 128), ((24, 16, 2, 4), 192), ((8, 8, 4, 6), 64)]
 
 
