@@ -186,6 +186,20 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G_dev, const void *chi, const 
 int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const void *chi,
                    const void *psi, int ckpt_stride, int spin_dt, void *stream);
 
+/* ---- diagnostics of the approximation -------------------------------------------------------- */
+
+/* The exact sign function squares to one, which gives the overlap operator of Sec. 2 (eq. 1) its
+ * exact chiral symmetry (Sec. 1).  With S the polynomial of ovl_sign_apply plus the deflation of
+ * d (nullable): r_out[r] = ||S (S psi_r) - psi_r|| / ||psi_r|| for each of the nrhs right-hand
+ * sides in `in` ([nrhs][4][3][T][Z][Y][X] of spin_dt, caller-owned device memory, unchanged),
+ * 0 where psi_r = 0.  r_out: caller-owned host array of nrhs doubles.  Two sign evaluations in
+ * the storage precision of g, then S^2 psi - psi and FP64 inner products on the device.
+ * Allocates two vectors of the input's size for the duration of the call; synchronises the
+ * stream.  Errors: as ovl_sign_apply (EINVAL also for a NULL r_out), ENONFINITE for a
+ * non-finite norm. */
+int ovl_sign_residual(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, const void *in,
+                      int nrhs, int spin_dt, double *r_out, void *stream);
+
 /* ---- overlap inversion ---------------------------------------------------------------------- */
 
 /* Solve D[mu] x = b for one FP64 vector (Sec. 2: the overlap operator exists to be inverted; the

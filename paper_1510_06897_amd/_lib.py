@@ -42,6 +42,7 @@ SIGNATURES = {
     "ovl_defl_correct": (_i, [_vp, _vp, _vp, _dp, _i, _i, _vp]),
     "ovl_wilson_link_vjp": (_i, [_vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_sign_force": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
+    "ovl_sign_residual": (_i, [_vp, _vp, _vp, _vp, _i, _i, _dp, _vp]),
     "ovl_overlap_solve": (_i, [_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _d, _i,
                                ctypes.POINTER(_i), _dp, _vp]),
     "ovl_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p, _dp, _vp]),

@@ -224,6 +224,16 @@ def sign_apply(g: GaugeField, poly: Polynomial, psi, defl: Deflation = None, out
     return out
 
 
+def sign_residual(g: GaugeField, poly: Polynomial, psi, defl: Deflation = None) -> np.ndarray:
+    """||S (S psi_r) - psi_r|| / ||psi_r|| per right-hand side for the approximate sign function S
+    of sign_apply (the exact one squares to one); FP64 reductions on the device."""
+    nrhs = _check_spinor(psi, g.dims)
+    r = (ctypes.c_double * nrhs)()
+    call("ovl_sign_residual", g.handle, poly._h, defl._h if defl is not None else None,
+         _ptr(psi), nrhs, _spin_dtype(psi), r, _stream())
+    return np.array(r[:], dtype=np.float64)
+
+
 def overlap_apply(g: GaugeField, poly: Polynomial, psi, mu: float, defl: Deflation = None,
                   dagger: bool = False, out=None):
     """D[mu] psi (Sec. 2, eq. 1), or D[mu]^+ psi when dagger."""

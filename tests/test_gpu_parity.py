@@ -628,3 +628,60 @@ def test_dw_full_size_24x24x24x48(ovl):
     g32 = ovl.GaugeField(dev(u), "f32")
     got32 = host(ovl.kernel_apply(g32, dev(psi, torch.complex64)))
     assert rel_err(got32, ref) < 1e-6
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_sign_residual_vs_oracle(ovl, store):
+    """||S(S psi) - psi|| / ||psi|| (the sign function squares to one) with deflation, two
+    right-hand sides, against the oracle's S applied twice (FP32 on the same rounded inputs)."""
+    dims = (4, 4, 2, 6)
+    u = latgen.smeared_field(dims, 10180, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20180, nrhs=2)
+    psi[1] *= 3.0
+    phi, lam = random_basis(dims, 3, 20181)
+    alpha = och.coeffs_sign_interp(31, 0.1)
+    p = ovl.Polynomial(alpha, LMAX)
+    if store == "f64":
+        u_r, psi_r, phi_r = u, psi, phi
+        x = dev(psi)
+    else:
+        u_r, psi_r, phi_r = (latgen.round_to_f32(a) for a in (u, psi, phi))
+        x = dev(psi, torch.complex64)
+    g = ovl.GaugeField(dev(u), store)
+    d = ovl.Deflation(dev(phi), lam, store)
+    got = ovl.sign_residual(g, p, x, defl=d)
+    for r in range(2):
+        s1 = och.sign_apply(u_r, psi_r[r], alpha, LMAX, phi_r, lam)
+        s2 = och.sign_apply(u_r, s1, alpha, LMAX, phi_r, lam)
+        ref = np.linalg.norm(s2 - psi_r[r]) / np.linalg.norm(psi_r[r])
+        assert 1e-4 < ref < 1.0
+        if store == "f64":
+            assert abs(got[r] - ref) < 1e-10 * ref
+        else:
+            assert abs(got[r] - ref) < 1e-5
+    zero = torch.zeros_like(x)
+    assert np.all(ovl.sign_residual(g, p, zero, defl=d) == 0.0)
+
+
+def test_ginsparg_wilson_residual_gpu(ovl):
+    """At mu = 0, gamma5 D + D gamma5 - 2 D gamma5 D = -1/2 gamma5 (S^2 - 1) for any Hermitian S:
+    the Ginsparg-Wilson residual of the device's overlap operator equals half the device's
+    sign-function residual (FP64, deflated)."""
+    dims = (4, 4, 4, 4)
+    u = latgen.smeared_field(dims, 10182, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20182)
+    phi, lam = random_basis(dims, 4, 20183)
+    alpha = och.coeffs_sign_interp(31, 0.1)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f64")
+    x = dev(psi)
+    g5 = torch.tensor([1.0, 1.0, -1.0, -1.0], dtype=torch.float64, device="cuda").view(4, 1, 1, 1, 1, 1)
+    dx = ovl.overlap_apply(g, p, x, 0.0, defl=d)
+    dg5x = ovl.overlap_apply(g, p, g5 * x, 0.0, defl=d)
+    dg5dx = ovl.overlap_apply(g, p, g5 * dx, 0.0, defl=d)
+    gw = g5 * dx + dg5x - 2.0 * dg5dx
+    lhs = float(torch.linalg.vector_norm(gw) / torch.linalg.vector_norm(x))
+    rs = float(ovl.sign_residual(g, p, x, defl=d)[0])
+    assert rs > 1e-4
+    assert abs(lhs - 0.5 * rs) < 1e-10 * rs
