@@ -428,6 +428,29 @@ def main():
                      "bytes_per_site": BYTES_DW[store]}
         log(f"K 24^3x48 {store}: {us:.1f} us, {gbps:.0f} GB/s")
         gb.close()
+
+    # ---------------- sign(K) psi at 24^3x48: the recurrence in the HBM-bound regime ----------
+    sign_big = {}
+    p_big = ovl.Polynomial(ovl.cheb_sign_coeffs(DEGREE_C2, 0.05), LMAX * (1 + 2.0 ** -6))
+    for store in ("f64", "f32", "bf16"):
+        gb = ovl.GaugeField(d_ub, store)
+        x = d_pb if store == "f64" else d_pb.to(torch.complex64)
+        y = torch.empty_like(x)
+        for _ in range(2):
+            ovl.sign_apply(gb, p_big, x, out=y)
+        torch.cuda.synchronize()
+        ovl.timing_read()
+        ovl.timing_enable(True)
+        ms = gpu_ms(torch, lambda: ovl.sign_apply(gb, p_big, x, out=y), 3, warmup=0)
+        ovl.timing_enable(False)
+        k_ms_b, k_n_b = ovl.timing_read()
+        us = 1e3 * k_ms_b / k_n_b
+        gbps = BYTES_STEP[store] * vol_b / (us * 1e-6) / 1e9
+        sign_big[store] = {"ms_per_apply": round(ms, 3), "step_kernel_us": round(us, 2),
+                           "step_GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
+                           "bytes_per_site": BYTES_STEP[store]}
+        log(f"sign 24^3x48 {store}: {ms:.2f} ms/apply, step kernel {us:.1f} us, {gbps:.0f} GB/s")
+        gb.close()
     del d_ub, d_pb
 
     extra = {} if args.no_extra else measure_extra(ovl, latgen, low_modes, torch, dev)
@@ -445,7 +468,7 @@ def main():
         phi_o = odefl.cgs2(latgen.gaussian_spinor(DIMS_C2, 777, nrhs=N_EV_C2))
         lam_o = np.linspace(-0.52, 0.52, N_EV_C2) + 0.003
         alpha_o = och.coeffs_sign_interp(DEGREE_C2, eps)
-        reps = 2
+        reps = 6   # about 10 s of single-core oracle work
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=1):
             c0 = time.perf_counter()
@@ -522,6 +545,9 @@ def main():
         },
         "cpu_baseline": cpu,
         "dw_24x24x24x48": dw,
+        "sign_24x24x24x48": {"workload": "sign(K)psi on 24^3x48 near-unit links, degree 199, "
+                                         "eps 0.05, no deflation, one source",
+                             **sign_big},
     }
     line.update(extra)
     print(json.dumps(line), flush=True)
