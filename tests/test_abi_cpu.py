@@ -108,6 +108,14 @@ def test_operator_validation_before_hip(lib):
     assert lib.ovl_defl_correct(None, dummy, None, None, 1, 0, None) == -1
     assert lib.ovl_sign_force(None, None, None, dummy, dummy, 0, 0, None) == -1
     assert lib.ovl_status_flags(None, None, 0) == -1
+    assert lib.ovl_kernel_axpby(None, dummy, dummy, 1.0, None, 0.0, None, 0.0, 1, 0, 1.5, None) == -1
+    assert lib.ovl_wilson_link_vjp(None, dummy, dummy, dummy, 0, 0, None) == -1
+    assert lib.ovl_overlap_solve(None, None, None, 0.1, dummy, dummy, None, None, 1e-10, 10, None,
+                                 None, None) == -1
+    assert lib.ovl_batch_sign_apply(None, 0, None, 0, None) == -1
+    r = (ctypes.c_double * 1)()
+    assert lib.ovl_sign_residual(None, None, None, dummy, 1, 0, r, None) == -1
+    assert lib.ovl_sign_residual(None, None, None, dummy, 1, 0, None, None) == -1
     h = ctypes.c_void_p()
     lam = (ctypes.c_double * 1)(0.5)
     dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
