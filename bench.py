@@ -453,6 +453,19 @@ def main():
         gb.close()
     del d_ub, d_pb
 
+    # ---------------- measured HBM ceiling: a plain device copy of 4 GiB ----------------
+    # (read 4 GiB + write 4 GiB per copy); the stencil figures are also quoted against it
+    src_c = torch.empty(1 << 30, dtype=torch.float32, device=dev).fill_(1.0)
+    dst_c = torch.empty_like(src_c)
+    copy_ms = gpu_ms(torch, lambda: dst_c.copy_(src_c), 5)
+    copy_gbps = 2.0 * src_c.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del src_c, dst_c
+    log(f"device copy 4 GiB: {copy_ms:.2f} ms, {copy_gbps:.0f} GB/s")
+    for tbl in (dw, sign_big):
+        for v in tbl.values():
+            key = "GBps" if "GBps" in v else "step_GBps"
+            v["frac_of_copy"] = round(v[key] / copy_gbps, 4)
+
     extra = {} if args.no_extra else measure_extra(ovl, latgen, low_modes, torch, dev)
 
     # ---------------- CPU oracle baseline (bounded sample) ----------------
@@ -544,6 +557,8 @@ def main():
             "bytes_per_launch": k_bytes,
         },
         "cpu_baseline": cpu,
+        "hbm_copy_4GiB": {"GBps": round(copy_gbps, 1), "frac_of_8TBps": round(copy_gbps / HBM_PEAK_GBPS, 4),
+                          "note": "torch copy_ of a 4 GiB buffer, read + write bytes"},
         "dw_24x24x24x48": dw,
         "sign_24x24x24x48": {"workload": "sign(K)psi on 24^3x48 near-unit links, degree 199, "
                                          "eps 0.05, no deflation, one source",
