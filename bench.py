@@ -36,6 +36,9 @@ DIMS_DW = (24, 24, 24, 48)
 # algorithmic bytes per site: each link, input and output read or written once
 BYTES_STEP = {"f64": 1248, "f32": 624, "bf16": 480}   # Clenshaw step: links + 3.5 spinor streams
 BYTES_DW = {"f64": 960, "f32": 480, "bf16": 336}       # D_W / K: links + in + out
+# with two-row link reads (third row completed as for SU(3)) the links cost 2/3 of their bytes
+BYTES_STEP_R12 = {"f64": 1056, "f32": 528, "bf16": 432}
+BYTES_DW_R12 = {"f64": 768, "f32": 384, "bf16": 288}
 
 
 def counter_traffic(tag):
@@ -204,12 +207,15 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
     ms_f = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, out=G), 2)
     # one segment: every t_m is regenerated into HBM once (N vectors, 19 GB) instead of sqrt(N)
     ms_all = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=299, out=G), 2)
+    g32.reconstruct()
+    ms_r12 = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, out=G), 2)
     out["force"] = {
         "workload": "d Re<chi, p(K/lmax) psi>/dU on 24^3x48 near-unit links, degree 299, FP32, "
                     "checkpoint stride ceil(sqrt 299) = 18",
         "ms_per_force": round(ms_f, 2),
         "forces_per_s": round(1e3 / ms_f, 3),
         "ms_per_force_stride_299": round(ms_all, 2),
+        "ms_per_force_two_row_links": round(ms_r12, 2),
     }
     log(f"force 24^3x48: {ms_f:.1f} ms (stride 299: {ms_all:.1f} ms)")
     return out
@@ -427,6 +433,16 @@ def main():
                      "frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
                      "bytes_per_site": BYTES_DW[store]}
         log(f"K 24^3x48 {store}: {us:.1f} us, {gbps:.0f} GB/s")
+        # the same with two-row link reads (the field is SU(3); the check result is reported)
+        r12_dev = gb.reconstruct()
+        us2 = 1e3 * gpu_ms(torch, lambda: ovl.kernel_apply(gb, x, out=y), reps, warmup=3)
+        gbps2 = BYTES_DW_R12[store] * vol_b / (us2 * 1e-6) / 1e9
+        dw[store]["two_row_links"] = {"us_per_apply": round(us2, 2), "GBps": round(gbps2, 1),
+                                      "frac_of_8TBps": round(gbps2 / HBM_PEAK_GBPS, 4),
+                                      "bytes_per_site": BYTES_DW_R12[store],
+                                      "speedup": round(us / us2, 3),
+                                      "third_row_max_dev": r12_dev}
+        log(f"K 24^3x48 {store} two-row links: {us2:.1f} us")
         gb.close()
 
     # ---------------- sign(K) psi at 24^3x48: the recurrence in the HBM-bound regime ----------
@@ -450,6 +466,21 @@ def main():
                            "step_GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
                            "bytes_per_site": BYTES_STEP[store]}
         log(f"sign 24^3x48 {store}: {ms:.2f} ms/apply, step kernel {us:.1f} us, {gbps:.0f} GB/s")
+        gb.reconstruct()
+        ovl.sign_apply(gb, p_big, x, out=y)
+        torch.cuda.synchronize()
+        ovl.timing_read()
+        ovl.timing_enable(True)
+        ms2 = gpu_ms(torch, lambda: ovl.sign_apply(gb, p_big, x, out=y), 3, warmup=0)
+        ovl.timing_enable(False)
+        k_ms_b, k_n_b = ovl.timing_read()
+        us2 = 1e3 * k_ms_b / k_n_b
+        gbps2 = BYTES_STEP_R12[store] * vol_b / (us2 * 1e-6) / 1e9
+        sign_big[store]["two_row_links"] = {
+            "ms_per_apply": round(ms2, 3), "step_kernel_us": round(us2, 2),
+            "step_GBps": round(gbps2, 1), "frac_of_8TBps": round(gbps2 / HBM_PEAK_GBPS, 4),
+            "bytes_per_site": BYTES_STEP_R12[store], "speedup": round(ms / ms2, 3)}
+        log(f"sign 24^3x48 {store} two-row links: {ms2:.2f} ms/apply")
         gb.close()
     del d_ub, d_pb
 
@@ -463,8 +494,9 @@ def main():
     log(f"device copy 4 GiB: {copy_ms:.2f} ms, {copy_gbps:.0f} GB/s")
     for tbl in (dw, sign_big):
         for v in tbl.values():
-            key = "GBps" if "GBps" in v else "step_GBps"
-            v["frac_of_copy"] = round(v[key] / copy_gbps, 4)
+            for w in (v, v["two_row_links"]):
+                key = "GBps" if "GBps" in w else "step_GBps"
+                w["frac_of_copy"] = round(w[key] / copy_gbps, 4)
 
     extra = {} if args.no_extra else measure_extra(ovl, latgen, low_modes, torch, dev)
 

@@ -83,6 +83,16 @@ int ovl_gauge_create(ovl_gauge **g, const int32_t dims[4], const void *U_dev, in
 int ovl_gauge_destroy(ovl_gauge *g);
 /* Extents and storage dtype of a handle. */
 int ovl_gauge_info(const ovl_gauge *g, int32_t dims_out[4], int *store_dt);
+/* Two-row link reads (on = 1): every later stencil launch on this handle reads the first two
+ * rows of each link and completes the third as conj(row0 x row1), exact for SU(3) matrices, so
+ * a K application moves 2/3 of the link bytes (per site FP64 768, FP32 384, BF16 links 288 bytes
+ * instead of 960, 480, 336).  The stored third rows stay in place.  Enabling first measures on
+ * the device the largest element-wise deviation of the stored third rows from the completed ones
+ * (*max_dev, nullable) and refuses with EINVAL when it exceeds tol (links that are not SU(3) to
+ * within their storage rounding: FP64 ~1e-15, FP32 ~1e-7, BF16 ~1e-2).  on = 0 switches back to
+ * full reads.  Enabling synchronises the stream; a batch launch reads two rows only if every
+ * item's handle allows it.  Errors: EINVAL, ENOMEM, EHIP. */
+int ovl_gauge_reconstruct(ovl_gauge *g, int on, double tol, double *max_dev, void *stream);
 
 /* Polynomial of Sec. 2, eq. 3: coefficients alpha_host[0..n_alpha-1] of T_0 .. T_{n_alpha-1}
  * (FP64, copied), applied to X = gamma5 (D_W - m_W) / lmax.  n_alpha >= 2 (at least one K

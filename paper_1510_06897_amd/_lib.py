@@ -25,6 +25,7 @@ SIGNATURES = {
     "ovl_gauge_create": (_i, [ctypes.POINTER(_vp), _i32x4, _vp, _i, _i, _vp]),
     "ovl_gauge_destroy": (_i, [_vp]),
     "ovl_gauge_info": (_i, [_vp, _i32x4, ctypes.POINTER(_i)]),
+    "ovl_gauge_reconstruct": (_i, [_vp, _i, _d, _dp, _vp]),
     "ovl_poly_create": (_i, [ctypes.POINTER(_vp), _dp, _i, _d, _d]),
     "ovl_poly_destroy": (_i, [_vp]),
     "ovl_poly_eval": (_i, [_vp, _d, _dp]),

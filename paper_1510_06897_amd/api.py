@@ -92,6 +92,17 @@ class GaugeField:
     def spin_dtype(self):
         return torch.complex128 if self.store == "f64" else torch.complex64
 
+    # largest stored-vs-completed third-row deviation accepted by default, per storage dtype
+    _R12_TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 5e-2}
+
+    def reconstruct(self, on: bool = True, tol: float = None) -> float:
+        """Read links as two rows and complete the third (SU(3) fields only): checks the field on
+        the device and returns the largest third-row deviation; raises OvlError if above tol."""
+        dev = ctypes.c_double(0.0)
+        call("ovl_gauge_reconstruct", self._h, 1 if on else 0,
+             float(self._R12_TOL[self.store] if tol is None else tol), ctypes.byref(dev), _stream())
+        return float(dev.value)
+
     def flags(self, clear: bool = True) -> int:
         f = ctypes.c_uint32(0)
         call("ovl_status_flags", self._h, ctypes.byref(f), 1 if clear else 0)

@@ -52,6 +52,20 @@ __host__ __device__ __forceinline__ cx<T> cjmadd(cx<T> acc, cx<T> a, cx<T> b) {
   return acc;
 }
 
+// Third row of an SU(3) matrix from the first two: unitarity and det = 1 give
+// row2 = conj(row0 x row1).  Links kept with two rows are read as six elements and completed
+// here (the stored third row is not read).
+template <class T>
+__host__ __device__ __forceinline__ void su3_row2(cx<T> m[3][3]) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const int c = (b + 1) % 3, d = (b + 2) % 3;
+    cx<T> x = cmadd(mk<T>(T(0), T(0)), m[0][c], m[1][d]);
+    x = cmadd(x, -m[0][d], m[1][c]);
+    m[2][b] = mk<T>(x.re, -x.im);
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // storage formats of one complex element.  F64: double2, F32: float2, BF16: two bfloat16 in one
 // 32-bit word (real part in the low half).

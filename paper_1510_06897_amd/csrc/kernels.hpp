@@ -63,6 +63,7 @@ struct StepItem {
   double *norm_partial;   // [nblk * nrhs][2] or null
   Geom g;
   int lstride;            // elements between consecutive link components inside a block (64)
+  int r12;                // the field allows two-row link reads (SU(3) within its tolerance)
   // Workgroup order.  ty > 0: the (x, y, z) volume is cut into tiles of Lx x ty x tz sites
   // (whole x lines); consecutive workgroups cover one t-slice of a tile, then the same tile at
   // t + 1, ... through all t, then the next tile.  The t-, z- and y-neighbours a workgroup reads
@@ -81,6 +82,7 @@ struct StepArgs {
   double kd, kh, a, t, mu;
   int v_role, w_role, out_role;
   int v_g5, src_g5, y_g5, mode, remap, n_items;
+  int r12;                // TABLE: every item allows two-row link reads
   int total_blocks;       // workgroups of the launch
   const StepItem *table;  // TABLE: n_items items in device memory
   StepItem item;          // !TABLE: the one problem
@@ -104,7 +106,7 @@ __global__ void write_item_kernel(StepItem it, StepItem *dst) {
 // arithmetic on each thread's path; threads q < 4 own the spin components afterwards.  Within
 // an item the right-hand side is the fastest logical index, so the workgroups that read the same
 // links run together and share them through L2.
-template <class C, class SE, class LE, int SPB, bool TABLE, int NQ = 4>
+template <class C, class SE, class LE, int SPB, bool TABLE, int NQ = 4, bool R12 = false>
 __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   static_assert(NQ == 4 || NQ == 8, "4 or 8 threads per site");
   __shared__ double lds[2 * 16];
@@ -116,6 +118,7 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
       if (p.table[i].blk0 <= gb) it = i;
   const StepItem &I = TABLE ? p.table[it] : p.item;
   const Ext4 ex = ext_of(I.g);
+  constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
   const int lb = gb - I.blk0;
   const int r = lb % nrhs;
@@ -199,13 +202,13 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
       const uint32_t lane_links = (uint32_t)dq * 9u * (uint32_t)I.lstride;
       if (NQ == 4) {
         quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + link_lane(site), k, C(1),
-                                   vg5);
+                                   vg5, r12);
         quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + link_lane(bwd), k, C(-1),
-                                  vg5);
+                                  vg5, r12);
       } else {
         const bool bw = q >= 4;
         quad_hop_sel<C, SE, LE>(acc, v, cs, U, ls, bw ? bwd : fwd,
-                                lane_links + link_lane(bw ? bwd : site), k, bw, vg5);
+                                lane_links + link_lane(bw ? bwd : site), k, bw, vg5, r12);
       }
     }
 #pragma unroll
@@ -298,32 +301,24 @@ __device__ __forceinline__ void load_spinor_pair(rsrc_t v, uint32_t cs, uint32_t
     }
 }
 
+// the links of two x-adjacent sites (r12: two stored rows, the third completed)
 template <class LE>
-__device__ __forceinline__ void load_link_pair(rsrc_t U, uint32_t ls, uint32_t l0,
+__device__ __forceinline__ void load_link_pair(rsrc_t U, uint32_t ls, uint32_t l0, bool r12,
                                                cx<float> m0[3][3], cx<float> m1[3][3]) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) bld2<LE>(U, (a * 3 + b) * ls, l0, m0[a][b], m1[a][b]);
+  if (r12) {
+    su3_row2(m0);
+    su3_row2(m1);
+  } else {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) bld2<LE>(U, (6 + b) * ls, l0, m0[2][b], m1[2][b]);
+  }
 }
 
-template <class C, class LE>
-__device__ __forceinline__ void load_link_c(rsrc_t U, uint32_t ls, uint32_t l, cx<C> m[3][3]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(U, (a * 3 + b) * ls, l);
-}
-
-template <class LE>
-__device__ __forceinline__ void load_link(rsrc_t U, uint32_t ls, uint32_t l, cx<float> m[3][3]) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) m[a][b] = bld<float, LE>(U, (a * 3 + b) * ls, l);
-}
-
-template <class LE, int SPB, bool TABLE>
+template <class LE, int SPB, bool TABLE, bool R12 = false>
 __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
   using C = float;
   using SE = float2;
@@ -336,6 +331,7 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
       if (p.table[i].blk0 <= gb) it = i;
   const StepItem &I = TABLE ? p.table[it] : p.item;
   const Ext4 ex = ext_of(I.g);
+  constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
   const int lb = gb - I.blk0;
   const int r = lb % nrhs;
@@ -393,7 +389,7 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
         {
           cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
           load_spinor_pair<SE>(v, cs, s0, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + link_lane(s0), m0, m1);
+          load_link_pair<LE>(U, ls, ll + link_lane(s0), r12, m0, m1);
           hop_apply<C, false>(accA, u1, d1, m0, k, C(1));  // x:     psi(x + 1), U(x)
           hop_apply<C, true>(accB, u0, d0, m0, k, C(-1));  // x + 1: psi(x), U(x)^+
           cx<C> un[2][3], dn[2][3];
@@ -403,7 +399,7 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
         {
           cx<C> up[2][3], dp[2][3], mp[3][3];
           load_spinor<C, SE>(v, cs, xp, vg5, up, dp);
-          load_link<LE>(U, ls, ll + link_lane(xp), mp);
+          load_link3<C, LE>(U, ls, ll + link_lane(xp), r12, mp);
           hop_apply<C, true>(accA, up, dp, mp, k, C(-1));  // x: psi(x - 1), U(x - 1)^+
         }
       } else {
@@ -412,14 +408,14 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
         {
           cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
           load_spinor_pair<SE>(v, cs, fwd, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + link_lane(s0), m0, m1);
+          load_link_pair<LE>(U, ls, ll + link_lane(s0), r12, m0, m1);
           hop_apply<C, false>(accA, u0, d0, m0, k, C(1));
           hop_apply<C, false>(accB, u1, d1, m1, k, C(1));
         }
         {
           cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
           load_spinor_pair<SE>(v, cs, bwd, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + link_lane(bwd), m0, m1);
+          load_link_pair<LE>(U, ls, ll + link_lane(bwd), r12, m0, m1);
           hop_apply<C, true>(accA, u0, d0, m0, k, C(-1));
           hop_apply<C, true>(accB, u1, d1, m1, k, C(-1));
         }
@@ -539,7 +535,7 @@ __host__ __device__ constexpr int slab_lds_bytes(int spb, int lx) {
   return (12 * (spb + 2 * lx) + 2 * 12 * spb + 9 * spb) * (int)sizeof(cx<C>);
 }
 
-template <class C, class SE, class LE, int NW, bool TABLE>
+template <class C, class SE, class LE, int NW, bool TABLE, bool R12 = false>
 __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) {
   constexpr int SPB = 64 * NW;
   extern __shared__ __align__(16) unsigned char slab_smem[];
@@ -551,6 +547,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
       if (p.table[i].blk0 <= gb) it = i;
   const StepItem &I = TABLE ? p.table[it] : p.item;
   const Ext4 ex = ext_of(I.g);
+  constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
   const int lb = gb - I.blk0;
   const int r = lb % nrhs;
@@ -600,7 +597,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
     }
   }
   cx<C> mf[3][3];  // forward link of this thread's direction
-  load_link_c<C, LE>(U, ls, (uint32_t)q * 9u * (uint32_t)I.lstride + link_lane(site), mf);
+  load_link3<C, LE>(U, ls, (uint32_t)q * 9u * (uint32_t)I.lstride + link_lane(site), r12, mf);
   if (q == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -642,7 +639,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
         for (int c = 0; c < 3; ++c) mb[a][c] = xlink[(a * 3 + c) * SPB + sb];
     } else {
       const int bwd = c4.y == 0 ? site + (ex.ly - 1) * ex.sy : site - ex.sy;
-      load_link_c<C, LE>(U, ls, ll + link_lane(bwd), mb);
+      load_link3<C, LE>(U, ls, ll + link_lane(bwd), r12, mb);
     }
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -660,7 +657,7 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
     load_spinor<C, SE>(v, cs, fwd, vg5, u, d);
     hop_apply<C, false>(acc, u, d, mf, k, C(1));
     cx<C> mb[3][3];
-    load_link_c<C, LE>(U, ls, ll + link_lane(bwd), mb);
+    load_link3<C, LE>(U, ls, ll + link_lane(bwd), r12, mb);
     load_spinor<C, SE>(v, cs, bwd, vg5, u, d);
     hop_apply<C, true>(acc, u, d, mb, k, C(-1));
   }
@@ -1009,6 +1006,38 @@ __global__ void pack_links_kernel(const S *__restrict__ src, D *__restrict__ dst
   if (k >= (int64_t)36 * V) return;
   const int64_t comp = k / V, site = k - comp * V;
   cvt(src[k], dst[(int64_t)link_lane((uint32_t)site) + comp * 64]);
+}
+
+// Largest |stored third row - third row completed from the first two| (FP64, element-wise
+// complex modulus) over the links of blockIdx.x's 256 (site, mu) pairs: partial[blockIdx.x].
+template <class LE>
+__global__ void __launch_bounds__(256) su3_row2_dev_kernel(const LE *U, int V, double *partial) {
+  __shared__ double red[4];
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;  // k = 4 site + mu
+  double dev = 0.0;
+  if (k < (int64_t)4 * V) {
+    const uint32_t site = (uint32_t)(k >> 2), mu = (uint32_t)(k & 3);
+    const uint32_t ls = 64u * elem_traits<LE>::bytes;
+    const rsrc_t r = make_rsrc(U, link_bytes(V, ls));
+    cx<double> m[3][3], stored[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) m[a][b] = bld<double, LE>(r, (a * 3 + b) * ls, mu * 9u * 64u + link_lane(site));
+#pragma unroll
+    for (int b = 0; b < 3; ++b) stored[b] = m[2][b];
+    su3_row2(m);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const cx<double> e = m[2][b] - stored[b];
+      dev = fmax(dev, sqrt(e.re * e.re + e.im * e.im));
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // ---------------------------------------------------------------------------------------------

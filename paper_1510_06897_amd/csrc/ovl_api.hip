@@ -120,6 +120,7 @@ struct ovl_gauge {
   int lstride;        // elements between link components inside a block (kLinkBlock)
   void *links;        // [ceil(V / 64)][4 * 3 * 3][64] complex in store_dt
   uint32_t *flags;    // sticky device flags
+  int r12 = 0;        // kernels read two rows per link and complete the third (SU(3) fields)
 };
 
 struct ovl_poly {
@@ -311,33 +312,33 @@ int64_t items_work(const StepItem *items, int n) {
 
 // launch one step; a single-problem launch plans its item here, a table launch was planned when
 // its table was written (p.total_blocks, spb)
-template <class C, class SE, class LE, int NW>
+template <class C, class SE, class LE, int NW, bool R12>
 int launch_slab(StepArgs<false> &p, hipStream_t s) {
   const int bytes = slab_lds_bytes<C>(64 * NW, p.item.g.L[0]);
   static std::once_flag once;
   static hipError_t attr = hipSuccess;
   std::call_once(once, [] {
-    attr = hipFuncSetAttribute((const void *)step_slab_kernel<C, SE, LE, NW, false>,
+    attr = hipFuncSetAttribute((const void *)step_slab_kernel<C, SE, LE, NW, false, R12>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 512);
   });
   HIP_TRY(attr);
-  step_slab_kernel<C, SE, LE, NW, false><<<p.total_blocks, 256 * NW, bytes, s>>>(p);
+  step_slab_kernel<C, SE, LE, NW, false, R12><<<p.total_blocks, 256 * NW, bytes, s>>>(p);
   HIP_TRY(hipGetLastError());
   return OVL_OK;
 }
 
-template <class C, class SE, class LE, bool TABLE>
-int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
+template <class C, class SE, class LE, bool TABLE, bool R12>
+int launch_step_r(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab) {
   if (slab) {
     if constexpr (TABLE) {
       return fail(OVL_EINVAL, "the slab order takes single problems");
     } else {
       switch (spb) {
-        case 64: return launch_slab<C, SE, LE, 1>(p, s);
-        case 128: return launch_slab<C, SE, LE, 2>(p, s);
-        case 192: return launch_slab<C, SE, LE, 3>(p, s);
+        case 64: return launch_slab<C, SE, LE, 1, R12>(p, s);
+        case 128: return launch_slab<C, SE, LE, 2, R12>(p, s);
+        case 192: return launch_slab<C, SE, LE, 3, R12>(p, s);
         case 256:
-          if constexpr (sizeof(C) == 4) return launch_slab<C, SE, LE, 4>(p, s);
+          if constexpr (sizeof(C) == 4) return launch_slab<C, SE, LE, 4, R12>(p, s);
           return fail(OVL_EINVAL, "FP64 slab of 256 sites does not fit the LDS");
         default: return fail(OVL_EINVAL, "slab of %d sites", spb);
       }
@@ -345,20 +346,29 @@ int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
   }
   if (spb == 128) {
     if constexpr (std::is_same<SE, float2>::value)
-      step2_kernel<LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
+      step2_kernel<LE, 64, TABLE, R12><<<p.total_blocks, 256, 0, s>>>(p);
     else
       return fail(OVL_EINVAL, "two sites per lane need FP32 spinors");
   } else if (spb == 64) {
-    step_kernel<C, SE, LE, 64, TABLE><<<p.total_blocks, 256, 0, s>>>(p);
+    step_kernel<C, SE, LE, 64, TABLE, 4, R12><<<p.total_blocks, 256, 0, s>>>(p);
   } else if (spb == 16) {
-    step_kernel<C, SE, LE, 16, TABLE><<<p.total_blocks, 64, 0, s>>>(p);
+    step_kernel<C, SE, LE, 16, TABLE, 4, R12><<<p.total_blocks, 64, 0, s>>>(p);
   } else if (spb == 8) {
-    step_kernel<C, SE, LE, 8, TABLE, 8><<<p.total_blocks, 64, 0, s>>>(p);
+    step_kernel<C, SE, LE, 8, TABLE, 8, R12><<<p.total_blocks, 64, 0, s>>>(p);
   } else {
     return fail(OVL_EINVAL, "no step kernel for %d sites per workgroup", spb);
   }
   HIP_TRY(hipGetLastError());
   return OVL_OK;
+}
+
+// two-row link reads where the problem's field allows them (single problem: its handle; a
+// table launch: every item's, recorded in p.r12 when the table was written)
+template <class C, class SE, class LE, bool TABLE>
+int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
+  const bool r12 = TABLE ? p.r12 != 0 : p.item.r12 != 0;
+  return r12 ? launch_step_r<C, SE, LE, TABLE, true>(p, spb, s, slab)
+             : launch_step_r<C, SE, LE, TABLE, false>(p, spb, s, slab);
 }
 
 template <bool TABLE>
@@ -390,6 +400,7 @@ void fill_item(StepItem &it, const ovl_gauge *g, int nrhs) {
   it.U = g->links;
   it.g = g->g;
   it.lstride = g->lstride;
+  it.r12 = g->r12;
   it.nrhs = nrhs;
 }
 
@@ -649,6 +660,8 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   args.n_items = nj;
   args.total_blocks = plan_items(items, nj, cfg, site_bytes_of(prec));
   args.remap = cfg.remap;
+  args.r12 = 1;
+  for (int j = 0; j < nj; ++j) args.r12 = args.r12 && items[j].r12;
   if (TABLE) {
     StepItem *table = (StepItem *)base;
     for (int j = 0; j < nj; ++j) {
@@ -858,6 +871,45 @@ int ovl_gauge_info(const ovl_gauge *g, int32_t dims_out[4], int *store_dt) {
   if (!g || !dims_out || !store_dt) return fail(OVL_EINVAL, "NULL argument");
   for (int i = 0; i < 4; ++i) dims_out[i] = g->g.L[i];
   *store_dt = g->store_dt;
+  return OVL_OK;
+}
+
+// Two-row link reads: enable after checking on the device that every stored third row matches
+// the one completed from the first two (an SU(3) field up to storage rounding) within tol.
+int ovl_gauge_reconstruct(ovl_gauge *g, int on, double tol, double *max_dev, void *stream) {
+  g_err[0] = 0;
+  if (!g) return fail(OVL_EINVAL, "gauge handle is NULL");
+  if (!on) {
+    if (g->r12) g->serial = g_poly_serial.fetch_add(1);  // new key for cached step graphs
+    g->r12 = 0;
+    if (max_dev) *max_dev = 0.0;
+    return OVL_OK;
+  }
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(OVL_EINVAL, "tol must be finite and >= 0");
+  const hipStream_t s = as_stream(stream);
+  const int V = g->g.V;
+  const int nblk = (int)(((int64_t)4 * V + 255) / 256);
+  Scratch sc;
+  int rc = scratch_alloc(sc, sizeof(double) * nblk, s);
+  if (rc) return rc;
+  double *partial = (double *)sc.p;
+  if (g->store_dt == OVL_F64)
+    su3_row2_dev_kernel<<<nblk, 256, 0, s>>>((const double2 *)g->links, V, partial);
+  else if (g->store_dt == OVL_F32)
+    su3_row2_dev_kernel<<<nblk, 256, 0, s>>>((const float2 *)g->links, V, partial);
+  else
+    su3_row2_dev_kernel<<<nblk, 256, 0, s>>>((const bf16c *)g->links, V, partial);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h(nblk);
+  HIP_TRY(hipMemcpyAsync(h.data(), partial, sizeof(double) * nblk, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double dev = 0.0;
+  for (double v : h) dev = std::isnan(v) ? v : std::max(dev, v);
+  if (max_dev) *max_dev = dev;
+  if (!(dev <= tol))
+    return fail(OVL_EINVAL, "links are not SU(3) within %g: third rows deviate by %g", tol, dev);
+  if (!g->r12) g->serial = g_poly_serial.fetch_add(1);
+  g->r12 = 1;
   return OVL_OK;
 }
 

@@ -42,6 +42,23 @@ __device__ __forceinline__ cx<C> zmul(cx<C> z, cx<C> d) {
   return mk<C>(z.re * d.re - z.im * d.im, z.re * d.im + z.im * d.re);
 }
 
+// one link (component stride ls bytes, element lsite): all three rows, or with r12 the first
+// two, the third completed as for an SU(3) matrix (uniform per launch)
+template <class C, class LE>
+__device__ __forceinline__ void load_link3(rsrc_t Um, uint32_t ls, uint32_t lsite, bool r12,
+                                           cx<C> m[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(Um, (a * 3 + b) * ls, lsite);
+  if (r12) {
+    su3_row2(m);
+  } else {
+#pragma unroll
+    for (int b = 0; b < 3; ++b) m[2][b] = bld<C, LE>(Um, (6 + b) * ls, lsite);
+  }
+}
+
 template <class C, bool DAG>
 __device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], const cx<C> d[2][3],
                                           const cx<C> m[3][3], const DirCoef<C> &k, C sgn);
@@ -51,7 +68,7 @@ __device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], co
 template <class C, class SE, class LE, bool DAG>
 __device__ __forceinline__ void quad_hop(cx<C> acc[12], rsrc_t v, uint32_t cs, rsrc_t Um,
                                          uint32_t ls, uint32_t nb, uint32_t lsite,
-                                         const DirCoef<C> &k, C sgn, bool g5) {
+                                         const DirCoef<C> &k, C sgn, bool g5, bool r12) {
   cx<C> u[2][3], d[2][3];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -62,10 +79,7 @@ __device__ __forceinline__ void quad_hop(cx<C> acc[12], rsrc_t v, uint32_t cs, r
       d[s][c] = g5 ? -x : x;
     }
   cx<C> m[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(Um, (a * 3 + b) * ls, lsite);
+  load_link3<C, LE>(Um, ls, lsite, r12, m);
   hop_apply<C, DAG>(acc, u, d, m, k, sgn);
 }
 
@@ -115,7 +129,8 @@ __device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], co
 template <class C, class SE, class LE>
 __device__ __forceinline__ void quad_hop_sel(cx<C> acc[12], rsrc_t v, uint32_t cs, rsrc_t Um,
                                              uint32_t ls, uint32_t nb, uint32_t lsite,
-                                             const DirCoef<C> &k, bool dag, bool g5) {
+                                             const DirCoef<C> &k, bool dag, bool g5,
+                                             bool r12) {
   cx<C> u[2][3], d[2][3];
 #pragma unroll
   for (int s = 0; s < 2; ++s)
@@ -126,10 +141,7 @@ __device__ __forceinline__ void quad_hop_sel(cx<C> acc[12], rsrc_t v, uint32_t c
       d[s][c] = g5 ? -x : x;
     }
   cx<C> m[3][3], mm[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) m[a][b] = bld<C, LE>(Um, (a * 3 + b) * ls, lsite);
+  load_link3<C, LE>(Um, ls, lsite, r12, m);
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll

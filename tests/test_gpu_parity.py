@@ -628,6 +628,17 @@ def test_dw_full_size_24x24x24x48(ovl):
     g32 = ovl.GaugeField(dev(u), "f32")
     got32 = host(ovl.kernel_apply(g32, dev(psi, torch.complex64)))
     assert rel_err(got32, ref) < 1e-6
+    # two-row link reads, as the benchmark times them beside the full reads
+    g64.reconstruct()
+    assert max_rel(host(ovl.kernel_apply(g64, dev(psi))), ref) < 1e-13
+    g32.reconstruct()
+    got32 = host(ovl.kernel_apply(g32, dev(psi, torch.complex64)))
+    assert rel_err(got32, ref) < 1e-6
+    gbf = ovl.GaugeField(dev(u), "bf16")
+    gbf.reconstruct()
+    u_r = complete_third_row(latgen.round_to_bf16(u))
+    got = host(ovl.kernel_apply(gbf, dev(psi, torch.complex64)))
+    assert max_rel(got, ow.kop(u_r, latgen.round_to_f32(psi))) < 1e-6
 
 
 @pytest.mark.parametrize("store", ["f64", "f32"])
@@ -685,3 +696,119 @@ def test_ginsparg_wilson_residual_gpu(ovl):
     rs = float(ovl.sign_residual(g, p, x, defl=d)[0])
     assert rs > 1e-4
     assert abs(lhs - 0.5 * rs) < 1e-10 * rs
+
+
+def complete_third_row(u):
+    """Links with row 2 replaced by conj(row0 x row1) (FP64), the matrices a two-row read sees."""
+    u = np.array(u, dtype=np.complex128, copy=True)
+    r0, r1 = u[:, 0], u[:, 1]
+    for b in range(3):
+        c, d = (b + 1) % 3, (b + 2) % 3
+        u[:, 2, b] = np.conj(r0[:, c] * r1[:, d] - r0[:, d] * r1[:, c])
+    return u
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dims,spb,tiles", [((4, 4, 4, 4), 8, 0), ((6, 4, 2, 4), 16, 0),
+                                            ((8, 8, 4, 6), 64, 1), ((8, 8, 4, 6), 128, 1),
+                                            ((16, 8, 4, 6), 128, 2)])
+def test_two_row_links_kernel(ovl, tmp_path, store, dims, spb, tiles):
+    """K with links read as two rows (third completed as for SU(3)) in every launch form, against
+    the oracle on the links the kernel sees; two right-hand sides."""
+    if store == "f64" and spb == 128 and tiles == 1:
+        pytest.skip("two sites per lane take FP32 spinors")
+    prec = {"f64": 0, "f32": 1, "bf16": 2}[store]
+    cache = tmp_path / "r12.txt"
+    cache.write_text(" ".join(map(str, dims)) + f" {prec} 2 {spb} {tiles} 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.random_su3_field(dims, 10185, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20185, nrhs=2)
+    g = ovl.GaugeField(dev(u), store)
+    dev_max = g.reconstruct()
+    assert dev_max < {"f64": 1e-14, "f32": 1e-6, "bf16": 2e-2}[store]
+    assert ovl.launch_config(g, 2) == (spb, tiles, 1)
+    if store == "f64":
+        got = host(ovl.kernel_apply(g, dev(psi)))
+        for r in range(2):
+            assert max_rel(got[r], ow.kop(u, psi[r])) < 1e-13
+        return
+    u_r = complete_third_row(latgen.round_to_f32(u) if store == "f32" else latgen.round_to_bf16(u))
+    got = host(ovl.kernel_apply(g, dev(psi, torch.complex64)))
+    for r in range(2):
+        assert max_rel(got[r], ow.kop(u_r, latgen.round_to_f32(psi[r]))) < 1e-6
+
+
+def test_two_row_links_refused_for_non_su3(ovl):
+    """A field that is not SU(3) is refused (status EINVAL, deviation reported) and keeps full
+    reads."""
+    dims = (4, 4, 2, 4)
+    rng = np.random.default_rng(7)
+    shape = (4, 3, 3) + tuple(reversed(dims))
+    u = (rng.normal(size=shape) + 1j * rng.normal(size=shape)) * 0.5
+    psi = latgen.gaussian_spinor(dims, 20186)
+    g = ovl.GaugeField(dev(u), "f64")
+    with pytest.raises(ovl.OvlError) as e:
+        g.reconstruct()
+    assert e.value.status == "OVL_EINVAL"
+    got = host(ovl.kernel_apply(g, dev(psi)))
+    assert max_rel(got, ow.kop(u, psi)) < 1e-14
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_two_row_links_sign_overlap_and_graphs(ovl, store):
+    """Deflated sign and overlap with two-row links (replayed from the step graph on repeated
+    calls), then back to full reads: each against the oracle on the links it reads."""
+    dims = (4, 6, 4, 8)
+    u = latgen.smeared_field(dims, 10187, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20187)
+    phi, lam = random_basis(dims, 3, 20188)
+    alpha = och.coeffs_sign_interp(31, 0.1)
+    cdt = torch.complex128 if store == "f64" else torch.complex64
+    tol = 1e-12 if store == "f64" else 1e-6
+    g = ovl.GaugeField(dev(u), store)
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, store)
+    x = dev(psi, cdt)
+    u_full = u if store == "f64" else latgen.round_to_f32(u)
+    u_two = complete_third_row(u_full)
+    ref_full = och.sign_apply(u_full, psi, alpha, LMAX, phi, lam)
+    ref_two = och.sign_apply(u_two, psi, alpha, LMAX, phi, lam)
+    out = torch.empty_like(x)
+    for _ in range(3):
+        ovl.sign_apply(g, p, x, defl=d, out=out)
+    full = host(out)
+    assert rel_err(full, ref_full) < tol
+    g.reconstruct()
+    for _ in range(3):
+        ovl.sign_apply(g, p, x, defl=d, out=out)
+        assert rel_err(host(out), ref_two) < tol
+    o = host(ovl.overlap_apply(g, p, x, 0.05, defl=d))
+    assert rel_err(o, oov.overlap_apply(u_two, psi, 0.05, alpha, LMAX, phi, lam)) < tol
+    g.reconstruct(False)
+    for _ in range(2):
+        ovl.sign_apply(g, p, x, defl=d, out=out)
+        assert np.array_equal(host(out), full)
+    assert g.flags() == 0
+
+
+def test_two_row_links_batch(ovl):
+    """A batch whose items all read two rows equals the one-problem launches bitwise; with one
+    item on full reads the whole launch reads full links and equals those launches bitwise."""
+    alpha = och.coeffs_sign_interp(15, 0.08)
+    p = ovl.Polynomial(alpha, LMAX)
+    probs = []
+    # volumes whose one-problem launches take the batch's launch form (16 sites per workgroup)
+    for i, dims in enumerate([(8, 8, 8, 8), (6, 6, 8, 16), (8, 8, 6, 12)]):
+        u = latgen.random_su3_field(dims, 10189 + i)
+        psi = latgen.gaussian_spinor(dims, 20189 + i, nrhs=1 + i % 2)
+        g = ovl.GaugeField(dev(u), "f32")
+        g.reconstruct()
+        probs.append((g, dev(psi, torch.complex64)))
+    outs = ovl.batch_sign_apply(p, probs)
+    for (g, x), o in zip(probs, outs):
+        assert torch.equal(ovl.sign_apply(g, p, x), o)
+    probs[1][0].reconstruct(False)
+    outs = ovl.batch_sign_apply(p, probs)
+    for (g, x), o in zip(probs, outs):
+        g.reconstruct(False)
+        assert torch.equal(ovl.sign_apply(g, p, x), o)
