@@ -134,6 +134,14 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
     num = sum(float(torch.linalg.vector_norm(a.to(torch.complex128) - b) ** 2)
               for a, b in zip(outs, outs64))
     den = sum(float(torch.linalg.vector_norm(b) ** 2) for b in outs64)
+    # the same batch with two-row link reads (every field is SU(3))
+    for g, _ in probs32:
+        g.reconstruct()
+    ms_b2 = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs32, outs), 5)
+    ovl.batch_sign_apply(p32, probs32, outs)
+    torch.cuda.synchronize()
+    num2 = sum(float(torch.linalg.vector_norm(a.to(torch.complex128) - b) ** 2)
+               for a, b in zip(outs, outs64))
     out["batched"] = {
         "workload": "sign(K)psi, degree 299, eps 0.05, no deflation: 12 point sources on "
                     "16^3x32 + 4 x 8^3x16 + 2 x 12^3x24 (own stout-smeared fields), FP32",
@@ -144,8 +152,13 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
         "speedup_vs_unbatched_f32": round(ms_u / ms_b, 3),
         "speedup_vs_plain_f64": round(ms_64 / ms_b, 3),
         "rel_err_vs_f64_gpu": (num / den) ** 0.5,
+        "two_row_links": {"ms_per_batch": round(ms_b2, 3),
+                          "rhs_applies_per_s": round(n_rhs_total * 1e3 / ms_b2, 2),
+                          "speedup_vs_plain_f64": round(ms_64 / ms_b2, 3),
+                          "rel_err_vs_f64_gpu": (num2 / den) ** 0.5},
     }
-    log(f"batched: {ms_b:.2f} ms/batch, unbatched {ms_u:.2f}, FP64 {ms_64:.2f}")
+    log(f"batched: {ms_b:.2f} ms/batch (two-row links {ms_b2:.2f}), unbatched {ms_u:.2f}, "
+        f"FP64 {ms_64:.2f}")
     del probs32, probs64, outs, outs64
 
     # (2) BF16 links, FP32 spinors, 24 deflated modes (FP32 matrix-core projection), degree 399
@@ -174,6 +187,12 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
     torch.cuda.synchronize()
     err = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y64)
                 / torch.linalg.vector_norm(y64))
+    gbf.reconstruct()
+    ms_bf2 = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), 5)
+    ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
+    torch.cuda.synchronize()
+    err2 = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y64)
+                 / torch.linalg.vector_norm(y64))
     # the deflation projection alone (FP32 matrix cores), for its utilisation
     ms_proj = gpu_ms(torch, lambda: ovl.defl_project(dbf, x32), 20)
     proj_flops = 8.0 * 24 * 12 * int(np.prod(dims))    # complex MAC = 8 real flops
@@ -189,6 +208,9 @@ def measure_extra(ovl, latgen, low_modes, torch, dev):
         "projection_mfma_TFLOPs": round(proj_flops / (ms_proj * 1e-3) / 1e12, 3),
         "projection_mfma_frac_of_fp32_peak": round(proj_flops / (ms_proj * 1e-3) / 157.3e12, 5),
         "projection_GBps": round(24 * 12 * int(np.prod(dims)) * 8 / (ms_proj * 1e-3) / 1e9, 1),
+        "two_row_links": {"applies_per_s": round(1e3 / ms_bf2, 2),
+                          "speedup_vs_plain_f64": round(ms_p64 / ms_bf2, 3),
+                          "rel_err_vs_f64_gpu_same_polynomial": err2},
     }
     log(f"BF16 24-mode: {ms_bf:.2f} ms/apply, FP64 {ms_p64:.2f} ms, err {err:.2e}")
     del g64, gbf, dbf, d64, phi
