@@ -144,3 +144,19 @@ def test_autotune_cache_file(lib, tmp_path):
     f = tmp_path / "tune.txt"
     f.write_text("16 16 16 32 1 1 64 1 1 17.5\n8 8 8 16 0 1 16 0 1 9.0\nbad line\n")
     assert lib.ovl_autotune_load(str(f).encode()) == 2
+
+
+def test_two_row_reference_helper():
+    """The reference the two-row GPU tests use: SU(3) links come back unchanged, a link that is
+    not SU(3) does not, and the completed third row is orthonormal to the first two."""
+    import numpy as np
+    import latgen
+    from tests.conftest import complete_third_row
+    u = latgen.random_su3_field((2, 3, 2, 2), 5, noise=0.8)
+    assert np.abs(complete_third_row(u) - u).max() < 1e-14
+    bad = u.copy()
+    bad[:, 2] *= 1.5
+    assert np.abs(complete_third_row(bad) - bad).max() > 0.1
+    w = complete_third_row(bad * 1.0)
+    m = np.moveaxis(w[0].reshape(3, 3, -1), -1, 0)
+    assert np.abs(m @ np.conj(np.swapaxes(m, 1, 2)) - np.eye(3)).max() < 1e-14

@@ -16,7 +16,7 @@ from oracle import deflation as odefl
 from oracle import force as oforce
 from oracle import overlap as oov
 from oracle import wilson as ow
-from tests.conftest import rel_err
+from tests.conftest import complete_third_row, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -696,16 +696,6 @@ def test_ginsparg_wilson_residual_gpu(ovl):
     rs = float(ovl.sign_residual(g, p, x, defl=d)[0])
     assert rs > 1e-4
     assert abs(lhs - 0.5 * rs) < 1e-10 * rs
-
-
-def complete_third_row(u):
-    """Links with row 2 replaced by conj(row0 x row1) (FP64), the matrices a two-row read sees."""
-    u = np.array(u, dtype=np.complex128, copy=True)
-    r0, r1 = u[:, 0], u[:, 1]
-    for b in range(3):
-        c, d = (b + 1) % 3, (b + 2) % 3
-        u[:, 2, b] = np.conj(r0[:, c] * r1[:, d] - r0[:, d] * r1[:, c])
-    return u
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
