@@ -73,9 +73,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile", nargs="?", const="c2", choices=["c2", "dw", "proj", "force"],
+    ap.add_argument("--profile", nargs="?", const="c2", choices=["c2", "dw", "dw2", "proj", "force"],
                     help="run one part only, for rocprofv3 runs: c2 = the timed FP32 overlap "
-                         "loop (default), dw = K at 24^3x48 in FP64/FP32/BF16, proj = the FP32 "
+                         "loop (default), dw = K at 24^3x48 in FP64/FP32/BF16 (dw2: with two-row "
+                         "link reads), proj = the FP32 "
                          "matrix-core deflation projection at 16^3x32 with 24 vectors, force = "
                          "the FP32 force at 24^3x48, degree 299")
     ap.add_argument("--no-extra", action="store_true",
@@ -249,11 +250,13 @@ def dw_inputs(latgen, torch, dev):
     return torch.from_numpy(u).to(dev), torch.from_numpy(psi).to(dev)
 
 
-def profile_dw(ovl, latgen, torch, dev, reps):
+def profile_dw(ovl, latgen, torch, dev, reps, two_row=False):
     """K applications at 24^3x48 in the three storage precisions (the bench's D_W figures)."""
     d_ub, d_pb = dw_inputs(latgen, torch, dev)
     for store in ("f64", "f32", "bf16"):
         gb = ovl.GaugeField(d_ub, store)
+        if two_row:
+            gb.reconstruct()
         x = d_pb if store == "f64" else d_pb.to(torch.complex64)
         y = torch.empty_like(x)
         for _ in range(reps):
@@ -318,8 +321,8 @@ def main():
     ovl.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.profile == "dw":
-        profile_dw(ovl, latgen, torch, dev, args.steps)
+    if args.profile in ("dw", "dw2"):
+        profile_dw(ovl, latgen, torch, dev, args.steps, two_row=args.profile == "dw2")
         return
     if args.profile == "proj":
         profile_proj(ovl, torch, dev, args.steps)
