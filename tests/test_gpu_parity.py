@@ -802,3 +802,22 @@ def test_two_row_links_batch(ovl):
     for (g, x), o in zip(probs, outs):
         g.reconstruct(False)
         assert torch.equal(ovl.sign_apply(g, p, x), o)
+
+
+def test_zero_right_hand_sides_rejected(ovl):
+    """An empty batch of right-hand sides is an argument error (EINVAL) before any launch, for
+    the stencil, the sign function, the residual diagnostic and the batched form."""
+    dims = (4, 4, 2, 2)
+    g = ovl.GaugeField(dev(latgen.random_su3_field(dims, 1)), "f64")
+    p = ovl.Polynomial(och.coeffs_sign_interp(7, 0.1), LMAX)
+    empty = torch.zeros((0, 4, 3) + tuple(reversed(dims)), dtype=torch.complex128, device="cuda")
+    for call in (lambda: ovl.kernel_apply(g, empty), lambda: ovl.sign_apply(g, p, empty),
+                 lambda: ovl.sign_residual(g, p, empty),
+                 lambda: ovl.batch_sign_apply(p, [(g, empty)])):
+        with pytest.raises(ovl.OvlError) as e:
+            call()
+        assert e.value.status == "OVL_EINVAL"
+    # the handle still works afterwards
+    x = dev(latgen.gaussian_spinor(dims, 2))
+    assert max_rel(host(ovl.kernel_apply(g, x)), ow.kop(latgen.random_su3_field(dims, 1),
+                                                         latgen.gaussian_spinor(dims, 2))) < 1e-14
