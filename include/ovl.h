@@ -26,8 +26,9 @@
  *           used for the deflation inner products, the Gram-Schmidt basis set-up, the deflation
  *           weights and the final norm check.
  * Pointers: "_dev" pointers are device memory of the current HIP device, "_host" pointers host
- *           memory.  The caller owns every data pointer; the library owns only its handles and
- *           the temporaries it allocates (stream-ordered, freed before the call's work ends).
+ *           memory.  The caller owns every data pointer; the library owns only its handles, the
+ *           temporaries it allocates (stream-ordered, freed before the call's work ends) and the
+ *           work vectors of its cached step graphs (see ovl_graph_enable).
  * Streams:  every operator is enqueued on the caller's stream (a hipStream_t passed as void*,
  *           NULL for the null stream) and is asynchronous: results are visible after the stream
  *           synchronises.  Calls that share a handle may run on different streams only if they do
@@ -270,15 +271,15 @@ int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear);
 
 /* Step graphs (on by default).  A sign or overlap evaluation of one problem small enough for
  * one-wave workgroups (fewer than 64K site-right-hand-sides) and of degree >= 3 is bound by the
- * launch rate.  The second time the same evaluation is requested (same gauge handle, polynomial
- * handle, source and output pointers, right-hand-side count, precision, gamma5 on the source
- * and launch configuration) its plain recurrence steps are captured into a HIP graph, which is
- * replayed from then on; the deflation projection, the final fused step and the norm check
- * stay direct launches.  The library keeps up to 8 such graphs, each with its own work vector
- * (one right-hand-side set of spinors); evicting one synchronises the device.  Two calls that
- * overlap in time and share a graph race on its work vector, as they would on their shared
- * output.  on = 0 turns the mechanism off for later calls (cached graphs are kept).  Results
- * are bitwise identical either way. */
+ * launch rate.  The second time the same evaluation is requested (same gauge handle and link
+ * read mode, polynomial handle, source and output pointers, right-hand-side count, precision,
+ * gamma5 on the source and launch configuration) its plain recurrence steps are captured into a
+ * HIP graph, which is replayed from then on; the deflation projection, the final fused step and
+ * the norm check stay direct launches.  The library keeps up to 8 such graphs, each with its own
+ * work vector (one right-hand-side set of spinors); evicting one synchronises the device.  Two
+ * calls that overlap in time and share a graph race on its work vector, as they would on their
+ * shared output.  on = 0 turns the mechanism off for later calls (cached graphs are kept).
+ * Results are bitwise identical either way. */
 int ovl_graph_enable(int on);
 
 /* Kernel timing of the fused Chebyshev step: when enabled, every sign evaluation (sign, overlap,
