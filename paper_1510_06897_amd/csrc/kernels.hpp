@@ -1047,8 +1047,9 @@ __global__ void __launch_bounds__(256) su3_row2_dev_kernel(const LE *U, int V, d
 //   G_mu(x)_ij (+)= -1/2 sum_pairs coef sum_{k<2} [ h^-(a(x))_{k,i} conj(h^-(t(x+mu))_{k,j})
 //                                                 + h^+(t(x))_{k,i} conj(h^+(a(x+mu))_{k,j}) ]
 // ((1 -+ gamma_mu)/2 are Hermitian projectors, so the 4-spin sums reduce to half-spinor sums.)
-// Pair i uses a_i = a0 + i * a_step and t_i = t0 + i * t_step (elements), coef = coef_first for
-// i = 0 and coef_rest otherwise.  Thread (site, mu) owns link G_mu(x): it accumulates the whole
+// Pair i < len0 uses a_i = a0 + i * a_step and t_i = t0 + i * t_step (elements), pair i >= len0
+// the second run a1 + (i - len0) * a_step, t1 + (i - len0) * t_step; coef = coef_first for i = 0
+// and coef_rest otherwise.  Thread (site, mu) owns link G_mu(x): it accumulates the whole
 // segment in registers and reads and writes G once (gather only, no atomics).  The four
 // direction waves of a workgroup share the 64 sites: a(x) and t(x) are read from HBM once per
 // workgroup (wave mu loads spin-colour components 3 mu .. 3 mu + 2) and handed over in LDS,
@@ -1056,8 +1057,9 @@ __global__ void __launch_bounds__(256) su3_row2_dev_kernel(const LE *U, int V, d
 // t(x+mu) are read per thread, issued before the barrier.
 template <class C, class SE, class GE>
 __global__ void __launch_bounds__(256)
-    link_vjp_kernel(GE *G, const SE *a0, int64_t a_step, const SE *t0, int64_t t_step, int len,
-                    double coef_first, double coef_rest, Geom geo, int a_g5, int accumulate) {
+    link_vjp_kernel(GE *G, const SE *a0, const SE *a1, int64_t a_step, const SE *t0,
+                    const SE *t1, int64_t t_step, int len0, int len, double coef_first,
+                    double coef_rest, Geom geo, int a_g5, int accumulate) {
   const int mu = threadIdx.x >> 6, sl = threadIdx.x & 63;
   const int site = blockIdx.x * 64 + sl;
   const Ext4 ex = ext_of(geo);
@@ -1078,8 +1080,9 @@ __global__ void __launch_bounds__(256)
     for (int j = 0; j < 3; ++j) acc[i][j] = mk<C>(0, 0);
   for (int pi = 0; pi < len; ++pi) {
     const int b = pi & 1;
-    const rsrc_t ra = make_rsrc(a0 + pi * a_step, 12u * cs);
-    const rsrc_t rt = make_rsrc(t0 + pi * t_step, 12u * cs);
+    const bool first_run = pi < len0;
+    const rsrc_t ra = make_rsrc(first_run ? a0 + pi * a_step : a1 + (pi - len0) * a_step, 12u * cs);
+    const rsrc_t rt = make_rsrc(first_run ? t0 + pi * t_step : t1 + (pi - len0) * t_step, 12u * cs);
     cx<C> hmt[2][3], hpa[2][3];
     if (active) {
       cx<C> u[2][3], d[2][3], xa[3], xt[3];

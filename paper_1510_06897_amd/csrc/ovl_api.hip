@@ -1431,24 +1431,28 @@ namespace {
 
 // One launch accumulates len pairs (a_i, t_i) = (a0 + i * step, t0 + i * step) into G; the
 // first pair carries weight coef_first, the others coef_rest.
-int launch_vjp(Prec prec, const ovl_gauge *g, void *G, const void *a0, int a_g5, const void *t0,
-               size_t step_bytes, int len, double coef_first, double coef_rest, int accumulate,
-               hipStream_t s) {
+// one VJP launch over up to two runs of pairs: len0 pairs from (a0, t0), then len - len0 from
+// (a1, t1), consecutive pairs step_bytes apart within a run
+int launch_vjp(Prec prec, const ovl_gauge *g, void *G, const void *a0, const void *a1, int a_g5,
+               const void *t0, const void *t1, size_t step_bytes, int len0, int len,
+               double coef_first, double coef_rest, int accumulate, hipStream_t s) {
   if (len <= 0) return OVL_OK;
   const dim3 grid((unsigned)((g->g.V + 63) / 64));
   switch (prec) {
     case P_F64:
       link_vjp_kernel<double, double2, double2><<<grid, 256, 0, s>>>(
-          (double2 *)G, (const double2 *)a0, (int64_t)(step_bytes / sizeof(double2)),
-          (const double2 *)t0, (int64_t)(step_bytes / sizeof(double2)), len, coef_first,
-          coef_rest, g->g, a_g5, accumulate);
+          (double2 *)G, (const double2 *)a0, (const double2 *)a1,
+          (int64_t)(step_bytes / sizeof(double2)), (const double2 *)t0, (const double2 *)t1,
+          (int64_t)(step_bytes / sizeof(double2)), len0, len, coef_first, coef_rest, g->g, a_g5,
+          accumulate);
       break;
     case P_F32:
     case P_F32_BF16:
       link_vjp_kernel<float, float2, float2><<<grid, 256, 0, s>>>(
-          (float2 *)G, (const float2 *)a0, (int64_t)(step_bytes / sizeof(float2)),
-          (const float2 *)t0, (int64_t)(step_bytes / sizeof(float2)), len, coef_first, coef_rest,
-          g->g, a_g5, accumulate);
+          (float2 *)G, (const float2 *)a0, (const float2 *)a1,
+          (int64_t)(step_bytes / sizeof(float2)), (const float2 *)t0, (const float2 *)t1,
+          (int64_t)(step_bytes / sizeof(float2)), len0, len, coef_first, coef_rest, g->g, a_g5,
+          accumulate);
       break;
     default:
       return fail(OVL_EDTYPE, "bad precision");
@@ -1471,7 +1475,8 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G, const void *chi, const void
   if (rc) return rc;
   if (!psi) return fail(OVL_EINVAL, "psi is NULL");
   if (!fits_u32(36ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "G exceeds 4 GiB");
-  return launch_vjp(prec, g, G, chi, 0, psi, 0, 1, 1.0, 1.0, accumulate, as_stream(stream));
+  return launch_vjp(prec, g, G, chi, chi, 0, psi, psi, 0, 1, 1, 1.0, 1.0, accumulate,
+                    as_stream(stream));
 }
 
 // dL = Re[<b_1, dX t_0> + 2 sum_{m=1}^{N-1} <b_{m+1}, dX t_m>] with b the Clenshaw vectors of chi
@@ -1577,17 +1582,15 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
     // come from the segment above (or the start values)
     for (int m = m1; m >= std::max(m0, 1); --m)
       if ((rc = xstep(bv(m), bv(m + 1), 2.0, chi, al[m], bv(m + 2), -1.0))) return rc;
-    // pairs (b_{m+1}, t_m), m = m0 .. m1, in runs whose ring slots are consecutive
-    int m = m0;
-    while (m <= m1) {
-      const int slot = (m + 1) % R;
-      const int len = std::min(m1 - m + 1, R - slot);
-      const double cf = (m == 0 ? 1.0 : 2.0) / p->lmax;
-      if ((rc = launch_vjp(prec, g, G, bv(m + 1), 1, seg(m - m0), vecp, len, cf, 2.0 / p->lmax, 1,
-                           s)))
-        return rc;
-      m += len;
-    }
+    // pairs (b_{m+1}, t_m), m = m0 .. m1, in one launch: the ring slots of b_{m0+1} .. b_{m1+1}
+    // are consecutive up to one wrap (a segment holds at most S < R pairs), so they form at most
+    // two runs; the t_m are consecutive in the segment buffer
+    const int len = m1 - m0 + 1;
+    const int len0 = std::min(len, R - (m0 + 1) % R);
+    const double cf = (m0 == 0 ? 1.0 : 2.0) / p->lmax;
+    if ((rc = launch_vjp(prec, g, G, bv(m0 + 1), bv(m0 + 1 + len0), 1, seg(0), seg(len0), vecp,
+                         len0, len, cf, 2.0 / p->lmax, 1, s)))
+      return rc;
   }
   return OVL_OK;
 }
