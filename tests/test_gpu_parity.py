@@ -821,3 +821,25 @@ def test_zero_right_hand_sides_rejected(ovl):
     x = dev(latgen.gaussian_spinor(dims, 2))
     assert max_rel(host(ovl.kernel_apply(g, x)), ow.kop(latgen.random_su3_field(dims, 1),
                                                          latgen.gaussian_spinor(dims, 2))) < 1e-14
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_two_row_links_force(ovl, store):
+    """The checkpointed force with two-row link reads against the oracle gradient on the links the
+    kernels see (ragged segments: degree 63, stride ceil(sqrt 63) = 8)."""
+    dims = (4, 4, 4, 4)
+    u = latgen.smeared_field(dims, 10195, steps=1)
+    chi = latgen.gaussian_spinor(dims, 20195)
+    psi = latgen.gaussian_spinor(dims, 20196)
+    alpha = och.coeffs_sign_interp(63, 0.07)
+    g = ovl.GaugeField(dev(u), store)
+    g.reconstruct()
+    p = ovl.Polynomial(alpha, LMAX)
+    if store == "f64":
+        got = host(ovl.sign_force(g, p, dev(chi), dev(psi)))
+        assert max_rel(got, oforce.sign_force(u, chi, psi, alpha, LMAX)) < 1e-12
+        return
+    u_two = complete_third_row(latgen.round_to_f32(u))
+    got = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64)))
+    ref = oforce.sign_force(u_two, latgen.round_to_f32(chi), latgen.round_to_f32(psi), alpha, LMAX)
+    assert rel_err(got, ref) < 1e-5
