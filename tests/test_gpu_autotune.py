@@ -25,7 +25,12 @@ def test_autotune_and_results(tmp_path):
         us = ovl.autotune(g, nrhs=2, cache_path=cache)
         assert us > 0
         cfg = ovl.launch_config(g, nrhs=2)
-        assert cfg[0] in (16, 64, 128)
+        # any candidate may win: one site per lane (8, 16, 64 sites per workgroup), two sites per
+        # lane (128, FP32 only) or an LDS slab (order 2, 64 to 256 sites)
+        if cfg[1] == 2:
+            assert cfg[0] in (64, 128, 192, 256)
+        else:
+            assert cfg[0] in ((8, 16, 64) if store == "f64" else (8, 16, 64, 128))
         assert ovl.autotune_load(cache) == 1
         got = ovl.kernel_apply(g, torch.from_numpy(psi).cuda().to(cdt)).cpu().numpy()
         for r in range(2):
