@@ -157,12 +157,16 @@ int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, voi
 int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
                       int dagger, void *out, const void *in, int nrhs, int spin_dt, void *stream);
 
-/* Batched form of ovl_sign_apply (no deflation): up to 16 lattice problems -- each its own gauge
- * field, volume and right-hand-side count -- evaluated with one polynomial in one kernel launch
- * per K application, so small volumes fill the GPU together and the right-hand sides of one field
- * share its links through L2.  All items must have the same operator precision (spin_dt and link
- * storage).  Errors as ovl_sign_apply, plus EINVAL (n_items outside [1, 16]) and EALIAS (an
- * output overlapping any item's input or another output). */
+/* Batched form of ovl_sign_apply (no deflation; Sec. 2, eq. 3): up to 16 lattice problems --
+ * each its own gauge field, volume and right-hand-side count -- evaluated with one polynomial in
+ * one kernel launch per K application, so small volumes fill the GPU together and the
+ * right-hand sides of one field share its links.  All items must have the same operator
+ * precision (spin_dt and link storage).  The launch uses the configuration ovl_autotune measured
+ * for the same problem set (same item order, extents, right-hand-side counts and precision),
+ * else the default rules.  tune_cache_path (nullable): a tuning cache written by ovl_autotune,
+ * read the first time this process names it, before the configuration is looked up.
+ * Errors as ovl_sign_apply, plus EINVAL (n_items outside [1, 16], unreadable cache) and EALIAS
+ * (an output overlapping any item's input or another output). */
 typedef struct {
   const ovl_gauge *g; /* gauge field of this item                                  */
   const void *in;     /* [nrhs][4][3][V] complex of spin_dt                        */
@@ -170,7 +174,7 @@ typedef struct {
   int nrhs;
 } ovl_batch_item;
 int ovl_batch_sign_apply(const ovl_batch_item *items, int n_items, const ovl_poly *p, int spin_dt,
-                         void *stream);
+                         const char *tune_cache_path, void *stream);
 
 /* c_dev[r][i] = phi_i^+ in_r (complex double, interleaved; n_ev * nrhs entries), FP64
  * accumulation with a deterministic two-pass reduction (Sec. 2, eq. 3 projection). */
@@ -236,29 +240,42 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
 
 /* ---- launch tuning ------------------------------------------------------------------------ */
 
-/* Measure the fused stencil kernel on this gauge field for nrhs right-hand sides of spin_dt over
- * its launch configurations and keep the fastest for every later call with the same extents,
- * precision and nrhs.  A configuration is (spb, order, remap).  Order 1 = t-streaming tile order,
- * 0 = memory order, with spb = 8 (eight threads per site: forward and backward hops on separate
- * threads), 16 or 64 (four threads per site) or 128 (two x-adjacent sites per lane).  Order 2 =
- * LDS slab of whole x lines with spb = 64, 128, 192 or 256 sites (single problems; spb a multiple
- * of Lx dividing Lx Ly).  Remap = XCD-contiguous workgroup ranges on or off.  The winner is
- * appended to the text file cache_path when not NULL (one line: Lx Ly Lz Lt precision nrhs spb
- * order remap microseconds).  *best_us (nullable) receives the winner's time per K application.
- * Synchronises the stream; allocates two temporary vectors.
- * Errors: EINVAL, EDTYPE, EDIMS, ENOMEM, EHIP. */
-int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_path,
-                 double *best_us, void *stream);
-/* Load configurations written by ovl_autotune; returns the number of entries read (>= 0) or
- * OVL_EINVAL when the file cannot be opened. */
+/* Measure the fused Chebyshev step kernel (Sec. 2: stencil and polynomial algebra in one
+ * kernel) on a problem set -- one item: the single-problem launch of ovl_sign_apply and the
+ * other operators; several: the batched launch of ovl_batch_sign_apply -- over its launch
+ * configurations and keep the fastest for every later launch of the same problem set (the
+ * precision and each item's extents and right-hand-side count, in order).  A configuration is
+ * (spb, order, remap, rb).  Order 1 = t-streaming tile order, 0 = memory order, with spb = 8
+ * (eight threads per site: forward and backward hops on separate threads), 16 or 64 (four threads
+ * per site) or 128 (two x-adjacent sites per lane).  Order 2 = LDS slab of whole x lines with
+ * spb = 64, 128, 192 or 256 sites (single problems; spb a multiple of Lx dividing Lx Ly).
+ * Remap = XCD-contiguous workgroup ranges on or off.  rb = right-hand-side block: 1, 2 or 4
+ * right-hand sides per thread reusing one read of the thread's two links (spb 16 or 64, orders
+ * 0 and 1).  Each candidate runs 2 untimed and 10 timed steps that read the items' inputs and
+ * write their outputs (the outputs' contents are then undefined).  p (nullable) supplies lmax and
+ * m_W for the step's coefficients.  The winner is appended to the text file cache_path when not
+ * NULL (one line: B prec n_items, then Lx Ly Lz Lt nrhs per item, then spb order remap rb
+ * microseconds).  *best_us (nullable) receives the winner's time per step.  Synchronises the
+ * stream.  Errors: as ovl_batch_sign_apply, ENOMEM, EHIP. */
+int ovl_autotune(const ovl_batch_item *items, int n_items, const ovl_poly *p, int spin_dt,
+                 const char *cache_path, double *best_us, void *stream);
+/* Load configurations written by ovl_autotune (also the single-problem short form
+ * "Lx Ly Lz Lt precision nrhs spb order remap microseconds", rb = 1); returns the number of
+ * entries read (>= 0) or OVL_EINVAL when the file cannot be opened. */
 int ovl_autotune_load(const char *cache_path);
-/* The configuration the library will use: cfg_out = {sites per workgroup, order, remap}
- * (see ovl_autotune).  Defaults: 8 sites per workgroup below 4K site-right-hand-sides, 16 below
- * 64K, else 64 in tile order, with 128 (two sites per lane) for FP32 links from 512K
- * site-right-hand-sides; remap on.  Two sites per lane need FP32 spinors, an even Lx and 16-byte
- * aligned vectors (a call whose vectors are not aligned runs with 64); a slab entry that does not
- * fit the lattice falls back to the default. */
+/* The configuration the library will use for a single problem: cfg_out = {sites per workgroup,
+ * order, remap} (see ovl_autotune).  Defaults: 8 sites per workgroup below 4K
+ * site-right-hand-sides, 16 below 64K, else 64 in tile order, with 128 (two sites per lane) for
+ * FP32 links from 512K site-right-hand-sides; remap on; rb 1.  Two sites per lane need FP32
+ * spinors, an even Lx and 16-byte aligned vectors (a call whose vectors are not aligned runs
+ * with 64); a slab entry that does not fit the lattice falls back to the default. */
 int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]);
+/* The configuration an evaluation of this problem set will use (the batched launch for several
+ * items, the single-problem launch for one): cfg_out = {spb, order, remap, rb}, with the items'
+ * own vectors deciding whether two sites per lane are possible.  Errors: as
+ * ovl_batch_sign_apply. */
+int ovl_batch_launch_config(const ovl_batch_item *items, int n_items, int spin_dt,
+                            int cfg_out[4]);
 
 /* ---- diagnostics ------------------------------------------------------------------------- */
 

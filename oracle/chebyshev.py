@@ -113,7 +113,7 @@ def poly_apply(u, psi, alpha, lmax, m_w=M_W):
 
 
 def chebyshev_vectors(u, psi, n, lmax, m_w=M_W):
-    """[T_0(X) psi, ..., T_n(X) psi] by the forward recurrence (used by checks and the force)."""
+    """[T_0(X) psi, ..., T_n(X) psi] by the forward recurrence (used by the tests)."""
     out = [psi.astype(np.complex128)]
     if n >= 1:
         out.append(kop(u, out[0], m_w) / lmax)

@@ -38,7 +38,7 @@ SIGNATURES = {
     "ovl_kernel_axpby": (_i, [_vp, _vp, _vp, _d, _vp, _d, _vp, _d, _i, _i, _d, _vp]),
     "ovl_sign_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_overlap_apply": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
-    "ovl_batch_sign_apply": (_i, [_vp, _i, _vp, _i, _vp]),
+    "ovl_batch_sign_apply": (_i, [_vp, _i, _vp, _i, ctypes.c_char_p, _vp]),
     "ovl_defl_project": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "ovl_defl_correct": (_i, [_vp, _vp, _vp, _dp, _i, _i, _vp]),
     "ovl_wilson_link_vjp": (_i, [_vp, _vp, _vp, _vp, _i, _i, _vp]),
@@ -46,9 +46,10 @@ SIGNATURES = {
     "ovl_sign_residual": (_i, [_vp, _vp, _vp, _vp, _i, _i, _dp, _vp]),
     "ovl_overlap_solve": (_i, [_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _d, _i,
                                ctypes.POINTER(_i), _dp, _vp]),
-    "ovl_autotune": (_i, [_vp, _i, _i, ctypes.c_char_p, _dp, _vp]),
+    "ovl_autotune": (_i, [_vp, _i, _vp, _i, ctypes.c_char_p, _dp, _vp]),
     "ovl_autotune_load": (_i, [ctypes.c_char_p]),
     "ovl_launch_config": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
+    "ovl_batch_launch_config": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),
     "ovl_last_error": (ctypes.c_char_p, []),
     "ovl_status_flags": (_i, [_vp, ctypes.POINTER(ctypes.c_uint32), _i]),
     "ovl_graph_enable": (_i, [_i]),

@@ -274,9 +274,8 @@ def overlap_solve(g: GaugeField, poly: Polynomial, b, mu: float, defl: Deflation
     return x, it.value, res.value
 
 
-def batch_sign_apply(poly: Polynomial, problems, outs=None):
-    """sum_m alpha_m T_m(X_i) psi_i for a list of (GaugeField, psi) problems in one launch per
-    K application (Sec. 2, eq. 3 without deflation).  Returns the list of outputs."""
+def _batch_items(problems, outs=None):
+    """ovl_batch_item array for a list of (GaugeField, psi) problems, with their outputs."""
     if not 1 <= len(problems) <= 16:
         raise ValueError("between 1 and 16 problems")
     arr = (_lib.BatchItem * len(problems))()
@@ -288,7 +287,17 @@ def batch_sign_apply(poly: Polynomial, problems, outs=None):
         dt = _spin_dtype(psi)
         arr[i] = _lib.BatchItem(g.handle.value, psi.data_ptr(), out.data_ptr(), nrhs)
         res.append(out)
-    call("ovl_batch_sign_apply", arr, len(problems), poly._h, dt, _stream())
+    return arr, res, dt
+
+
+def batch_sign_apply(poly: Polynomial, problems, outs=None, tune_cache: str = None):
+    """sum_m alpha_m T_m(X_i) psi_i for a list of (GaugeField, psi) problems in one launch per
+    K application (Sec. 2, eq. 3 without deflation), in the configuration ``autotune`` measured
+    for the same problem set (``tune_cache``: a cache file to read first).  Returns the list of
+    outputs."""
+    arr, res, dt = _batch_items(problems, outs)
+    call("ovl_batch_sign_apply", arr, len(problems), poly._h, dt,
+         tune_cache.encode() if tune_cache else None, _stream())
     return res
 
 
@@ -370,14 +379,31 @@ class SignFunction(torch.autograd.Function):
         return grad_u, grad_psi, None, None
 
 
-def autotune(g: GaugeField, nrhs: int = 1, dtype=None, cache_path: str = None) -> float:
-    """Pick the fastest launch configuration of the fused stencil for this lattice; returns its
-    microseconds per K application.  The choice applies to every later call in this process."""
-    dt = _spin_dtype(torch.empty(0, dtype=dtype or g.spin_dtype))
+def autotune(problems, poly: Polynomial = None, cache_path: str = None, outs=None) -> float:
+    """Pick the fastest launch configuration of the fused Chebyshev step for a problem set: a list
+    of (GaugeField, psi) problems (the batched launch) or one such pair (the single-problem launch
+    of every operator).  Returns its microseconds per step; the choice applies to every later
+    launch of the same problem set in this process.  The outputs (``outs`` or temporaries) are
+    overwritten."""
+    if isinstance(problems, tuple) and len(problems) == 2 and isinstance(problems[0], GaugeField):
+        problems = [problems]
+    arr, _, dt = _batch_items(problems, outs)
     us = ctypes.c_double(0)
-    call("ovl_autotune", g.handle, int(nrhs), dt, cache_path.encode() if cache_path else None,
-         ctypes.byref(us), _stream())
+    call("ovl_autotune", arr, len(problems), poly._h if poly is not None else None, dt,
+         cache_path.encode() if cache_path else None, ctypes.byref(us), _stream())
     return us.value
+
+
+def batch_launch_config(problems):
+    """(sites per workgroup, order, XCD remap, right-hand-side block) an evaluation of this
+    problem set (a list of (GaugeField, psi) pairs, or one pair) will use."""
+    if isinstance(problems, tuple) and len(problems) == 2 and isinstance(problems[0], GaugeField):
+        problems = [problems]
+    outs = [torch.empty_like(psi) for _, psi in problems]   # distinct outputs for the checks
+    arr, _, dt = _batch_items(problems, outs)
+    out = (ctypes.c_int * 4)()
+    call("ovl_batch_launch_config", arr, len(problems), dt, out)
+    return tuple(out)
 
 
 def autotune_load(cache_path: str) -> int:

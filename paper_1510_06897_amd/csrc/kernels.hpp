@@ -106,9 +106,15 @@ __global__ void write_item_kernel(StepItem it, StepItem *dst) {
 // arithmetic on each thread's path; threads q < 4 own the spin components afterwards.  Within
 // an item the right-hand side is the fastest logical index, so the workgroups that read the same
 // links run together and share them through L2.
-template <class C, class SE, class LE, int SPB, bool TABLE, int NQ = 4, bool R12 = false>
+//
+// RB > 1 (right-hand-side block, NQ = 4): a workgroup takes RB consecutive right-hand sides of
+// its sites; each thread reads its direction's two links once into registers and reuses them for
+// the RB right-hand sides, one after the other (the LDS exchange is reused per right-hand side).
+template <class C, class SE, class LE, int SPB, bool TABLE, int NQ = 4, bool R12 = false,
+          int RB = 1>
 __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   static_assert(NQ == 4 || NQ == 8, "4 or 8 threads per site");
+  static_assert(RB == 1 || NQ == 4, "right-hand-side blocks take four threads per site");
   __shared__ double lds[2 * 16];
   __shared__ cx<C> part[NQ][12][SPB];  // directional partial sums
   const int gb = xcd_block(blockIdx.x, gridDim.x, p.remap);
@@ -120,9 +126,10 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   const Ext4 ex = ext_of(I.g);
   constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
+  const int nrb = (nrhs + RB - 1) / RB;  // right-hand-side blocks of the item
   const int lb = gb - I.blk0;
-  const int r = lb % nrhs;
-  const int b = lb / nrhs;
+  const int r0 = (lb % nrb) * RB;
+  const int b = lb / nrb;
   const int q = threadIdx.x / SPB;
   const int sl = threadIdx.x % SPB;
   const int dq = q & 3;       // direction of the thread's hop(s)
@@ -155,15 +162,21 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;  // component stride (bytes)
   const uint32_t vb = 12u * cs;                               // one right-hand side (bytes)
   const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
-  const int64_t base = (int64_t)r * 12 * V;
   const bool lower = q >= 2;                                  // spin components 2, 3
-  auto vec = [&](int role) -> const SE * {
-    const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
-    return reinterpret_cast<const SE *>(ptr) + base;
-  };
-  double nrm[2] = {0.0, 0.0};
-  const rsrc_t v = make_rsrc(vec(p.v_role), vb);
   const bool vg5 = p.v_g5 != 0;
+  int fwd = 0, bwd = 0;
+  if (active) dir_neighbours(ex, c4, site, dq, fwd, bwd);
+  const DirCoef<C> k = dir_coef<C>(dq);
+  const uint32_t lane_links = (uint32_t)dq * 9u * (uint32_t)I.lstride;
+  // right-hand-side blocks: the thread's two links, read once for the RB right-hand sides
+  cx<C> mfw[RB > 1 ? 3 : 1][3], mbw[RB > 1 ? 3 : 1][3];
+  if constexpr (RB > 1) {
+    if (active) {
+      const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
+      load_link3<C, LE>(U, ls, lane_links + link_lane(site), r12, mfw);
+      load_link3<C, LE>(U, ls, lane_links + link_lane(bwd), r12, mbw);
+    }
+  }
   // After the LDS exchange the thread owns spin component q of its site.  Small launches
   // (SPB < 64: few waves per CU, bound by memory latency) load the operands of that component's
   // vector algebra before the stencil so the two latencies overlap; large launches load them
@@ -171,111 +184,130 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   constexpr bool kEarly = SPB < 64;
   const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + site;  // element of component 3q
   const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
-  cx<C> vx[3], srcx[3], wx[3];
-  auto load_ops = [&]() {
+#pragma unroll 1
+  for (int rr = 0; rr < RB; ++rr) {
+    const int r = r0 + rr;
+    const bool ractive = r < nrhs;   // the last block of an item may be ragged
+    const bool act = active && ractive;
+    const int64_t base = (int64_t)(ractive ? r : 0) * 12 * V;
+    auto vec = [&](int role) -> const SE * {
+      const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
+      return reinterpret_cast<const SE *>(ptr) + base;
+    };
+    double nrm[2] = {0.0, 0.0};
+    const rsrc_t v = make_rsrc(vec(p.v_role), vb);
+    cx<C> vx[3], srcx[3], wx[3];
+    auto load_ops = [&]() {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vx[c] = srcx[c] = wx[c] = mk<C>(0, 0);
-    if (!active || !owner) return;
+      for (int c = 0; c < 3; ++c) vx[c] = srcx[c] = wx[c] = mk<C>(0, 0);
+      if (!act || !owner) return;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vx[c] = bldv<C, SE>(v, e0 + c * V);
-    if (need_src) {
-      const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
+      for (int c = 0; c < 3; ++c) vx[c] = bldv<C, SE>(v, e0 + c * V);
+      if (need_src) {
+        const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(sr, e0 + c * V);
-    }
-    if (p.w_role != ROLE_NONE) {
-      const rsrc_t w = make_rsrc(vec(p.w_role), vb);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) wx[c] = bldv<C, SE>(w, e0 + c * V);
-    }
-  };
-  if (kEarly) load_ops();
-  {
-    cx<C> acc[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
-    if (active) {
-      const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
-      int fwd, bwd;
-      dir_neighbours(ex, c4, site, dq, fwd, bwd);
-      const DirCoef<C> k = dir_coef<C>(dq);
-      const uint32_t lane_links = (uint32_t)dq * 9u * (uint32_t)I.lstride;
-      if (NQ == 4) {
-        quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + link_lane(site), k, C(1),
-                                   vg5, r12);
-        quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + link_lane(bwd), k, C(-1),
-                                  vg5, r12);
-      } else {
-        const bool bw = q >= 4;
-        quad_hop_sel<C, SE, LE>(acc, v, cs, U, ls, bw ? bwd : fwd,
-                                lane_links + link_lane(bw ? bwd : site), k, bw, vg5, r12);
+        for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(sr, e0 + c * V);
       }
-    }
+      if (p.w_role != ROLE_NONE) {
+        const rsrc_t w = make_rsrc(vec(p.w_role), vb);
 #pragma unroll
-    for (int i = 0; i < 12; ++i) part[q][i][sl] = acc[i];
-  }
-  __syncthreads();
-  if (!kEarly) load_ops();
-  if (active && owner) {
-    cx<C> hop[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      hop[c] = part[0][3 * q + c][sl] + part[1][3 * q + c][sl] + part[2][3 * q + c][sl] +
-               part[3][3 * q + c][sl];
-      if (NQ == 8)
-        hop[c] = hop[c] + (part[4][3 * q + c][sl] + part[5][3 * q + c][sl] +
-                           part[6][3 * q + c][sl] + part[7][3 * q + c][sl]);
-    }
-    const C kd = C(p.kd), kh = C(p.kh);
-    cx<C> res[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const cx<C> x = (vg5 && lower) ? -vx[c] : vx[c];
-      cx<C> y = mk<C>(kd * x.re + kh * hop[c].re, kd * x.im + kh * hop[c].im);
-      if (p.y_g5 && lower) y = -y;
-      res[c] = y;
-    }
-    if (p.a != 0.0) {
-      const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
-    }
-    if (p.w_role != ROLE_NONE) {
-      const C t = C(p.t);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(wx[c], t);
-    }
-    if (p.mode >= MODE_SIGN) {
-      for (int e = 0; e < I.n_ev; ++e) {
-        const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(I.phi) + (int64_t)e * 12 * V, vb);
-        const double2 ce = I.c[r * I.n_ev + e];
-        const double we = I.wdefl[e];
-        const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) res[c] = cmadd(res[c], bldv<C, SE>(ph, e0 + c * V), d);
+        for (int c = 0; c < 3; ++c) wx[c] = bldv<C, SE>(w, e0 + c * V);
       }
+    };
+    if (kEarly) load_ops();
+    {
+      cx<C> acc[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
+      if (act) {
+        if constexpr (RB > 1) {
+          cx<C> u[2][3], d[2][3];
+          load_spinor<C, SE>(v, cs, fwd, vg5, u, d);
+          hop_apply<C, false>(acc, u, d, mfw, k, C(1));
+          load_spinor<C, SE>(v, cs, bwd, vg5, u, d);
+          hop_apply<C, true>(acc, u, d, mbw, k, C(-1));
+        } else {
+          const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
+          if (NQ == 4) {
+            quad_hop<C, SE, LE, false>(acc, v, cs, U, ls, fwd, lane_links + link_lane(site), k,
+                                       C(1), vg5, r12);
+            quad_hop<C, SE, LE, true>(acc, v, cs, U, ls, bwd, lane_links + link_lane(bwd), k,
+                                      C(-1), vg5, r12);
+          } else {
+            const bool bw = q >= 4;
+            quad_hop_sel<C, SE, LE>(acc, v, cs, U, ls, bw ? bwd : fwd,
+                                    lane_links + link_lane(bw ? bwd : site), k, bw, vg5, r12);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 12; ++i) part[q][i][sl] = acc[i];
+    }
+    __syncthreads();
+    if (!kEarly) load_ops();
+    if (act && owner) {
+      cx<C> hop[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        nrm[0] += double(res[c].re) * double(res[c].re) + double(res[c].im) * double(res[c].im);
-        nrm[1] += double(srcx[c].re) * double(srcx[c].re) + double(srcx[c].im) * double(srcx[c].im);
+        hop[c] = part[0][3 * q + c][sl] + part[1][3 * q + c][sl] + part[2][3 * q + c][sl] +
+                 part[3][3 * q + c][sl];
+        if (NQ == 8)
+          hop[c] = hop[c] + (part[4][3 * q + c][sl] + part[5][3 * q + c][sl] +
+                             part[6][3 * q + c][sl] + part[7][3 * q + c][sl]);
       }
-      if (p.mode == MODE_OVERLAP || p.mode == MODE_OVERLAP_DAG) {
-        const C hp = C(0.5 * (1.0 + p.mu));
-        const C hm = (p.mode == MODE_OVERLAP && lower) ? C(-0.5 * (1.0 - p.mu)) : C(0.5 * (1.0 - p.mu));
+      const C kd = C(p.kd), kh = C(p.kh);
+      cx<C> res[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) res[c] = scale(srcx[c], hp) + scale(res[c], hm);
+      for (int c = 0; c < 3; ++c) {
+        const cx<C> x = (vg5 && lower) ? -vx[c] : vx[c];
+        cx<C> y = mk<C>(kd * x.re + kh * hop[c].re, kd * x.im + kh * hop[c].im);
+        if (p.y_g5 && lower) y = -y;
+        res[c] = y;
+      }
+      if (p.a != 0.0) {
+        const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
+      }
+      if (p.w_role != ROLE_NONE) {
+        const C t = C(p.t);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(wx[c], t);
+      }
+      if (p.mode >= MODE_SIGN) {
+        for (int e = 0; e < I.n_ev; ++e) {
+          const rsrc_t ph = make_rsrc(reinterpret_cast<const SE *>(I.phi) + (int64_t)e * 12 * V, vb);
+          const double2 ce = I.c[r * I.n_ev + e];
+          const double we = I.wdefl[e];
+          const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) res[c] = cmadd(res[c], bldv<C, SE>(ph, e0 + c * V), d);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          nrm[0] += double(res[c].re) * double(res[c].re) + double(res[c].im) * double(res[c].im);
+          nrm[1] += double(srcx[c].re) * double(srcx[c].re) + double(srcx[c].im) * double(srcx[c].im);
+        }
+        if (p.mode == MODE_OVERLAP || p.mode == MODE_OVERLAP_DAG) {
+          const C hp = C(0.5 * (1.0 + p.mu));
+          const C hm = (p.mode == MODE_OVERLAP && lower) ? C(-0.5 * (1.0 - p.mu)) : C(0.5 * (1.0 - p.mu));
+#pragma unroll
+          for (int c = 0; c < 3; ++c) res[c] = scale(srcx[c], hp) + scale(res[c], hm);
+        }
+      }
+      const rsrc_t o = make_rsrc(vec(p.out_role), vb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) bstv<C, SE>(o, e0 + c * V, res[c]);
+    }
+    if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
+      block_sum<2>(nrm, lds);
+      if (threadIdx.x == 0 && ractive) {
+        const int64_t pb = (int64_t)b * nrhs + r;  // partial of (site block b, right-hand side r)
+        I.norm_partial[pb * 2 + 0] = nrm[0];
+        I.norm_partial[pb * 2 + 1] = nrm[1];
       }
     }
-    const rsrc_t o = make_rsrc(vec(p.out_role), vb);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) bstv<C, SE>(o, e0 + c * V, res[c]);
-  }
-  if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
-    block_sum<2>(nrm, lds);
-    if (threadIdx.x == 0) {
-      I.norm_partial[(int64_t)lb * 2 + 0] = nrm[0];
-      I.norm_partial[(int64_t)lb * 2 + 1] = nrm[1];
-    }
+    if constexpr (RB > 1) __syncthreads();  // part[] and lds[] are reused by the next one
   }
 }
 
@@ -933,6 +965,36 @@ __global__ void __launch_bounds__(kBlock)
   for (int i = 0; i < 12; ++i) store_c(io, (int64_t)i * V + site, acc[i]);
 }
 
+// inout_r += sum_{e0 <= i < e0 + ne} phi_i (w.v[i - e0] * c[r][i]) with the weights passed by value
+// in the kernel arguments (the public correction entry point: nothing to stage on the device)
+constexpr int kWChunk = 256;
+struct WChunk {
+  double v[kWChunk];
+};
+template <class C, class SE>
+__global__ void __launch_bounds__(kBlock)
+    correct_w_kernel(SE *inout, const SE *__restrict__ phi, int e0, int ne, int n_ev,
+                     const double2 *__restrict__ c, WChunk w, int V) {
+  const int site = blockIdx.x * kBlock + threadIdx.x;
+  const int r = blockIdx.y;
+  if (site >= V) return;
+  SE *io = inout + (int64_t)r * 12 * V;
+  cx<C> acc[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = load_c<C>(io, (int64_t)i * V + site);
+  for (int k = 0; k < ne; ++k) {
+    const int e = e0 + k;
+    const double2 ce = c[r * n_ev + e];
+    const double we = w.v[k];
+    const cx<C> d = mk<C>(C(ce.x * we), C(ce.y * we));
+#pragma unroll
+    for (int i = 0; i < 12; ++i)
+      acc[i] = cmadd(acc[i], load_c<C>(phi, ((int64_t)e * 12 + i) * V + site), d);
+  }
+#pragma unroll
+  for (int i = 0; i < 12; ++i) store_c(io, (int64_t)i * V + site, acc[i]);
+}
+
 // v *= 1 / sqrt(nrm2[0].x); records the norm before scaling into norms[slot]
 __global__ void normalize_kernel(double2 *v, const double2 *nrm2, int64_t n, double *norms,
                                  int slot) {
@@ -1049,17 +1111,22 @@ __global__ void __launch_bounds__(256) su3_row2_dev_kernel(const LE *U, int V, d
 // ((1 -+ gamma_mu)/2 are Hermitian projectors, so the 4-spin sums reduce to half-spinor sums.)
 // Pair i < len0 uses a_i = a0 + i * a_step and t_i = t0 + i * t_step (elements), pair i >= len0
 // the second run a1 + (i - len0) * a_step, t1 + (i - len0) * t_step; coef = coef_first for i = 0
-// and coef_rest otherwise.  Thread (site, mu) owns link G_mu(x): it accumulates the whole
-// segment in registers and reads and writes G once (gather only, no atomics).  The four
-// direction waves of a workgroup share the 64 sites: a(x) and t(x) are read from HBM once per
-// workgroup (wave mu loads spin-colour components 3 mu .. 3 mu + 2) and handed over in LDS,
-// double-buffered so that one barrier per pair suffices; the forward neighbours a(x+mu),
+// and coef_rest otherwise.  Thread (site, mu) owns link G_mu(x): the outer products of one pair
+// are formed in the compute precision C and added into FP64 registers, so the sum over the
+// segment's pairs (and, through the FP64 running buffer, over all segments) is FP64 whatever the
+// storage precision; G is read and written once per launch (gather only, no atomics).
+//   in_mode:  0 start from zero, 1 add the FP64 running sum G64, 2 add G (output dtype GE)
+//   out_mode: 0 write the FP64 running sum G64, 1 write G
+// The four direction waves of a workgroup share the 64 sites: a(x) and t(x) are read from HBM
+// once per workgroup (wave mu loads spin-colour components 3 mu .. 3 mu + 2) and handed over in
+// LDS, double-buffered so that one barrier per pair suffices; the forward neighbours a(x+mu),
 // t(x+mu) are read per thread, issued before the barrier.
 template <class C, class SE, class GE>
 __global__ void __launch_bounds__(256)
-    link_vjp_kernel(GE *G, const SE *a0, const SE *a1, int64_t a_step, const SE *t0,
-                    const SE *t1, int64_t t_step, int len0, int len, double coef_first,
-                    double coef_rest, Geom geo, int a_g5, int accumulate) {
+    link_vjp_kernel(GE *G, double2 *G64, const SE *a0, const SE *a1, int64_t a_step,
+                    const SE *t0, const SE *t1, int64_t t_step, int len0, int len,
+                    double coef_first, double coef_rest, Geom geo, int a_g5, int in_mode,
+                    int out_mode) {
   const int mu = threadIdx.x >> 6, sl = threadIdx.x & 63;
   const int site = blockIdx.x * 64 + sl;
   const Ext4 ex = ext_of(geo);
@@ -1073,11 +1140,11 @@ __global__ void __launch_bounds__(256)
   const uint32_t cs = (uint32_t)ex.V * elem_traits<SE>::bytes;
   // own-site spinors of the 64 sites: [buffer][a, t][component][site]
   __shared__ cx<C> own[2][2][12][64];
-  cx<C> acc[3][3];
+  cx<double> acc[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) acc[i][j] = mk<C>(0, 0);
+    for (int j = 0; j < 3; ++j) acc[i][j] = mk<double>(0, 0);
   for (int pi = 0; pi < len; ++pi) {
     const int b = pi & 1;
     const bool first_run = pi < len0;
@@ -1122,7 +1189,7 @@ __global__ void __launch_bounds__(256)
           od[s2][c] = own[b][1][(s2 + 2) * 3 + c][sl];
         }
       dir_project(ou, od, k, C(-1), hpt);
-      const C cf = C(pi == 0 ? coef_first : coef_rest);
+      const double cf = pi == 0 ? coef_first : coef_rest;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -1133,22 +1200,26 @@ __global__ void __launch_bounds__(256)
             s = cjmadd(s, hmt[kk][j], hma[kk][i]);
             s = cjmadd(s, hpa[kk][j], hpt[kk][i]);
           }
-          acc[i][j] = acc[i][j] + scale(s, cf);
+          acc[i][j].re = fma(cf, double(s.re), acc[i][j].re);
+          acc[i][j].im = fma(cf, double(s.im), acc[i][j].im);
         }
     }
   }
   if (!active) return;
   const uint32_t gs = (uint32_t)ex.V * elem_traits<GE>::bytes;
+  const uint32_t gs64 = (uint32_t)ex.V * 16u;
   const rsrc_t rg = make_rsrc(G, 36u * gs);
-  const C half = C(-0.5);
+  const rsrc_t rg64 = make_rsrc(G64, 36u * gs64);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const uint32_t so = ((uint32_t)mu * 9u + (uint32_t)(i * 3 + j)) * gs;
-      cx<C> v = scale(acc[i][j], half);
-      if (accumulate) v = v + bld<C, GE>(rg, so, site);
-      bst<C, GE>(rg, so, site, v);
+      const uint32_t comp = (uint32_t)mu * 9u + (uint32_t)(i * 3 + j);
+      cx<double> v = scale(acc[i][j], -0.5);
+      if (in_mode == 1) v = v + bld<double, double2>(rg64, comp * gs64, site);
+      else if (in_mode == 2) v = v + bld<double, GE>(rg, comp * gs, site);
+      if (out_mode == 0) bst<double, double2>(rg64, comp * gs64, site, v);
+      else bst<double, GE>(rg, comp * gs, site, v);
     }
 }
 

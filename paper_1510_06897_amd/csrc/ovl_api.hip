@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -137,9 +138,20 @@ struct ovl_defl {
   double2 *phi64;     // [n_ev][12][V] orthonormal, FP64
   void *phi_store;    // same in store_dt (== phi64 for F64)
   std::vector<double> lambda;
-  double *w_dev;      // weights for the polynomial with serial w_serial
-  std::vector<double> w_host;
-  uint64_t w_serial;
+  // Eigenvalue-correction weights w_i = sign(lambda_i) - p(lambda_i / lmax) of the last few
+  // polynomials used with this basis: slot k holds the weights of the polynomial with serial
+  // w_serial[k] in w_dev + k n_ev, uploaded from pinned staging w_pin + k n_ev on the caller's
+  // stream (event w_evt[k] marks the upload), so a call never waits for the device and a new
+  // polynomial never overwrites weights another polynomial's pending work reads.
+  static constexpr int kWSlots = 8;
+  double *w_dev;
+  double *w_pin;
+  hipEvent_t w_evt[kWSlots];
+  bool w_evt_live[kWSlots];
+  uint64_t w_serial[kWSlots];
+  uint64_t w_stamp[kWSlots];
+  double w_absmax[kWSlots];  // max |w_i|, for the norm bound of the final check
+  uint64_t w_clock;
   std::mutex mu;
 };
 
@@ -229,17 +241,19 @@ void step_tile(const Geom &g, int spb, int site_bytes, int &ty, int &tz) {
   }
 }
 
-// Launch configuration of the fused step kernel: sites per workgroup, t-streaming tile order
-// (where a tile fits) and the XCD-contiguous workgroup remap.  Default rules unless ovl_autotune
-// measured a better one for the lattice, precision and right-hand-side count.
+// Launch configuration of the fused step kernel: sites per workgroup, workgroup order (memory
+// order, t-streaming tiles where a tile fits, or the LDS slab), the XCD-contiguous workgroup
+// remap and the right-hand-side block (right-hand sides per thread sharing one link read).
+// Default rules unless ovl_autotune measured a better one for the same problem set: the
+// precision and the (extents, right-hand-side count) of every item of the launch, in order.
 struct LaunchCfg {
-  int spb, tiles, remap;
+  int spb, tiles, remap, rb;
 };
 struct TuneKey {
-  int L[4], prec, nrhs;
+  int prec;
+  std::vector<std::array<int, 5>> items;  // Lx Ly Lz Lt nrhs per item
   bool operator<(const TuneKey &o) const {
-    return std::lexicographical_compare(L, L + 4, o.L, o.L + 4) ||
-           (std::equal(L, L + 4, o.L) && (prec < o.prec || (prec == o.prec && nrhs < o.nrhs)));
+    return prec < o.prec || (prec == o.prec && items < o.items);
   }
 };
 std::mutex g_tune_mu;
@@ -247,14 +261,30 @@ std::map<TuneKey, LaunchCfg> g_tuned;
 
 LaunchCfg default_cfg(int64_t work, int prec = P_F64) {
   const int spb = (prec == P_F32 && work >= 512 * 1024) ? 128 : launch_spb(work);
-  return LaunchCfg{spb, 1, 1};
+  return LaunchCfg{spb, 1, 1, 1};
 }
 
-LaunchCfg lookup_cfg(const Geom &g, int prec, int nrhs, int64_t work) {
-  TuneKey k{{g.L[0], g.L[1], g.L[2], g.L[3]}, prec, nrhs};
+TuneKey tune_key(int prec, const StepItem *items, int n) {
+  TuneKey k;
+  k.prec = prec;
+  for (int i = 0; i < n; ++i)
+    k.items.push_back({items[i].g.L[0], items[i].g.L[1], items[i].g.L[2], items[i].g.L[3],
+                       items[i].nrhs});
+  return k;
+}
+
+LaunchCfg lookup_cfg(int prec, const StepItem *items, int n, int64_t work) {
+  const TuneKey k = tune_key(prec, items, n);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tuned.find(k);
   return it == g_tuned.end() ? default_cfg(work, prec) : it->second;
+}
+LaunchCfg lookup_cfg(const Geom &g, int prec, int nrhs, int64_t work) {
+  StepItem it;
+  std::memset(&it, 0, sizeof(it));
+  it.g = g;
+  it.nrhs = nrhs;
+  return lookup_cfg(prec, &it, 1, work);
 }
 
 // two sites per lane need FP32 spinors, an even Lx (pairs never straddle an x line) and 16-byte
@@ -270,8 +300,14 @@ bool pairs_ok(Prec prec, const StepItem *items, int n) {
   }
   return true;
 }
+// right-hand-side blocks exist for the one-site forms with four threads per site (16 and 64
+// sites per workgroup) in the memory and tile orders
+bool rb_ok(const LaunchCfg &c) {
+  return c.rb == 1 || ((c.rb == 2 || c.rb == 4) && (c.spb == 16 || c.spb == 64) && c.tiles != 2);
+}
 LaunchCfg fit_cfg(LaunchCfg c, bool pairs) {
   if (c.spb == 128 && !pairs && c.tiles != 2) c.spb = 64;
+  if (!rb_ok(c)) c.rb = 1;
   return c;
 }
 
@@ -295,7 +331,7 @@ int plan_items(StepItem *items, int n, const LaunchCfg &cfg, int site_bytes) {
     it.blk0 = total;
     it.ty = it.tz = 0;
     if (cfg.tiles == 1) step_tile(it.g, cfg.spb, site_bytes, it.ty, it.tz);
-    total += item_blocks(it.g.V, cfg.spb) * it.nrhs;
+    total += item_blocks(it.g.V, cfg.spb) * ((it.nrhs + cfg.rb - 1) / cfg.rb);
   }
   return total;
 }
@@ -327,9 +363,21 @@ int launch_slab(StepArgs<false> &p, hipStream_t s) {
   return OVL_OK;
 }
 
+template <class C, class SE, class LE, bool TABLE, bool R12, int SPB>
+int launch_rb(StepArgs<TABLE> &p, int rb, hipStream_t s) {
+  switch (rb) {
+    case 1: step_kernel<C, SE, LE, SPB, TABLE, 4, R12, 1><<<p.total_blocks, 4 * SPB, 0, s>>>(p); break;
+    case 2: step_kernel<C, SE, LE, SPB, TABLE, 4, R12, 2><<<p.total_blocks, 4 * SPB, 0, s>>>(p); break;
+    case 4: step_kernel<C, SE, LE, SPB, TABLE, 4, R12, 4><<<p.total_blocks, 4 * SPB, 0, s>>>(p); break;
+    default: return fail(OVL_EINVAL, "no right-hand-side block of %d", rb);
+  }
+  return OVL_OK;
+}
+
 template <class C, class SE, class LE, bool TABLE, bool R12>
-int launch_step_r(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab) {
-  if (slab) {
+int launch_step_r(StepArgs<TABLE> &p, const LaunchCfg &cfg, hipStream_t s) {
+  const int spb = cfg.spb;
+  if (cfg.tiles == 2) {
     if constexpr (TABLE) {
       return fail(OVL_EINVAL, "the slab order takes single problems");
     } else {
@@ -344,20 +392,24 @@ int launch_step_r(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab) {
       }
     }
   }
+  if (cfg.rb != 1 && spb != 64 && spb != 16)
+    return fail(OVL_EINVAL, "right-hand-side blocks need 16 or 64 sites per workgroup");
+  int rc = OVL_OK;
   if (spb == 128) {
     if constexpr (std::is_same<SE, float2>::value)
       step2_kernel<LE, 64, TABLE, R12><<<p.total_blocks, 256, 0, s>>>(p);
     else
       return fail(OVL_EINVAL, "two sites per lane need FP32 spinors");
   } else if (spb == 64) {
-    step_kernel<C, SE, LE, 64, TABLE, 4, R12><<<p.total_blocks, 256, 0, s>>>(p);
+    rc = launch_rb<C, SE, LE, TABLE, R12, 64>(p, cfg.rb, s);
   } else if (spb == 16) {
-    step_kernel<C, SE, LE, 16, TABLE, 4, R12><<<p.total_blocks, 64, 0, s>>>(p);
+    rc = launch_rb<C, SE, LE, TABLE, R12, 16>(p, cfg.rb, s);
   } else if (spb == 8) {
     step_kernel<C, SE, LE, 8, TABLE, 8, R12><<<p.total_blocks, 64, 0, s>>>(p);
   } else {
     return fail(OVL_EINVAL, "no step kernel for %d sites per workgroup", spb);
   }
+  if (rc) return rc;
   HIP_TRY(hipGetLastError());
   return OVL_OK;
 }
@@ -365,18 +417,18 @@ int launch_step_r(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab) {
 // two-row link reads where the problem's field allows them (single problem: its handle; a
 // table launch: every item's, recorded in p.r12 when the table was written)
 template <class C, class SE, class LE, bool TABLE>
-int launch_step(StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
+int launch_step(StepArgs<TABLE> &p, const LaunchCfg &cfg, hipStream_t s) {
   const bool r12 = TABLE ? p.r12 != 0 : p.item.r12 != 0;
-  return r12 ? launch_step_r<C, SE, LE, TABLE, true>(p, spb, s, slab)
-             : launch_step_r<C, SE, LE, TABLE, false>(p, spb, s, slab);
+  return r12 ? launch_step_r<C, SE, LE, TABLE, true>(p, cfg, s)
+             : launch_step_r<C, SE, LE, TABLE, false>(p, cfg, s);
 }
 
 template <bool TABLE>
-int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s, bool slab = false) {
+int dispatch_step(Prec prec, StepArgs<TABLE> &p, const LaunchCfg &cfg, hipStream_t s) {
   switch (prec) {
-    case P_F64: return launch_step<double, double2, double2, TABLE>(p, spb, s, slab);
-    case P_F32: return launch_step<float, float2, float2, TABLE>(p, spb, s, slab);
-    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, spb, s, slab);
+    case P_F64: return launch_step<double, double2, double2, TABLE>(p, cfg, s);
+    case P_F32: return launch_step<float, float2, float2, TABLE>(p, cfg, s);
+    case P_F32_BF16: return launch_step<float, float2, bf16c, TABLE>(p, cfg, s);
     default: return fail(OVL_EDTYPE, "bad precision");
   }
 }
@@ -385,7 +437,7 @@ int dispatch_step(Prec prec, StepArgs<TABLE> &p, int spb, hipStream_t s, bool sl
 int dispatch_cfg(Prec prec, StepArgs<false> &p, const LaunchCfg &cfg, hipStream_t s) {
   p.total_blocks = plan_items(&p.item, 1, cfg, site_bytes_of(prec));
   p.remap = cfg.remap;
-  return dispatch_step(prec, p, cfg.spb, s, cfg.tiles == 2);
+  return dispatch_step(prec, p, cfg, s);
 }
 int dispatch_single(Prec prec, StepArgs<false> &p, hipStream_t s) {
   const int64_t work = items_work(&p.item, 1);
@@ -465,19 +517,40 @@ int project(const float2 *phi, int n_ev, const float2 *psi, int psi_g5, int nrhs
   return OVL_OK;
 }
 
-// make sure d->w_dev holds w_i = sign(lambda_i) - p(lambda_i / lmax) for this polynomial
-int defl_weights(ovl_defl *d, const ovl_poly *p, hipStream_t s) {
+// Device weights w_i = sign(lambda_i) - p(lambda_i / lmax) (FP64, Sec. 2, eq. 3) of polynomial p
+// for basis d: the slot already holding them, else the least recently used slot, refilled on
+// stream s.  *w_out receives the device pointer, *absmax the largest |w_i|.
+int defl_weights(ovl_defl *d, const ovl_poly *p, hipStream_t s, const double **w_out,
+                 double *absmax) {
   std::lock_guard<std::mutex> lk(d->mu);
-  if (d->w_serial == p->serial) return OVL_OK;
-  for (int i = 0; i < d->n_ev; ++i) {
-    const double l = d->lambda[i];
-    const double sg = l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0);
-    d->w_host[i] = sg - cheb_eval(p->alpha, l / p->lmax);
+  int k = -1;
+  for (int i = 0; i < ovl_defl::kWSlots; ++i)
+    if (d->w_serial[i] == p->serial) k = i;
+  if (k < 0) {
+    k = 0;
+    for (int i = 1; i < ovl_defl::kWSlots; ++i)
+      if (d->w_stamp[i] < d->w_stamp[k]) k = i;
+    // the staging of slot k may still feed an upload that has not run yet
+    if (d->w_evt_live[k]) HIP_TRY(hipEventSynchronize(d->w_evt[k]));
+    double *wp = d->w_pin + (size_t)k * d->n_ev;
+    double m = 0.0;
+    for (int i = 0; i < d->n_ev; ++i) {
+      const double l = d->lambda[i];
+      const double sg = l > 0 ? 1.0 : (l < 0 ? -1.0 : 0.0);
+      wp[i] = sg - cheb_eval(p->alpha, l / p->lmax);
+      m = std::max(m, std::fabs(wp[i]));
+    }
+    d->w_serial[k] = 0;
+    HIP_TRY(hipMemcpyAsync(d->w_dev + (size_t)k * d->n_ev, wp, sizeof(double) * d->n_ev,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(d->w_evt[k], s));
+    d->w_evt_live[k] = true;
+    d->w_serial[k] = p->serial;
+    d->w_absmax[k] = m;
   }
-  HIP_TRY(hipMemcpyAsync(d->w_dev, d->w_host.data(), sizeof(double) * d->n_ev,
-                         hipMemcpyHostToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));  // w_host may be rewritten by the next polynomial
-  d->w_serial = p->serial;
+  d->w_stamp[k] = ++d->w_clock;
+  *w_out = d->w_dev + (size_t)k * d->n_ev;
+  *absmax = d->w_absmax[k];
   return OVL_OK;
 }
 
@@ -507,11 +580,11 @@ struct GraphKey {
   uint64_t g_serial, p_serial;
   const void *in;
   void *out;
-  int nrhs, prec, src_g5, spb, tiles, remap;
+  int nrhs, prec, src_g5, spb, tiles, remap, rb;
   bool operator==(const GraphKey &o) const {
     return device == o.device && g_serial == o.g_serial && p_serial == o.p_serial && in == o.in &&
            out == o.out && nrhs == o.nrhs && prec == o.prec && src_g5 == o.src_g5 &&
-           spb == o.spb && tiles == o.tiles && remap == o.remap;
+           spb == o.spb && tiles == o.tiles && remap == o.remap && rb == o.rb;
   }
 };
 struct GraphEntry {
@@ -577,20 +650,35 @@ hipStream_t capture_stream(int device) {
 // b_k = alpha_k src + 2 X b_{k+1} - b_{k+2}, k = N-1 .. 1 (b_N = alpha_N src and b_{N+1} = 0
 // are folded into the first two steps), result = alpha_0 src + X b_1 - b_2.  b_k lives in
 // `out` for even k and in one scratch vector for odd k; every step updates b_{k+2} in place.
+// Work space of one evaluation: the caller's fixed buffer (fixed != nullptr: the entry point that
+// allocates nothing; sizes above fixed_cap are rejected) or a stream-ordered allocation.
+struct SignSpace {
+  void *fixed = nullptr;
+  size_t fixed_cap = 0;
+};
+
+// The launch configuration of an evaluation of these problems: the tuned one for the same
+// problem set (ovl_autotune), else the default rules, fitted to what the vectors allow.
 template <bool TABLE>
-int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, double mu, int src_g5,
-                  int spin_dt, Prec prec, hipStream_t s) {
-  const int N = (int)p->alpha.size() - 1;
+LaunchCfg sign_cfg(const SignJob *jobs, int nj, Prec prec) {
   int64_t work = 0;
   for (int j = 0; j < nj; ++j) work += (int64_t)jobs[j].g->g.V * jobs[j].nrhs;
   bool pairs = prec != P_F64;
   for (int j = 0; j < nj; ++j)
     pairs = pairs && jobs[j].g->g.L[0] % 2 == 0 && aligned16(jobs[j].in) && aligned16(jobs[j].out) &&
             (!jobs[j].d || aligned16(jobs[j].d->phi_store));
-  LaunchCfg cfg = fit_cfg(
-      TABLE ? default_cfg(work, prec) : lookup_cfg(jobs[0].g->g, prec, jobs[0].nrhs, work), pairs);
-  cfg = TABLE ? (cfg.tiles == 2 ? fit_cfg(default_cfg(work, prec), pairs) : cfg)
-              : fit_slab(cfg, jobs[0].g->g, prec, work, pairs);
+  StepItem key_items[kMaxBatch];
+  for (int j = 0; j < nj; ++j) fill_item(key_items[j], jobs[j].g, jobs[j].nrhs);
+  LaunchCfg cfg = fit_cfg(lookup_cfg((int)prec, key_items, nj, work), pairs);
+  if (TABLE) return cfg.tiles == 2 ? fit_cfg(default_cfg(work, prec), pairs) : cfg;
+  return fit_slab(cfg, jobs[0].g->g, prec, work, pairs);
+}
+
+template <bool TABLE>
+int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, double mu, int src_g5,
+                  int spin_dt, Prec prec, hipStream_t s, const SignSpace &space = SignSpace()) {
+  const int N = (int)p->alpha.size() - 1;
+  const LaunchCfg cfg = sign_cfg<TABLE>(jobs, nj, prec);
   const int spb = cfg.spb;
   const bool slab = cfg.tiles == 2;
   // scratch: [item table] then per job [vector][norm partials][projection partials][c]
@@ -609,21 +697,30 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     off[j][3] = total;
     total += up(sizeof(double2) * (size_t)nrhs * n_ev);
   }
+  if (space.fixed && total > space.fixed_cap)
+    return fail(OVL_EINVAL, "the evaluation needs %zu bytes of work space, above the %zu-byte "
+                "fixed buffer", total, space.fixed_cap);
+  const double *wdev[kMaxBatch] = {};
+  double wmax[kMaxBatch] = {};
   for (int j = 0; j < nj; ++j)
     if (jobs[j].d) {
-      int rc = defl_weights(jobs[j].d, p, s);
+      int rc = defl_weights(jobs[j].d, p, s, &wdev[j], &wmax[j]);
       if (rc) return rc;
     }
   Scratch sc;
-  int rc = scratch_alloc(sc, total, s);
-  if (rc) return rc;
-  char *base = (char *)sc.p;
-  // step graph for a small single problem (the graph lock is held until its launch is enqueued)
+  int rc = OVL_OK;
+  if (!space.fixed) {
+    rc = scratch_alloc(sc, total, s);
+    if (rc) return rc;
+  }
+  char *base = space.fixed ? (char *)space.fixed : (char *)sc.p;
+  // step graph for a small single problem.  The graph lock is held until the final step, which
+  // reads the graph's work vector, is enqueued: an eviction by another thread frees that vector.
   std::unique_lock<std::mutex> glk(g_graph_mu, std::defer_lock);
   GraphEntry *ge = nullptr;
-  if (!TABLE && N >= 3 && spb < 64 && !slab && g_graphs.load() != 0) {
+  if (!TABLE && !space.fixed && N >= 3 && spb < 64 && !slab && g_graphs.load() != 0) {
     GraphKey key{jobs[0].g->device, jobs[0].g->serial, p->serial, jobs[0].in, jobs[0].out,
-                 jobs[0].nrhs, (int)prec, src_g5, cfg.spb, cfg.tiles, cfg.remap};
+                 jobs[0].nrhs, (int)prec, src_g5, cfg.spb, cfg.tiles, cfg.remap, cfg.rb};
     glk.lock();
     ge = graph_entry(key, (size_t)jobs[0].nrhs * 12 * jobs[0].g->g.V * elem_bytes(spin_dt));
     if (!ge) glk.unlock();
@@ -652,7 +749,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
       it.phi = J.d->phi_store;
       it.n_ev = J.d->n_ev;
       it.c = cvec;
-      it.wdefl = J.d->w_dev;
+      it.wdefl = wdev[j];
     }
   }
   StepArgs<TABLE> args;
@@ -678,7 +775,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   const double kdiag = 4.0 - p->m_W;
   // timing: one event pair around the plain steps k = N-1 .. 1 (consecutive launches)
   TimedRun run{nullptr, nullptr, N - 1};
-  if (g_timing.load() != 0 && N >= 2) {
+  if (g_timing.load() != 0 && N >= 2 && !space.fixed) {
     std::lock_guard<std::mutex> lk(g_timing_mu);
     run.e0 = pool_event();
     run.e1 = pool_event();
@@ -721,7 +818,7 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
     if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
       for (int k = N - 1; k >= 1 && rc == OVL_OK; --k) {
         set_step(k);
-        rc = dispatch_step(prec, args, spb, cs, slab);
+        rc = dispatch_step(prec, args, cfg, cs);
       }
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(cs, &graph);
@@ -740,11 +837,10 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   } else {
     for (int k = N - 1; k >= 1; --k) {
       set_step(k);
-      rc = dispatch_step(prec, args, spb, s, slab);
+      rc = dispatch_step(prec, args, cfg, s);
       if (rc) return rc;
     }
   }
-  if (glk.owns_lock()) glk.unlock();
   if (run.e0 && run.e1) {
     HIP_TRY(hipEventRecord(run.e1, s));
     std::lock_guard<std::mutex> lk(g_timing_mu);
@@ -752,16 +848,11 @@ int run_sign_jobs(const SignJob *jobs, int nj, const ovl_poly *p, int mode, doub
   }
   // final step: deflation correction, combine, norm partials
   set_step(0);
-  rc = dispatch_step(prec, args, spb, s, slab);
+  rc = dispatch_step(prec, args, cfg, s);
   if (rc) return rc;
   for (int j = 0; j < nj; ++j) {
     const SignJob &J = jobs[j];
-    double bound = p->bound;
-    if (J.d) {
-      double m = 0.0;
-      for (double w : J.d->w_host) m = std::max(m, std::fabs(w));
-      bound += m;
-    }
+    const double bound = p->bound + (J.d ? wmax[j] : 0.0);
     norm_check_kernel<<<J.nrhs, kBlock, 0, s>>>(
         items[j].norm_partial, item_blocks(J.g->g.V, spb), J.nrhs, bound * bound, J.g->flags,
         nullptr);
@@ -774,6 +865,108 @@ int run_sign(const ovl_gauge *g, const ovl_poly *p, ovl_defl *d, int mode, doubl
              void *out, const void *in, int nrhs, int spin_dt, Prec prec, hipStream_t s) {
   SignJob j{g, d, in, out, nrhs};
   return run_sign_jobs<false>(&j, 1, p, mode, mu, src_g5, spin_dt, prec, s);
+}
+
+// the problems of a batch: every item valid, one operator precision, no output overlapping any
+// input or another output (outputs are written while other items' inputs are still read)
+int check_batch(const ovl_batch_item *items, int n_items, int spin_dt, SignJob *jobs,
+                Prec &prec0) {
+  if (!items) return fail(OVL_EINVAL, "items is NULL");
+  if (n_items < 1 || n_items > kMaxBatch)
+    return fail(OVL_EINVAL, "n_items = %d out of range [1, %d]", n_items, kMaxBatch);
+  prec0 = P_BAD;
+  for (int i = 0; i < n_items; ++i) {
+    Prec prec;
+    const int rc = check_spinor_call(items[i].g, items[i].out, items[i].in, items[i].nrhs,
+                                     spin_dt, prec);
+    if (rc) return fail(rc, "item %d: %s", i, std::string(g_err).c_str());
+    if (i > 0 && prec != prec0)
+      return fail(OVL_EDTYPE, "item %d: link storage differs from item 0", i);
+    prec0 = prec;
+    jobs[i] = SignJob{items[i].g, nullptr, items[i].in, items[i].out, items[i].nrhs};
+  }
+  for (int i = 0; i < n_items; ++i)
+    for (int j = 0; j < n_items; ++j) {
+      const size_t bi = (size_t)items[i].nrhs * 12 * items[i].g->g.V * elem_bytes(spin_dt);
+      const size_t bj = (size_t)items[j].nrhs * 12 * items[j].g->g.V * elem_bytes(spin_dt);
+      const char *o = (const char *)items[i].out, *x = (const char *)items[j].in;
+      const char *oj = (const char *)items[j].out;
+      if (o < x + bj && x < o + bi)
+        return fail(OVL_EALIAS, "output of item %d overlaps the input of item %d", i, j);
+      if (i != j && o < oj + bj && oj < o + bi)
+        return fail(OVL_EALIAS, "outputs of items %d and %d overlap", i, j);
+    }
+  return OVL_OK;
+}
+
+// Tuning cache file: one entry per line,
+//   B <prec> <n_items> (<Lx> <Ly> <Lz> <Lt> <nrhs>) x n_items <spb> <order> <remap> <rb> <us>
+// or, for a single problem, the short form  <Lx> <Ly> <Lz> <Lt> <prec> <nrhs> <spb> <order>
+// <remap> <us>  (right-hand-side block 1).  Returns the entries read or a negative status.
+bool cfg_valid(const LaunchCfg &c) {
+  const bool ok_spb = c.tiles == 2 ? (c.spb == 64 || c.spb == 128 || c.spb == 192 || c.spb == 256)
+                                   : (c.spb == 8 || c.spb == 16 || c.spb == 64 || c.spb == 128);
+  return ok_spb && c.tiles >= 0 && c.tiles <= 2 && rb_ok(c);
+}
+int load_tune_cache(const char *path) {
+  FILE *f = std::fopen(path, "r");
+  if (!f) return fail(OVL_EINVAL, "cannot open tuning cache %s", path);
+  char line[4096];
+  int n = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    std::vector<double> v;
+    bool batch = false;
+    char *q = line;
+    while (*q == ' ' || *q == '\t') ++q;
+    if (*q == 'B') {
+      batch = true;
+      ++q;
+    }
+    char *end = nullptr;
+    for (;;) {
+      const double x = std::strtod(q, &end);
+      if (end == q) break;
+      v.push_back(x);
+      q = end;
+    }
+    TuneKey key;
+    LaunchCfg c;
+    if (batch) {
+      if (v.size() < 2) continue;
+      const int ni = (int)v[1];
+      if (ni < 1 || ni > kMaxBatch || (int)v.size() != 2 + 5 * ni + 5) continue;
+      key.prec = (int)v[0];
+      for (int i = 0; i < ni; ++i)
+        key.items.push_back({(int)v[2 + 5 * i], (int)v[3 + 5 * i], (int)v[4 + 5 * i],
+                             (int)v[5 + 5 * i], (int)v[6 + 5 * i]});
+      const int o = 2 + 5 * ni;
+      c = LaunchCfg{(int)v[o], (int)v[o + 1], v[o + 2] != 0 ? 1 : 0, (int)v[o + 3]};
+    } else {
+      if (v.size() != 10) continue;
+      key.prec = (int)v[4];
+      key.items.push_back({(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[5]});
+      c = LaunchCfg{(int)v[6], (int)v[7], v[8] != 0 ? 1 : 0, 1};
+    }
+    bool ok = key.prec >= 0 && key.prec <= 2 && cfg_valid(c);
+    for (const auto &it : key.items) ok = ok && it[4] >= 1;
+    if (!ok) continue;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = c;
+    ++n;
+  }
+  std::fclose(f);
+  return n;
+}
+// a cache named by a batch call is read once per process
+int load_tune_cache_once(const char *path) {
+  static std::mutex mu;
+  static std::vector<std::string> loaded;
+  std::lock_guard<std::mutex> lk(mu);
+  if (std::find(loaded.begin(), loaded.end(), path) != loaded.end()) return OVL_OK;
+  const int n = load_tune_cache(path);
+  if (n < 0) return n;
+  loaded.emplace_back(path);
+  return OVL_OK;
 }
 
 int check_poly(const ovl_poly *p) {
@@ -992,9 +1185,16 @@ int ovl_defl_create(ovl_defl **out, const int32_t dims[4], const void *phi_dev, 
   d->phi64 = nullptr;
   d->phi_store = nullptr;
   d->w_dev = nullptr;
+  d->w_pin = nullptr;
   d->lambda.assign(lambda, lambda + n_ev);
-  d->w_host.assign(n_ev, 0.0);
-  d->w_serial = 0;
+  d->w_clock = 0;
+  for (int k = 0; k < ovl_defl::kWSlots; ++k) {
+    d->w_evt[k] = nullptr;
+    d->w_evt_live[k] = false;
+    d->w_serial[k] = 0;
+    d->w_stamp[k] = 0;
+    d->w_absmax[k] = 0.0;
+  }
   const int V = geo.V;
   const int64_t nv = (int64_t)12 * V;  // complex entries per vector
   const int64_t n = nv * n_ev;
@@ -1002,11 +1202,18 @@ int ovl_defl_create(ovl_defl **out, const int32_t dims[4], const void *phi_dev, 
     if (d->phi_store && d->phi_store != d->phi64) (void)hipFree(d->phi_store);
     if (d->phi64) (void)hipFree(d->phi64);
     if (d->w_dev) (void)hipFree(d->w_dev);
+    if (d->w_pin) (void)hipHostFree(d->w_pin);
+    for (int k = 0; k < ovl_defl::kWSlots; ++k)
+      if (d->w_evt[k]) (void)hipEventDestroy(d->w_evt[k]);
     delete d;
     return code;
   };
+  const size_t wbytes = sizeof(double) * (size_t)n_ev * ovl_defl::kWSlots;
   hipError_t e = hipMalloc((void **)&d->phi64, n * sizeof(double2));
-  if (e == hipSuccess) e = hipMalloc((void **)&d->w_dev, sizeof(double) * n_ev);
+  if (e == hipSuccess) e = hipMalloc((void **)&d->w_dev, wbytes);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&d->w_pin, wbytes, hipHostMallocDefault);
+  for (int k = 0; k < ovl_defl::kWSlots && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&d->w_evt[k], hipEventDisableTiming);
   if (e != hipSuccess)
     return cleanup(fail(e == hipErrorOutOfMemory ? OVL_ENOMEM : OVL_EHIP, "defl alloc: %s",
                         hipGetErrorString(e)));
@@ -1077,6 +1284,8 @@ int ovl_defl_destroy(ovl_defl *d) {
   if (d->phi_store && d->phi_store != d->phi64) (void)hipFree(d->phi_store);
   (void)hipFree(d->phi64);
   (void)hipFree(d->w_dev);
+  (void)hipHostFree(d->w_pin);
+  for (int k = 0; k < ovl_defl::kWSlots; ++k) (void)hipEventDestroy(d->w_evt[k]);
   delete d;
   return OVL_OK;
 }
@@ -1340,38 +1549,16 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
 }
 
 int ovl_batch_sign_apply(const ovl_batch_item *items, int n_items, const ovl_poly *p,
-                         int spin_dt, void *stream) {
+                         int spin_dt, const char *tune_cache_path, void *stream) {
   g_err[0] = 0;
-  if (!items) return fail(OVL_EINVAL, "items is NULL");
-  if (n_items < 1 || n_items > kMaxBatch)
-    return fail(OVL_EINVAL, "n_items = %d out of range [1, %d]", n_items, kMaxBatch);
   int rc = check_poly(p);
   if (rc) return rc;
   SignJob jobs[kMaxBatch];
-  Prec prec0 = P_BAD;
-  for (int i = 0; i < n_items; ++i) {
-    Prec prec;
-    rc = check_spinor_call(items[i].g, items[i].out, items[i].in, items[i].nrhs, spin_dt, prec);
-    if (rc) return fail(rc, "item %d: %s", i, std::string(g_err).c_str());
-    if (i > 0 && prec != prec0)
-      return fail(OVL_EDTYPE, "item %d: link storage differs from item 0", i);
-    prec0 = prec;
-    jobs[i] = SignJob{items[i].g, nullptr, items[i].in, items[i].out, items[i].nrhs};
-  }
-  // outputs are written while other items' inputs are still read
-  for (int i = 0; i < n_items; ++i)
-    for (int j = 0; j < n_items; ++j) {
-      const size_t bi = (size_t)items[i].nrhs * 12 * items[i].g->g.V * elem_bytes(spin_dt);
-      const size_t bj = (size_t)items[j].nrhs * 12 * items[j].g->g.V * elem_bytes(spin_dt);
-      const char *o = (const char *)items[i].out, *x = (const char *)items[j].in;
-      const char *oj = (const char *)items[j].out;
-      if (o < x + bj && x < o + bi)
-        return fail(OVL_EALIAS, "output of item %d overlaps the input of item %d", i, j);
-      if (i != j && o < oj + bj && oj < o + bi)
-        return fail(OVL_EALIAS, "outputs of items %d and %d overlap", i, j);
-    }
-  return run_sign_jobs<true>(jobs, n_items, p, MODE_SIGN, 0.0, 0, spin_dt, prec0,
-                                  as_stream(stream));
+  Prec prec;
+  if ((rc = check_batch(items, n_items, spin_dt, jobs, prec))) return rc;
+  if (tune_cache_path && (rc = load_tune_cache_once(tune_cache_path))) return rc;
+  return run_sign_jobs<true>(jobs, n_items, p, MODE_SIGN, 0.0, 0, spin_dt, prec,
+                             as_stream(stream));
 }
 
 int ovl_defl_project(const ovl_defl *d, double *c_dev, const void *in, int nrhs, int spin_dt,
@@ -1403,23 +1590,24 @@ int ovl_defl_correct(const ovl_defl *d, void *inout, const double *c_dev, const 
   for (int i = 0; i < d->n_ev; ++i)
     if (!std::isfinite(w_host[i])) return fail(OVL_ENONFINITE, "w[%d] is not finite", i);
   hipStream_t s = as_stream(stream);
-  Scratch sc;
-  int rc = scratch_alloc(sc, sizeof(double) * d->n_ev, s);
-  if (rc) return rc;
-  HIP_TRY(hipMemcpyAsync(sc.p, w_host, sizeof(double) * d->n_ev, hipMemcpyHostToDevice, s));
   const int V = d->g.V;
   dim3 grid(grid_blocks(V), nrhs);
-  if (spin_dt == OVL_F64)
-    correct_kernel<double, double2><<<grid, kBlock, 0, s>>>((double2 *)inout, (const double2 *)d->phi_store,
-                                                           d->n_ev, (const double2 *)c_dev,
-                                                           (const double *)sc.p, 1.0, V);
-  else
-    correct_kernel<float, float2><<<grid, kBlock, 0, s>>>((float2 *)inout, (const float2 *)d->phi_store,
-                                                         d->n_ev, (const double2 *)c_dev,
-                                                         (const double *)sc.p, 1.0, V);
-  HIP_TRY(hipGetLastError());
-  // the staging copy must complete before the caller may reuse w_host
-  HIP_TRY(hipStreamSynchronize(s));
+  // the weights travel in the kernel arguments, kWChunk per launch: nothing is staged on the
+  // device and the call returns without waiting
+  for (int e0 = 0; e0 < d->n_ev; e0 += kWChunk) {
+    const int ne = std::min(kWChunk, d->n_ev - e0);
+    WChunk w;
+    for (int k = 0; k < kWChunk; ++k) w.v[k] = k < ne ? w_host[e0 + k] : 0.0;
+    if (spin_dt == OVL_F64)
+      correct_w_kernel<double, double2><<<grid, kBlock, 0, s>>>(
+          (double2 *)inout, (const double2 *)d->phi_store, e0, ne, d->n_ev,
+          (const double2 *)c_dev, w, V);
+    else
+      correct_w_kernel<float, float2><<<grid, kBlock, 0, s>>>(
+          (float2 *)inout, (const float2 *)d->phi_store, e0, ne, d->n_ev,
+          (const double2 *)c_dev, w, V);
+    HIP_TRY(hipGetLastError());
+  }
   return OVL_OK;
 }
 
@@ -1429,30 +1617,32 @@ int ovl_defl_correct(const ovl_defl *d, void *inout, const double *c_dev, const 
 // link derivatives
 namespace {
 
-// One launch accumulates len pairs (a_i, t_i) = (a0 + i * step, t0 + i * step) into G; the
-// first pair carries weight coef_first, the others coef_rest.
-// one VJP launch over up to two runs of pairs: len0 pairs from (a0, t0), then len - len0 from
-// (a1, t1), consecutive pairs step_bytes apart within a run
-int launch_vjp(Prec prec, const ovl_gauge *g, void *G, const void *a0, const void *a1, int a_g5,
-               const void *t0, const void *t1, size_t step_bytes, int len0, int len,
-               double coef_first, double coef_rest, int accumulate, hipStream_t s) {
+// One VJP launch over up to two runs of pairs: len0 pairs from (a0, t0), then len - len0 from
+// (a1, t1), consecutive pairs step_bytes apart within a run; the first pair carries weight
+// coef_first, the others coef_rest.  The sum starts from zero (in_mode 0), from the FP64 running
+// buffer G64 (1) or from G (2), and goes to G64 (out_mode 0) or to G (1).  For FP64 spinors G64
+// may be G itself.
+int launch_vjp(Prec prec, const ovl_gauge *g, void *G, double2 *G64, const void *a0,
+               const void *a1, int a_g5, const void *t0, const void *t1, size_t step_bytes,
+               int len0, int len, double coef_first, double coef_rest, int in_mode, int out_mode,
+               hipStream_t s) {
   if (len <= 0) return OVL_OK;
   const dim3 grid((unsigned)((g->g.V + 63) / 64));
   switch (prec) {
     case P_F64:
       link_vjp_kernel<double, double2, double2><<<grid, 256, 0, s>>>(
-          (double2 *)G, (const double2 *)a0, (const double2 *)a1,
+          (double2 *)G, G64, (const double2 *)a0, (const double2 *)a1,
           (int64_t)(step_bytes / sizeof(double2)), (const double2 *)t0, (const double2 *)t1,
           (int64_t)(step_bytes / sizeof(double2)), len0, len, coef_first, coef_rest, g->g, a_g5,
-          accumulate);
+          in_mode, out_mode);
       break;
     case P_F32:
     case P_F32_BF16:
       link_vjp_kernel<float, float2, float2><<<grid, 256, 0, s>>>(
-          (float2 *)G, (const float2 *)a0, (const float2 *)a1,
+          (float2 *)G, G64, (const float2 *)a0, (const float2 *)a1,
           (int64_t)(step_bytes / sizeof(float2)), (const float2 *)t0, (const float2 *)t1,
           (int64_t)(step_bytes / sizeof(float2)), len0, len, coef_first, coef_rest, g->g, a_g5,
-          accumulate);
+          in_mode, out_mode);
       break;
     default:
       return fail(OVL_EDTYPE, "bad precision");
@@ -1475,8 +1665,8 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G, const void *chi, const void
   if (rc) return rc;
   if (!psi) return fail(OVL_EINVAL, "psi is NULL");
   if (!fits_u32(36ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "G exceeds 4 GiB");
-  return launch_vjp(prec, g, G, chi, chi, 0, psi, psi, 0, 1, 1, 1.0, 1.0, accumulate,
-                    as_stream(stream));
+  return launch_vjp(prec, g, G, nullptr, chi, chi, 0, psi, psi, 0, 1, 1, 1.0, 1.0,
+                    accumulate ? 2 : 0, 1, as_stream(stream));
 }
 
 // dL = Re[<b_1, dX t_0> + 2 sum_{m=1}^{N-1} <b_{m+1}, dX t_m>] with b the Clenshaw vectors of chi
@@ -1492,7 +1682,8 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
   if (rc == OVL_EALIAS) return fail(OVL_EALIAS, "G overlaps psi");
   if (rc) return rc;
   if ((rc = check_poly(p))) return rc;
-  if (!fits_u32(36ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "G exceeds 4 GiB");
+  if (!fits_u32(36ull * g->g.V, OVL_F64))
+    return fail(OVL_EDIMS, "the FP64 sum of G over %d sites exceeds 4 GiB", g->g.V);
   if (ckpt_stride < 0) return fail(OVL_EINVAL, "ckpt_stride must be >= 0");
   const int N = (int)p->alpha.size() - 1;
   int S = ckpt_stride > 0 ? ckpt_stride : (int)std::ceil(std::sqrt((double)N));
@@ -1507,13 +1698,17 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
   hipStream_t s = as_stream(stream);
   const size_t vec = (size_t)12 * g->g.V * elem_bytes(spin_dt);
   const size_t vecp = (vec + 255) / 256 * 256;
-  // checkpoints, segment buffer of S vectors (+1 spare), ring of S + 2 Clenshaw vectors
+  // checkpoints, segment buffer of S vectors (+1 spare), ring of S + 2 Clenshaw vectors, and for
+  // FP32 spinors the FP64 running sum of G across the segments
   const int R = S + 2;
   const size_t nvec = (size_t)nslot + (S + 1) + R;
+  const bool f64 = prec == P_F64;
+  const size_t g64_bytes = (!f64 && nseg > 1) ? (size_t)36 * g->g.V * sizeof(double2) : 0;
   Scratch sc;
-  rc = scratch_alloc(sc, nvec * vecp, s);
+  rc = scratch_alloc(sc, nvec * vecp + g64_bytes, s);
   if (rc) return rc;
   char *base = (char *)sc.p;
+  double2 *G64 = f64 ? (double2 *)G : (g64_bytes ? (double2 *)(base + nvec * vecp) : nullptr);
   auto ck = [&](int m) -> void * { return base + (size_t)slot_of[m] * vecp; };
   auto seg = [&](int i) -> void * { return base + ((size_t)nslot + i) * vecp; };
   // b_k lives in ring slot k mod R: a segment touches b_{m0} .. b_{m1+2}, at most S + 2 vectors
@@ -1565,10 +1760,8 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
       tm = dst;
     }
   }
-  // backward sweep, segments from the top
-  HIP_TRY(hipMemsetAsync(G, 0, (size_t)36 * g->g.V * elem_bytes(spin_dt), s));
-  // b_{N+1} = 0 and b_N = alpha_N chi (a step whose stencil term has weight zero)
-  HIP_TRY(hipMemsetAsync(bv(N + 1), 0, vec, s));
+  // backward sweep, segments from the top.  b_{N+1} = 0 is never formed: the steps that would
+  // read it drop that term.  b_N = alpha_N chi (a step whose stencil term has weight zero).
   if ((rc = xstep(bv(N), chi, 0.0, chi, al[N], nullptr, 0.0))) return rc;
   for (int j = nseg - 1; j >= 0; --j) {
     const int m0 = j * S;
@@ -1581,15 +1774,19 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
     // b_m = alpha_m chi + 2 X b_{m+1} - b_{m+2} for m = m1 .. max(m0, 1); b_{m1+1} and b_{m1+2}
     // come from the segment above (or the start values)
     for (int m = m1; m >= std::max(m0, 1); --m)
-      if ((rc = xstep(bv(m), bv(m + 1), 2.0, chi, al[m], bv(m + 2), -1.0))) return rc;
+      if ((rc = xstep(bv(m), bv(m + 1), 2.0, chi, al[m], m + 2 <= N ? bv(m + 2) : nullptr, -1.0)))
+        return rc;
     // pairs (b_{m+1}, t_m), m = m0 .. m1, in one launch: the ring slots of b_{m0+1} .. b_{m1+1}
     // are consecutive up to one wrap (a segment holds at most S < R pairs), so they form at most
     // two runs; the t_m are consecutive in the segment buffer
     const int len = m1 - m0 + 1;
     const int len0 = std::min(len, R - (m0 + 1) % R);
+    // FP64 running sum: the top segment starts it, the last one (j = 0) writes G
     const double cf = (m0 == 0 ? 1.0 : 2.0) / p->lmax;
-    if ((rc = launch_vjp(prec, g, G, bv(m0 + 1), bv(m0 + 1 + len0), 1, seg(0), seg(len0), vecp,
-                         len0, len, cf, 2.0 / p->lmax, 1, s)))
+    const int in_mode = j == nseg - 1 ? 0 : 1;
+    const int out_mode = j == 0 ? 1 : 0;
+    if ((rc = launch_vjp(prec, g, G, G64, bv(m0 + 1), bv(m0 + 1 + len0), 1, seg(0), seg(len0),
+                         vecp, len0, len, cf, 2.0 / p->lmax, in_mode, out_mode, s)))
       return rc;
   }
   return OVL_OK;
@@ -1656,54 +1853,108 @@ int ovl_sign_residual(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
 }
 
 
-int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_path,
-                 double *best_us, void *stream) {
+// Times one plain Clenshaw step of the problem set (stencil input `in`, own-site reads of `in`
+// as source and recurrence vector, output `out`: the memory streams of an odd-k step) in every
+// candidate configuration and keeps the fastest for this problem set.
+int ovl_autotune(const ovl_batch_item *items, int n_items, const ovl_poly *p, int spin_dt,
+                 const char *cache_path, double *best_us, void *stream) {
   g_err[0] = 0;
-  if (!g) return fail(OVL_EINVAL, "gauge handle is NULL");
-  if (nrhs < 1 || nrhs > 65535) return fail(OVL_EINVAL, "nrhs = %d out of range", nrhs);
-  if (spin_dt != OVL_F64 && spin_dt != OVL_F32) return fail(OVL_EDTYPE, "spinor dtype %d", spin_dt);
-  const Prec prec = precision(spin_dt, g->store_dt);
-  if (prec == P_BAD) return fail(OVL_EDTYPE, "spinor dtype %d with link storage %d", spin_dt, g->store_dt);
-  if (!fits_u32(12ull * g->g.V, spin_dt)) return fail(OVL_EDIMS, "lattice too large");
-  hipStream_t s = as_stream(stream);
-  const size_t vec = (size_t)nrhs * 12 * g->g.V * elem_bytes(spin_dt);
-  const size_t vecp = (vec + 255) / 256 * 256;
-  Scratch sc;
-  int rc = scratch_alloc(sc, 2 * vecp, s);
+  SignJob jobs[kMaxBatch];
+  Prec prec;
+  int rc = check_batch(items, n_items, spin_dt, jobs, prec);
   if (rc) return rc;
-  HIP_TRY(hipMemsetAsync(sc.p, 0, 2 * vecp, s));
-  StepArgs<false> args = single_args(g, nrhs);
-  args.item.psi = sc.p;
-  args.item.buf[0] = (char *)sc.p + vecp;
-  args.y_g5 = 1;
-  args.kd = 2.5;
-  args.kh = -0.5;
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  LaunchCfg best{0, 0, 0};
-  float best_ms = 1e30f;
+  hipStream_t s = as_stream(stream);
+  const bool table = n_items > 1;
+  const double lmax = p ? p->lmax : 6.5, m_W = p ? p->m_W : 1.5;
+  StepItem its[kMaxBatch];
+  int maxr = 1;
+  int64_t work = 0;
+  for (int i = 0; i < n_items; ++i) {
+    fill_item(its[i], items[i].g, items[i].nrhs);
+    its[i].psi = items[i].in;
+    its[i].buf[0] = items[i].out;
+    its[i].buf[1] = const_cast<void *>(items[i].in);
+    maxr = std::max(maxr, items[i].nrhs);
+    work += (int64_t)items[i].g->g.V * items[i].nrhs;
+  }
+  Scratch sc;
+  if (table && (rc = scratch_alloc(sc, sizeof(StepItem) * n_items, s))) return rc;
+  StepArgs<false> a1;
+  StepArgs<true> at;
+  clear_args(a1);
+  clear_args(at);
+  for (StepArgs<false> *q : {&a1}) {
+    q->v_role = ROLE_PSI;
+    q->w_role = ROLE_B1;
+    q->out_role = ROLE_B0;
+    q->y_g5 = 1;
+    q->kd = 2.0 * (4.0 - m_W) / lmax;
+    q->kh = -1.0 / lmax;
+    q->a = 0.5;
+    q->t = -1.0;
+  }
+  at.v_role = a1.v_role;
+  at.w_role = a1.w_role;
+  at.out_role = a1.out_role;
+  at.y_g5 = 1;
+  at.kd = a1.kd;
+  at.kh = a1.kh;
+  at.a = a1.a;
+  at.t = a1.t;
+  at.n_items = n_items;
+  StepItem *table_dev = (StepItem *)sc.p;
+  at.table = table_dev;
+  at.r12 = 1;
+  for (int i = 0; i < n_items; ++i) at.r12 = at.r12 && its[i].r12;
   const int sb = site_bytes_of(prec);
-  const bool pairs = pairs_ok(prec, &args.item, 1);
+  const bool pairs = pairs_ok(prec, its, n_items);
   std::vector<LaunchCfg> cands;
   for (int spb : {128, 64, 16, 8})
     for (int tiles : {1, 0})
-      for (int remap : {1, 0}) {
-        if (spb == 128 && !pairs) continue;
-        if (tiles) {
-          int ty, tz;
-          step_tile(g->g, spb, sb, ty, tz);
-          if (ty == 0) continue;
+      for (int remap : {1, 0})
+        for (int rb : {1, 2, 4}) {
+          const LaunchCfg c{spb, tiles, remap, rb};
+          if (spb == 128 && !pairs) continue;
+          if (!rb_ok(c) || (rb > 1 && rb > maxr)) continue;
+          if (tiles) {
+            bool any = false;
+            for (int i = 0; i < n_items; ++i) {
+              int ty, tz;
+              step_tile(its[i].g, spb, sb, ty, tz);
+              any = any || ty > 0;
+            }
+            if (!any) continue;
+          }
+          cands.push_back(c);
         }
-        cands.push_back(LaunchCfg{spb, tiles, remap});
-      }
-  for (int spb : {64, 128, 192, 256})
-    if (slab_ok(g->g, spb, prec))
-      for (int remap : {1, 0}) cands.push_back(LaunchCfg{spb, 2, remap});
+  if (!table)
+    for (int spb : {64, 128, 192, 256})
+      if (slab_ok(its[0].g, spb, prec))
+        for (int remap : {1, 0}) cands.push_back(LaunchCfg{spb, 2, remap, 1});
+  auto launch = [&](const LaunchCfg &cfg) -> int {
+    if (!table) {
+      a1.item = its[0];
+      return dispatch_cfg(prec, a1, cfg, s);
+    }
+    return dispatch_step(prec, at, cfg, s);
+  };
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  LaunchCfg best{0, 0, 0, 1};
+  float best_ms = 1e30f;
   for (const LaunchCfg &cfg : cands) {
-    for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
+    if (table) {
+      at.total_blocks = plan_items(its, n_items, cfg, sb);
+      at.remap = cfg.remap;
+      for (int i = 0; i < n_items && rc == OVL_OK; ++i) {
+        write_item_kernel<<<1, 64, 0, s>>>(its[i], table_dev + i);
+        if (hipGetLastError() != hipSuccess) rc = fail(OVL_EHIP, "item table write");
+      }
+    }
+    for (int w = 0; w < 2 && rc == OVL_OK; ++w) rc = launch(cfg);
     if (rc == OVL_OK && hipEventRecord(e0, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
-    for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = dispatch_cfg(prec, args, cfg, s);
+    for (int w = 0; w < 10 && rc == OVL_OK; ++w) rc = launch(cfg);
     if (rc == OVL_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(OVL_EHIP, "event record");
     float ms = 0.f;
     if (rc == OVL_OK && (hipEventSynchronize(e1) != hipSuccess ||
@@ -1717,18 +1968,23 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc == OVL_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(OVL_EHIP, "synchronise");
   if (rc) return rc;
+  const TuneKey key = tune_key((int)prec, its, n_items);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{{g->g.L[0], g->g.L[1], g->g.L[2], g->g.L[3]}, (int)prec, nrhs}] = best;
+    g_tuned[key] = best;
   }
-  if (best_us) *best_us = 1e3 * best_ms / 10.0;
+  (void)work;
+  const double us = 1e3 * best_ms / 10.0;
+  if (best_us) *best_us = us;
   if (cache_path) {
     FILE *f = std::fopen(cache_path, "a");
     if (!f) return fail(OVL_EINVAL, "cannot open tuning cache %s", cache_path);
-    std::fprintf(f, "%d %d %d %d %d %d %d %d %d %.3f\n", g->g.L[0], g->g.L[1], g->g.L[2],
-                 g->g.L[3], (int)prec, nrhs, best.spb, best.tiles, best.remap,
-                 1e3 * best_ms / 10.0);
+    std::fprintf(f, "B %d %d", (int)prec, n_items);
+    for (const auto &it : key.items)
+      std::fprintf(f, " %d %d %d %d %d", it[0], it[1], it[2], it[3], it[4]);
+    std::fprintf(f, " %d %d %d %d %.3f\n", best.spb, best.tiles, best.remap, best.rb, us);
     std::fclose(f);
   }
   return OVL_OK;
@@ -1737,22 +1993,7 @@ int ovl_autotune(const ovl_gauge *g, int nrhs, int spin_dt, const char *cache_pa
 int ovl_autotune_load(const char *cache_path) {
   g_err[0] = 0;
   if (!cache_path) return fail(OVL_EINVAL, "NULL path");
-  FILE *f = std::fopen(cache_path, "r");
-  if (!f) return fail(OVL_EINVAL, "cannot open tuning cache %s", cache_path);
-  int L[4], prec, nrhs, spb, tiles, remap;
-  double us;
-  int n = 0;
-  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %lf", &L[0], &L[1], &L[2], &L[3], &prec,
-                     &nrhs, &spb, &tiles, &remap, &us) == 10) {
-    const bool ok_spb = tiles == 2 ? (spb == 64 || spb == 128 || spb == 192 || spb == 256)
-                                   : (spb == 8 || spb == 16 || spb == 64 || spb == 128);
-    if (!ok_spb || tiles < 0 || tiles > 2 || prec < 0 || prec > 2 || nrhs < 1) continue;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[TuneKey{{L[0], L[1], L[2], L[3]}, prec, nrhs}] = LaunchCfg{spb, tiles, remap != 0};
-    ++n;
-  }
-  std::fclose(f);
-  return n;
+  return load_tune_cache(cache_path);
 }
 
 int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3]) {
@@ -1766,6 +2007,23 @@ int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3])
   cfg_out[0] = c.spb;
   cfg_out[1] = c.tiles;
   cfg_out[2] = c.remap;
+  return OVL_OK;
+}
+
+int ovl_batch_launch_config(const ovl_batch_item *items, int n_items, int spin_dt,
+                            int cfg_out[4]) {
+  g_err[0] = 0;
+  if (!cfg_out) return fail(OVL_EINVAL, "NULL argument");
+  SignJob jobs[kMaxBatch];
+  Prec prec;
+  int rc = check_batch(items, n_items, spin_dt, jobs, prec);
+  if (rc) return rc;
+  const LaunchCfg c = n_items > 1 ? sign_cfg<true>(jobs, n_items, prec)
+                                  : sign_cfg<false>(jobs, n_items, prec);
+  cfg_out[0] = c.spb;
+  cfg_out[1] = c.tiles;
+  cfg_out[2] = c.remap;
+  cfg_out[3] = c.rb;
   return OVL_OK;
 }
 

@@ -112,7 +112,10 @@ def test_operator_validation_before_hip(lib):
     assert lib.ovl_wilson_link_vjp(None, dummy, dummy, dummy, 0, 0, None) == -1
     assert lib.ovl_overlap_solve(None, None, None, 0.1, dummy, dummy, None, None, 1e-10, 10, None,
                                  None, None) == -1
-    assert lib.ovl_batch_sign_apply(None, 0, None, 0, None) == -1
+    assert lib.ovl_batch_sign_apply(None, 0, None, 0, None, None) == -1
+    assert lib.ovl_autotune(None, 1, None, 0, None, None, None) == -1
+    cfg = (ctypes.c_int * 4)()
+    assert lib.ovl_batch_launch_config(None, 1, 0, cfg) == -1
     r = (ctypes.c_double * 1)()
     assert lib.ovl_sign_residual(None, None, None, dummy, 1, 0, r, None) == -1
     assert lib.ovl_sign_residual(None, None, None, dummy, 1, 0, None, None) == -1
@@ -142,8 +145,14 @@ def test_autotune_cache_file(lib, tmp_path):
     missing = str(tmp_path / "none.txt").encode()
     assert lib.ovl_autotune_load(missing) == -1
     f = tmp_path / "tune.txt"
-    f.write_text("16 16 16 32 1 1 64 1 1 17.5\n8 8 8 16 0 1 16 0 1 9.0\nbad line\n")
-    assert lib.ovl_autotune_load(str(f).encode()) == 2
+    f.write_text("16 16 16 32 1 1 64 1 1 17.5\n8 8 8 16 0 1 16 0 1 9.0\nbad line\n"
+                 # batch entries: two items; a right-hand-side block of 4 at 16 sites per
+                 # workgroup; rejected: a block with the two-sites-per-lane form, a bad item count
+                 "B 1 2 16 16 16 32 12 8 8 8 16 1 64 1 1 2 210.5\n"
+                 "B 0 1 8 8 8 16 4 16 0 1 4 12.0\n"
+                 "B 1 1 8 8 8 16 4 128 1 1 2 12.0\n"
+                 "B 1 3 8 8 8 16 4 64 1 1 1 12.0\n")
+    assert lib.ovl_autotune_load(str(f).encode()) == 4
 
 
 def test_two_row_reference_helper():

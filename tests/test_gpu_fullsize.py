@@ -92,4 +92,4 @@ def test_force_24x24x24x48(ovl):
     got = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64)))
     ref = oforce.sign_force(latgen.round_to_f32(u), latgen.round_to_f32(chi),
                             latgen.round_to_f32(psi), alpha, LMAX)
-    assert rel_err(got, ref) < 1e-5
+    assert rel_err(got, ref) < 1e-6

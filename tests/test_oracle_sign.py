@@ -88,13 +88,28 @@ def test_dense_polynomial(dense2):
     assert rel_err(ch.poly_apply(u, psi, alpha, LMAX).ravel(), expect) < 1e-13
 
 
-def test_chebyshev_vectors_bounded(dense2):
-    dims, u, lam, _ = dense2
+def test_chebyshev_vectors_spectral_closed_form(dense2):
+    """T_m(X) psi from the forward recurrence equals V cos(m arccos(Lambda/lmax)) V^+ psi, the
+    first-kind Chebyshev polynomial in its trigonometric closed form applied on the exact
+    eigenbasis (LAPACK); a dropped factor 2 or a shifted index fails from m = 2 on.  The norm
+    bound ||T_m(X) psi|| <= ||psi|| for lmax >= ||K|| follows and is checked too."""
+    dims, u, lam, vecs = dense2
     assert np.abs(lam).max() < LMAX
     psi = latgen.gaussian_spinor(dims, 53)
     nrm = np.linalg.norm(psi)
-    for t in ch.chebyshev_vectors(u, psi, 60, LMAX):
+    v = vecs.reshape(len(lam), -1).T
+    coef = v.conj().T @ psi.ravel()
+    theta = np.arccos(lam / LMAX)
+    ts = ch.chebyshev_vectors(u, psi, 60, LMAX)
+    assert len(ts) == 61
+    for m, t in enumerate(ts):
+        expect = v @ (np.cos(m * theta) * coef)
+        assert rel_err(t.ravel(), expect) < 1e-12, m
         assert np.linalg.norm(t) <= nrm * (1 + 1e-12)
+    # the weighted sum of the vectors is the polynomial
+    alpha = ch.coeffs_sign_interp(59, 0.06)
+    total = sum(a * t for a, t in zip(alpha, ts))
+    assert rel_err(total, ch.poly_apply(u, psi, alpha, LMAX)) < 1e-13
 
 
 def test_deflation_exact_on_span_and_square_bound(dense2):
