@@ -18,11 +18,17 @@ dL = Re sum_{x, mu} tr(G_mu(x)^+ dU_mu(x)).
   Re<tb_1, dX t_0>; dX = gamma5 dD_W / lmax, so every term is a D_W link VJP with a = gamma5 tb.
 * ``hmc_force(u, g)``: F_mu(x) = -TA(U_mu(x) G_mu(x)^+), TA the traceless anti-Hermitian part,
   which satisfies dL/d eps along U -> exp(eps Y) U = Re tr(F^+ Y) for Y in su(3).
+* ``sign_force_directional(u, chi, psi, alpha, lmax, y)``: the same derivative along one
+  direction, dL/d eps of L(U + eps Y) at eps = 0, by forward mode through the forward recurrence
+  (t'_0 = 0, t'_1 = X' psi, t'_{m+1} = 2 X t'_m + 2 X' t_m - t'_{m-1}, dL = Re<chi, sum_m alpha_m
+  t'_m>, with X' = gamma5 (-1/2 hopping with the links Y) / lmax).  It keeps four vectors, so it
+  runs on lattices where the reverse sweep's N stored vectors do not fit; Re tr(G^+ Y) summed
+  over the links equals it.
 """
 import numpy as np
 
 from .gamma import GAMMA
-from .wilson import shift_fwd, spin_mul, gamma5, kop, M_W
+from .wilson import shift_fwd, spin_mul, gamma5, hopping, kop, M_W
 
 
 def _outer_spin_summed(v, w):
@@ -75,3 +81,32 @@ def hmc_force(u, g):
     tr = np.einsum("miiTZYX->mTZYX", ah)
     ta = 0.5 * ah - (tr / 6.0)[:, None, None] * np.eye(3)[None, :, :, None, None, None, None]
     return -ta
+
+
+def sign_force_directional(u, chi, psi, alpha, lmax, y, m_w=M_W):
+    """d/d eps Re<chi, p(X[U + eps Y]) psi> at eps = 0 (forward mode through the recurrence)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    n = len(alpha) - 1
+
+    def xop(v):
+        return kop(u, v, m_w) / lmax
+
+    def dxop(v):
+        # D_W = 4 - 1/2 hopping(U) is real-linear in U (U and U^+ both enter), so its derivative
+        # along Y is -1/2 hopping(Y); the mass term does not depend on U
+        return gamma5(-0.5 * hopping(y, v)) / lmax
+
+    t_prev = psi.astype(np.complex128)
+    dt_prev = np.zeros_like(t_prev)
+    dsum = np.zeros_like(t_prev)
+    if n >= 1:
+        t_cur = xop(t_prev)
+        dt_cur = dxop(t_prev)
+        dsum = dsum + alpha[1] * dt_cur
+        for m in range(2, n + 1):
+            t_next = 2.0 * xop(t_cur) - t_prev
+            dt_next = 2.0 * xop(dt_cur) + 2.0 * dxop(t_cur) - dt_prev
+            dsum = dsum + alpha[m] * dt_next
+            t_prev, t_cur = t_cur, t_next
+            dt_prev, dt_cur = dt_cur, dt_next
+    return float(np.real(np.vdot(chi, dsum)))

@@ -126,3 +126,23 @@ def test_hmc_force_direction_derivative():
     fd = (_loss(moved(h_), chi, psi, alpha) - _loss(moved(-h_), chi, psi, alpha)) / (2 * h_)
     an = np.real(np.vdot(f, y))
     assert abs(fd - an) / abs(an) < 1e-7
+
+
+@pytest.mark.parametrize("deg", [1, 2, 9, 64])
+def test_directional_derivative_fd_and_reverse_mode(deg):
+    """The forward-mode directional derivative against central finite differences of the
+    polynomial (independent of any derivative code) and against the reverse sweep's G
+    contracted with the same direction, Re sum tr(G^+ Y)."""
+    dims = (2, 3, 2, 4)
+    u = latgen.smeared_field(dims, 111, steps=1)
+    chi = latgen.gaussian_spinor(dims, 112)
+    psi = latgen.gaussian_spinor(dims, 113)
+    alpha = ch.coeffs_sign_interp(max(deg, 1), 0.1) if deg > 2 else np.array([0.3, -0.7, 0.4][:deg + 1])
+    rng = np.random.Generator(np.random.PCG64(latgen.seed_for("direction", 3)))
+    y = rng.standard_normal(u.shape) + 1j * rng.standard_normal(u.shape)
+    dl = force.sign_force_directional(u, chi, psi, alpha, LMAX, y)
+    h = 1e-6
+    fd = (_loss(u + h * y, chi, psi, alpha) - _loss(u - h * y, chi, psi, alpha)) / (2 * h)
+    assert abs(dl - fd) < 1e-7 * max(1.0, abs(fd))
+    g = force.sign_force(u, chi, psi, alpha, LMAX)
+    assert abs(dl - np.real(np.vdot(g, y))) < 1e-12 * max(1.0, abs(dl))
