@@ -253,8 +253,9 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
  * right-hand sides per thread reusing one read of the thread's two links (spb 16 or 64, orders
  * 0 and 1).  Each candidate runs 2 untimed and 10 timed steps that read the items' inputs and
  * write their outputs (the outputs' contents are then undefined).  p (nullable) supplies lmax and
- * m_W for the step's coefficients.  The winner is appended to the text file cache_path when not
- * NULL (one line: B prec n_items, then Lx Ly Lz Lt nrhs per item, then spb order remap rb
+ * m_W for the step's coefficients.  The key includes whether every item's handle reads two-row
+ * links (ovl_gauge_reconstruct).  The winner is appended to the text file cache_path when not
+ * NULL (one line: B prec r12 n_items, then Lx Ly Lz Lt nrhs per item, then spb order remap rb
  * microseconds).  *best_us (nullable) receives the winner's time per step.  Synchronises the
  * stream.  Errors: as ovl_batch_sign_apply, ENOMEM, EHIP. */
 int ovl_autotune(const ovl_batch_item *items, int n_items, const ovl_poly *p, int spin_dt,
@@ -299,15 +300,26 @@ int ovl_status_flags(const ovl_gauge *g, uint32_t *flags, int clear);
  * Results are bitwise identical either way. */
 int ovl_graph_enable(int on);
 
-/* Kernel timing of the fused Chebyshev step: when enabled, every sign evaluation (sign, overlap,
+/* Kernel timing (measurement support).  When enabled, every sign evaluation (sign, overlap,
  * batched sign) records one HIP event on its stream before its first plain recurrence step and
- * one after its last (the steps k = N-1 .. 1 are consecutive launches of that kernel, so the
- * interval divided by N - 1 is the kernel's average duration back to back, inter-launch gaps
- * included).  ovl_timing_read returns the summed interval (ms) and the number of launches it
- * covers since the last read (synchronising the recorded events) and resets both.  Evaluations
- * of degree 1 record nothing. */
+ * one after its last (the steps k = N-1 .. 1 are consecutive launches of the fused Chebyshev
+ * step kernel, so the interval divided by N - 1 is the kernel's average duration back to back,
+ * inter-launch gaps included; evaluations of degree 1 record nothing), and every link-VJP launch
+ * of the force (ovl_sign_force, ovl_wilson_link_vjp) records one event pair around itself.
+ * ovl_timing_read(kind, ...) returns, for kind 0 (fused Chebyshev step) or 1 (link VJP), the
+ * summed intervals (ms) and the number of launches they cover since that kind was last read
+ * (synchronising the recorded events), and resets them.  Errors: EINVAL (NULL, bad kind). */
 int ovl_timing_enable(int on);
-int ovl_timing_read(double *total_ms, int64_t *launches);
+int ovl_timing_read(int kind, double *total_ms, int64_t *launches);
+
+/* Device-memory bandwidth ceilings (measurement support, not part of the method): one launch of
+ * a plain stream over `bytes` bytes of 16-byte elements, on `stream`.  kind 0: read src (bytes),
+ * write one 4-byte value per thread to dst (dst must hold 8 MiB); kind 1: copy src to dst
+ * (bytes each); kind 2: dst = x XOR y XOR z with x, y, z the three consecutive `bytes`-long
+ * arrays at src (3 * bytes read, bytes written).  Buffers: caller-owned device memory, 16-byte
+ * aligned, non-overlapping.  Errors: EINVAL (NULL, bytes not a positive multiple of 16,
+ * misaligned, bad kind), EHIP. */
+int ovl_stream_probe(int kind, void *dst, const void *src, int64_t bytes, void *stream);
 
 /* Library version string. */
 const char *ovl_version(void);

@@ -54,7 +54,8 @@ SIGNATURES = {
     "ovl_status_flags": (_i, [_vp, ctypes.POINTER(ctypes.c_uint32), _i]),
     "ovl_graph_enable": (_i, [_i]),
     "ovl_timing_enable": (_i, [_i]),
-    "ovl_timing_read": (_i, [_dp, ctypes.POINTER(ctypes.c_int64)]),
+    "ovl_timing_read": (_i, [_i, _dp, ctypes.POINTER(ctypes.c_int64)]),
+    "ovl_stream_probe": (_i, [_i, _vp, _vp, ctypes.c_int64, _vp]),
     "ovl_version": (ctypes.c_char_p, []),
 }
 

@@ -431,9 +431,19 @@ def timing_enable(on: bool = True):
     call("ovl_timing_enable", 1 if on else 0)
 
 
-def timing_read():
-    """(total milliseconds, launches) of the fused Chebyshev step kernel since the last read."""
+def timing_read(kind: int = 0):
+    """(total milliseconds, launches) since the last read of this kind: 0 = the fused Chebyshev
+    step kernel (runs of plain recurrence steps), 1 = link-VJP launches of the force."""
     ms = ctypes.c_double(0)
     n = ctypes.c_int64(0)
-    call("ovl_timing_read", ctypes.byref(ms), ctypes.byref(n))
+    call("ovl_timing_read", int(kind), ctypes.byref(ms), ctypes.byref(n))
     return ms.value, n.value
+
+
+STREAM_READ, STREAM_COPY, STREAM_3TO1 = 0, 1, 2
+
+
+def stream_probe(kind: int, dst, src, nbytes: int):
+    """One plain device-memory stream (bandwidth ceiling): read, copy or three-to-one, on the
+    current stream (see ovl_stream_probe)."""
+    call("ovl_stream_probe", int(kind), _ptr(dst), _ptr(src), int(nbytes), _stream())

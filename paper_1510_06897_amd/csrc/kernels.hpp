@@ -1223,4 +1223,58 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Bandwidth ceilings of the device memory: plain streams of 16-byte elements, each element touched
+// once, four loads in flight per thread (grid-stride).  Read: every element is loaded and folded
+// into a per-thread value (stored once per thread so the loads stay live).  Copy: dst = src.
+// Three-to-one: dst = x ^ y ^ z (three read streams, one write stream).
+__global__ void __launch_bounds__(256) stream_read_kernel(const uint4 *__restrict__ src, int64_t n,
+                                                          uint32_t *__restrict__ sink) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t acc = 0;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    acc ^= (a.x ^ a.y ^ a.z ^ a.w) ^ (b.x ^ b.y ^ b.z ^ b.w) ^ (c.x ^ c.y ^ c.z ^ c.w) ^
+           (d.x ^ d.y ^ d.z ^ d.w);
+  }
+  for (; i < n; i += stride) {
+    const uint4 a = src[i];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(256) stream_copy_kernel(const uint4 *__restrict__ src, int64_t n,
+                                                          uint4 *__restrict__ dst) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(256) stream_3to1_kernel(const uint4 *__restrict__ src, int64_t n,
+                                                          uint4 *__restrict__ dst) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint4 *x = src, *y = src + n, *z = src + 2 * n;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + stride < n; i += 2 * stride) {
+    const uint4 a0 = x[i], b0 = y[i], c0 = z[i];
+    const uint4 a1 = x[i + stride], b1 = y[i + stride], c1 = z[i + stride];
+    dst[i] = make_uint4(a0.x ^ b0.x ^ c0.x, a0.y ^ b0.y ^ c0.y, a0.z ^ b0.z ^ c0.z, a0.w ^ b0.w ^ c0.w);
+    dst[i + stride] = make_uint4(a1.x ^ b1.x ^ c1.x, a1.y ^ b1.y ^ c1.y, a1.z ^ b1.z ^ c1.z,
+                                 a1.w ^ b1.w ^ c1.w);
+  }
+  for (; i < n; i += stride) {
+    const uint4 a = x[i], b = y[i], c = z[i];
+    dst[i] = make_uint4(a.x ^ b.x ^ c.x, a.y ^ b.y ^ c.y, a.z ^ b.z ^ c.z, a.w ^ b.w ^ c.w);
+  }
+}
+
 }  // namespace ovl

@@ -89,9 +89,12 @@ int scratch_alloc(Scratch &sc, size_t bytes, hipStream_t s) {
 
 // kernel timing of the fused Chebyshev step (see ovl_timing_enable): one event pair brackets the
 // n consecutive plain step launches of one sign evaluation
+// kinds of timed launch runs (ovl_timing_read)
+enum : int { TK_STEP = 0, TK_VJP = 1, TK_COUNT = 2 };
 struct TimedRun {
   hipEvent_t e0, e1;
   int n;
+  int kind = TK_STEP;
 };
 std::atomic<int> g_timing{0};
 std::mutex g_timing_mu;
@@ -188,6 +191,9 @@ Prec precision(int spin_dt, int store_dt) {
 // Elements between consecutive link components inside a 64-site block (see link_lane).
 constexpr int kLinkBlock = 64;
 
+// workgroups of the stream probes: 32 per compute unit of a 256-CU device, grid-stride
+constexpr unsigned kStreamBlocks = 256 * 32;
+
 // every array a kernel addresses through one buffer resource must span < 4 GiB
 bool fits_u32(uint64_t n_elems, int dt) { return n_elems * (uint64_t)elem_bytes(dt) < (1ull << 32); }
 
@@ -251,9 +257,10 @@ struct LaunchCfg {
 };
 struct TuneKey {
   int prec;
+  int r12;                                // two-row link reads (every item's field allows them)
   std::vector<std::array<int, 5>> items;  // Lx Ly Lz Lt nrhs per item
   bool operator<(const TuneKey &o) const {
-    return prec < o.prec || (prec == o.prec && items < o.items);
+    return prec < o.prec || (prec == o.prec && (r12 < o.r12 || (r12 == o.r12 && items < o.items)));
   }
 };
 std::mutex g_tune_mu;
@@ -267,6 +274,8 @@ LaunchCfg default_cfg(int64_t work, int prec = P_F64) {
 TuneKey tune_key(int prec, const StepItem *items, int n) {
   TuneKey k;
   k.prec = prec;
+  k.r12 = 1;
+  for (int i = 0; i < n; ++i) k.r12 = k.r12 && items[i].r12 != 0;
   for (int i = 0; i < n; ++i)
     k.items.push_back({items[i].g.L[0], items[i].g.L[1], items[i].g.L[2], items[i].g.L[3],
                        items[i].nrhs});
@@ -279,11 +288,12 @@ LaunchCfg lookup_cfg(int prec, const StepItem *items, int n, int64_t work) {
   auto it = g_tuned.find(k);
   return it == g_tuned.end() ? default_cfg(work, prec) : it->second;
 }
-LaunchCfg lookup_cfg(const Geom &g, int prec, int nrhs, int64_t work) {
+LaunchCfg lookup_cfg(const Geom &g, int prec, int nrhs, int64_t work, int r12) {
   StepItem it;
   std::memset(&it, 0, sizeof(it));
   it.g = g;
   it.nrhs = nrhs;
+  it.r12 = r12;
   return lookup_cfg(prec, &it, 1, work);
 }
 
@@ -442,8 +452,9 @@ int dispatch_cfg(Prec prec, StepArgs<false> &p, const LaunchCfg &cfg, hipStream_
 int dispatch_single(Prec prec, StepArgs<false> &p, hipStream_t s) {
   const int64_t work = items_work(&p.item, 1);
   const bool pairs = pairs_ok(prec, &p.item, 1);
-  const LaunchCfg cfg = fit_slab(fit_cfg(lookup_cfg(p.item.g, prec, p.item.nrhs, work), pairs),
-                                 p.item.g, prec, work, pairs);
+  const LaunchCfg cfg = fit_slab(
+      fit_cfg(lookup_cfg(p.item.g, prec, p.item.nrhs, work, p.item.r12), pairs), p.item.g, prec,
+      work, pairs);
   return dispatch_cfg(prec, p, cfg, s);
 }
 
@@ -900,9 +911,10 @@ int check_batch(const ovl_batch_item *items, int n_items, int spin_dt, SignJob *
 }
 
 // Tuning cache file: one entry per line,
-//   B <prec> <n_items> (<Lx> <Ly> <Lz> <Lt> <nrhs>) x n_items <spb> <order> <remap> <rb> <us>
-// or, for a single problem, the short form  <Lx> <Ly> <Lz> <Lt> <prec> <nrhs> <spb> <order>
-// <remap> <us>  (right-hand-side block 1).  Returns the entries read or a negative status.
+//   B <prec> <r12> <n_items> (<Lx> <Ly> <Lz> <Lt> <nrhs>) x n_items <spb> <order> <remap> <rb> <us>
+// or, for a single problem with full link reads, the short form  <Lx> <Ly> <Lz> <Lt> <prec>
+// <nrhs> <spb> <order> <remap> <us>  (right-hand-side block 1).  Returns the entries read or a
+// negative status.
 bool cfg_valid(const LaunchCfg &c) {
   const bool ok_spb = c.tiles == 2 ? (c.spb == 64 || c.spb == 128 || c.spb == 192 || c.spb == 256)
                                    : (c.spb == 8 || c.spb == 16 || c.spb == 64 || c.spb == 128);
@@ -932,18 +944,20 @@ int load_tune_cache(const char *path) {
     TuneKey key;
     LaunchCfg c;
     if (batch) {
-      if (v.size() < 2) continue;
-      const int ni = (int)v[1];
-      if (ni < 1 || ni > kMaxBatch || (int)v.size() != 2 + 5 * ni + 5) continue;
+      if (v.size() < 3) continue;
+      const int ni = (int)v[2];
+      if (ni < 1 || ni > kMaxBatch || (int)v.size() != 3 + 5 * ni + 5) continue;
       key.prec = (int)v[0];
+      key.r12 = v[1] != 0 ? 1 : 0;
       for (int i = 0; i < ni; ++i)
-        key.items.push_back({(int)v[2 + 5 * i], (int)v[3 + 5 * i], (int)v[4 + 5 * i],
-                             (int)v[5 + 5 * i], (int)v[6 + 5 * i]});
-      const int o = 2 + 5 * ni;
+        key.items.push_back({(int)v[3 + 5 * i], (int)v[4 + 5 * i], (int)v[5 + 5 * i],
+                             (int)v[6 + 5 * i], (int)v[7 + 5 * i]});
+      const int o = 3 + 5 * ni;
       c = LaunchCfg{(int)v[o], (int)v[o + 1], v[o + 2] != 0 ? 1 : 0, (int)v[o + 3]};
     } else {
       if (v.size() != 10) continue;
       key.prec = (int)v[4];
+      key.r12 = 0;
       key.items.push_back({(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[5]});
       c = LaunchCfg{(int)v[6], (int)v[7], v[8] != 0 ? 1 : 0, 1};
     }
@@ -992,6 +1006,26 @@ extern "C" {
 const char *ovl_last_error(void) { return g_err; }
 
 const char *ovl_version(void) { return "ovl 0.1 (gfx950)"; }
+
+// plain device-memory streams of 16-byte elements (the bandwidth ceilings the kernels are
+// compared with); enqueued on the caller's stream
+int ovl_stream_probe(int kind, void *dst, const void *src, int64_t bytes, void *stream) {
+  g_err[0] = 0;
+  if (!dst || !src) return fail(OVL_EINVAL, "NULL argument");
+  if (bytes <= 0 || bytes % 16 != 0) return fail(OVL_EINVAL, "bytes must be a positive multiple of 16");
+  if (!aligned16(dst) || !aligned16(src)) return fail(OVL_EINVAL, "buffers must be 16-byte aligned");
+  const int64_t n = bytes / 16;
+  const unsigned blocks = kStreamBlocks;
+  hipStream_t s = as_stream(stream);
+  switch (kind) {
+    case 0: stream_read_kernel<<<blocks, 256, 0, s>>>((const uint4 *)src, n, (uint32_t *)dst); break;
+    case 1: stream_copy_kernel<<<blocks, 256, 0, s>>>((const uint4 *)src, n, (uint4 *)dst); break;
+    case 2: stream_3to1_kernel<<<blocks, 256, 0, s>>>((const uint4 *)src, n, (uint4 *)dst); break;
+    default: return fail(OVL_EINVAL, "stream kind %d", kind);
+  }
+  HIP_TRY(hipGetLastError());
+  return OVL_OK;
+}
 
 int ovl_gauge_create(ovl_gauge **out, const int32_t dims[4], const void *U_dev, int in_dt,
                      int store_dt, void *stream) {
@@ -1628,6 +1662,13 @@ int launch_vjp(Prec prec, const ovl_gauge *g, void *G, double2 *G64, const void 
                hipStream_t s) {
   if (len <= 0) return OVL_OK;
   const dim3 grid((unsigned)((g->g.V + 63) / 64));
+  TimedRun run{nullptr, nullptr, 1, TK_VJP};
+  if (g_timing.load() != 0) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    run.e0 = pool_event();
+    run.e1 = pool_event();
+  }
+  if (run.e0) HIP_TRY(hipEventRecord(run.e0, s));
   switch (prec) {
     case P_F64:
       link_vjp_kernel<double, double2, double2><<<grid, 256, 0, s>>>(
@@ -1648,6 +1689,11 @@ int launch_vjp(Prec prec, const ovl_gauge *g, void *G, double2 *G64, const void 
       return fail(OVL_EDTYPE, "bad precision");
   }
   HIP_TRY(hipGetLastError());
+  if (run.e0 && run.e1) {
+    HIP_TRY(hipEventRecord(run.e1, s));
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_events.push_back(run);
+  }
   return OVL_OK;
 }
 
@@ -1981,7 +2027,7 @@ int ovl_autotune(const ovl_batch_item *items, int n_items, const ovl_poly *p, in
   if (cache_path) {
     FILE *f = std::fopen(cache_path, "a");
     if (!f) return fail(OVL_EINVAL, "cannot open tuning cache %s", cache_path);
-    std::fprintf(f, "B %d %d", (int)prec, n_items);
+    std::fprintf(f, "B %d %d %d", (int)prec, key.r12, n_items);
     for (const auto &it : key.items)
       std::fprintf(f, " %d %d %d %d %d", it[0], it[1], it[2], it[3], it[4]);
     std::fprintf(f, " %d %d %d %d %.3f\n", best.spb, best.tiles, best.remap, best.rb, us);
@@ -2003,7 +2049,8 @@ int ovl_launch_config(const ovl_gauge *g, int nrhs, int spin_dt, int cfg_out[3])
   // vectors are taken as 16-byte aligned (torch allocations are)
   const int64_t work = (int64_t)g->g.V * nrhs;
   const bool pairs = prec != P_F64 && g->g.L[0] % 2 == 0;
-  const LaunchCfg c = fit_slab(fit_cfg(lookup_cfg(g->g, prec, nrhs, work), pairs), g->g, prec, work, pairs);
+  const LaunchCfg c = fit_slab(fit_cfg(lookup_cfg(g->g, prec, nrhs, work, g->r12), pairs), g->g,
+                               prec, work, pairs);
   cfg_out[0] = c.spb;
   cfg_out[1] = c.tiles;
   cfg_out[2] = c.remap;
@@ -2045,12 +2092,18 @@ int ovl_timing_enable(int on) {
   return OVL_OK;
 }
 
-int ovl_timing_read(double *total_ms, int64_t *launches) {
+int ovl_timing_read(int kind, double *total_ms, int64_t *launches) {
   if (!total_ms || !launches) return fail(OVL_EINVAL, "NULL argument");
+  if (kind < 0 || kind >= TK_COUNT) return fail(OVL_EINVAL, "timing kind %d", kind);
   std::lock_guard<std::mutex> lk(g_timing_mu);
   double tot = 0.0;
   int64_t n = 0;
+  std::vector<TimedRun> keep;
   for (auto &run : g_timing_events) {
+    if (run.kind != kind) {
+      keep.push_back(run);
+      continue;
+    }
     HIP_TRY(hipEventSynchronize(run.e1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, run.e0, run.e1));
@@ -2061,7 +2114,7 @@ int ovl_timing_read(double *total_ms, int64_t *launches) {
   }
   *launches = n;
   *total_ms = tot;
-  g_timing_events.clear();
+  g_timing_events.swap(keep);
   return OVL_OK;
 }
 

@@ -148,10 +148,10 @@ def test_autotune_cache_file(lib, tmp_path):
     f.write_text("16 16 16 32 1 1 64 1 1 17.5\n8 8 8 16 0 1 16 0 1 9.0\nbad line\n"
                  # batch entries: two items; a right-hand-side block of 4 at 16 sites per
                  # workgroup; rejected: a block with the two-sites-per-lane form, a bad item count
-                 "B 1 2 16 16 16 32 12 8 8 8 16 1 64 1 1 2 210.5\n"
-                 "B 0 1 8 8 8 16 4 16 0 1 4 12.0\n"
-                 "B 1 1 8 8 8 16 4 128 1 1 2 12.0\n"
-                 "B 1 3 8 8 8 16 4 64 1 1 1 12.0\n")
+                 "B 1 0 2 16 16 16 32 12 8 8 8 16 1 64 1 1 2 210.5\n"
+                 "B 0 1 1 8 8 8 16 4 16 0 1 4 12.0\n"
+                 "B 1 0 1 8 8 8 16 4 128 1 1 2 12.0\n"
+                 "B 1 0 3 8 8 8 16 4 64 1 1 1 12.0\n")
     assert lib.ovl_autotune_load(str(f).encode()) == 4
 
 

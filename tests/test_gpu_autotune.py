@@ -109,7 +109,7 @@ def test_batch_autotune_used_by_the_batch(ovl, tmp_path, store):
                      for g, x in probs)
     for rb, spb in ((4, 64), (2, 16)):
         forced = tmp_path / f"rb{rb}.txt"
-        forced.write_text(f"B {prec} {len(probs)} {items} {spb} 0 1 {rb} 0\n")
+        forced.write_text(f"B {prec} 0 {len(probs)} {items} {spb} 0 1 {rb} 0\n")
         ovl.batch_sign_apply(p, probs, tune_cache=str(forced))   # reads the file once
         assert ovl.batch_launch_config(probs) == (spb, 0, 1, rb)
         check()

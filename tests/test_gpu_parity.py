@@ -313,7 +313,7 @@ def test_sign_overlap_rhs_blocks(ovl, tmp_path, dims, spb, order, rb, store):
     prec = {"f64": 0, "f32": 1}[store]
     nrhs = 5
     cache = tmp_path / "rb.txt"
-    cache.write_text(f"B {prec} 1 {' '.join(map(str, dims))} {nrhs} {spb} {order} 1 {rb} 0\n")
+    cache.write_text(f"B {prec} 0 1 {' '.join(map(str, dims))} {nrhs} {spb} {order} 1 {rb} 0\n")
     assert ovl.autotune_load(str(cache)) == 1
     u = latgen.smeared_field(dims, 10183, steps=1)
     psi = latgen.gaussian_spinor(dims, 20183, nrhs=nrhs)
