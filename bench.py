@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the overlap-operator hot path on one MI355X.
 
-Workload (one "step"): D[mu] psi = 1/2 ((1 + mu) psi + (1 - mu) gamma5 sign(K) psi) on an 8^3x16
-lattice with 3-step stout-smeared (rho = 0.1) synthetic links, sign(K) = Chebyshev polynomial of
-degree 199 in X = K/lmax (199 fused stencil + Clenshaw kernels) plus the deflation of the 12 lowest
-|lambda| eigenpairs of K, mu alternating 0.01 / 0.05 (Cundy & Lee, Sec. 2, eqs. 1-3).  The
-headline form stores links and spinors in FP32 and accumulates in FP32 (FP64 deflation inner
-products and norm check); the plain FP64 form of the same work is timed beside it.
-
-Also measured: the fused D_W + gamma5 stencil (K) at 24^3x48 in FP64, FP32 and BF16-link storage
-(a working set larger than the 256 MB Infinity Cache), and the FP64 CPU oracle on a bounded sample
-of the same workload.
+Headline workload (one "step"): the Chebyshev sign function of Cundy & Lee, Sec. 2, eq. 3,
+sign(K) psi ~ sum_m alpha_m T_m(K/lmax) psi with K = gamma5 (D_W - m_W), m_W = 1.5, of degree 300
+(N = 299 fused stencil + Clenshaw kernels, eps = 0.05), applied to a batch of lattice problems in
+one kernel launch per K application: 12 spin-colour point sources on a 16^3x32 lattice plus
+4 x 8^3x16 and 2 x 12^3x24 lattices with one Gaussian source each, every lattice with its own
+synthetic near-unit SU(3) field smeared by 3 plain stout steps (rho = 0.1).  FP32 storage and
+arithmetic, two-row link reads (the third row of each SU(3) link completed in registers), the
+launch configuration chosen by the library's autotuner for this problem set.  `value` is
+right-hand-side sign(K) psi applications per second.  Beside it: the same batch with full link
+reads, in the default configuration, unbatched, and in plain FP64; the BF16-link 16^3x32 form with
+24 deflated modes; the FP32 force on 24^3x48 smeared links; the deflated overlap operator on
+8^3x16; K and sign(K) psi at 24^3x48; device-memory stream ceilings; the FP64 oracle's errors on
+every form and its time on the host cores.
 
 Prints ONE JSON line.  `python bench.py --gpus N --steps K --warmup W`.
 """
@@ -28,17 +31,27 @@ sys.path.insert(0, ROOT)
 METRIC = "sign(K)psi applies/s + D_W HBM GB/s, mixed/batched vs FP64 plain at stated rel err"
 HBM_PEAK_GBPS = 8000.0
 LMAX = 6.5
-DIMS_C2 = (8, 8, 8, 16)
-DEGREE_C2 = 200          # stated degree; the top odd index 199 is the number of K applications
-N_EV_C2 = 12
-MUS = (0.01, 0.05)
-DIMS_DW = (24, 24, 24, 48)
+LMAX_BF16 = LMAX * (1 + 2.0 ** -6)   # BF16 links are not unitary: margin on ||K||
+# batched workload (lattice, right-hand sides); item 0 carries the 12 point sources
+C4_SHAPES = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
+C4_DEGREE, C4_EPS = 300, 0.05
+C3_DIMS, C3_DEGREE, C3_NEV = (16, 16, 16, 32), 400, 24
+C5_DIMS, C5_DEGREE, C5_EPS, C5_STRIDE = (24, 24, 24, 48), 300, 0.05, 18
+C2_DIMS, C2_DEGREE, C2_NEV, MUS = (8, 8, 8, 16), 200, 12, (0.01, 0.05)
 # algorithmic bytes per site: each link, input and output read or written once
-BYTES_STEP = {"f64": 1248, "f32": 624, "bf16": 480}   # Clenshaw step: links + 3.5 spinor streams
-BYTES_DW = {"f64": 960, "f32": 480, "bf16": 336}       # D_W / K: links + in + out
-# with two-row link reads (third row completed as for SU(3)) the links cost 2/3 of their bytes
-BYTES_STEP_R12 = {"f64": 1056, "f32": 528, "bf16": 432}
-BYTES_DW_R12 = {"f64": 768, "f32": 384, "bf16": 288}
+BYTES_LINK = {"f64": 576, "f32": 288, "bf16": 144}          # 4 x 3 x 3 complex
+BYTES_LINK_R12 = {"f64": 384, "f32": 192, "bf16": 96}       # two rows read
+BYTES_SPIN = {"f64": 192, "f32": 96, "bf16": 96}            # 12 complex (BF16: FP32 spinors)
+STEP_STREAMS = 3.5   # Clenshaw step: b_{k+1}, b_{k+2}, b_k, and psi on odd k only
+GOLDEN_FORCE = os.path.join(ROOT, "tests", "golden", "force_directional_24x24x24x48.json")
+
+
+def step_bytes(store, r12=False):
+    return (BYTES_LINK_R12 if r12 else BYTES_LINK)[store] + STEP_STREAMS * BYTES_SPIN[store]
+
+
+def dw_bytes(store, r12=False):
+    return (BYTES_LINK_R12 if r12 else BYTES_LINK)[store] + 2 * BYTES_SPIN[store]
 
 
 def counter_traffic(tag):
@@ -72,17 +85,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--profile", nargs="?", const="c2", choices=["c2", "dw", "dw2", "proj", "force"],
-                    help="run one part only, for rocprofv3 runs: c2 = the timed FP32 overlap "
-                         "loop (default), dw = K at 24^3x48 in FP64/FP32/BF16 (dw2: with two-row "
-                         "link reads), proj = the FP32 "
-                         "matrix-core deflation projection at 16^3x32 with 24 vectors, force = "
-                         "the FP32 force at 24^3x48, degree 299")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the FP64 oracle leg (CPU baseline and errors vs the oracle)")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the batched, BF16/24-mode and force measurements")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only copy a 256 MiB device buffer twice (scale for the HBM byte counters)")
+                    help="headline only: skip the BF16/24-mode, force, overlap, 24^3x48 and "
+                         "stream measurements")
+    ap.add_argument("--profile", choices=["c4", "c3", "force", "c2", "dw", "dw2", "proj", "copy"],
+                    help="run one part only, for rocprofv3: c4 = the timed batched loop of the "
+                         "headline (--steps batches), c3 = the BF16 24-mode loop, force = the "
+                         "FP32 force at 24^3x48, c2 = the FP32 overlap loop, dw = K at 24^3x48 "
+                         "in FP64/FP32/BF16 (dw2: two-row link reads), proj = the FP32 "
+                         "matrix-core projection at 16^3x32 with 24 vectors, copy = two plain "
+                         "256 MiB device copies (scale of the byte counters)")
     return ap.parse_args()
 
 
@@ -101,247 +115,258 @@ def gpu_ms(torch, fn, reps, warmup=1):
     return e0.elapsed_time(e1) / reps
 
 
-def measure_extra(ovl, latgen, low_modes, torch, dev):
-    """Batched mixed-volume form, BF16 links with 24 deflated modes, and the force."""
-    out = {}
-    # (1) batched: 12 spin-colour point sources on 16^3x32 + 4 x 8^3x16 + 2 x 12^3x24, degree 299
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+# ------------------------------------------------------------------------------------------------
+# inputs (host, seeded)
+_FIELDS = {}
+
+
+def c4_inputs(latgen):
+    """[(dims, links, sources)] of the batched workload (cached)."""
+    if "c4" not in _FIELDS:
+        out = []
+        for i, (dims, nrhs) in enumerate(C4_SHAPES):
+            u = latgen.smeared_field(dims, latgen.seed_for("gauge", 4, i))
+            if nrhs == 12:
+                src = np.stack([latgen.point_source(dims, s, c) for s in range(4) for c in range(3)])
+            else:
+                src = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 4, i), nrhs=1)
+            out.append((dims, u, src))
+        _FIELDS["c4"] = out
+    return _FIELDS["c4"]
+
+
+def c5_inputs(latgen):
+    """Links, psi, chi of the force workload: the seeds of the stored oracle derivatives."""
+    if "c5" not in _FIELDS:
+        u = latgen.smeared_field(C5_DIMS, latgen.seed_for("gauge", 5))
+        psi = latgen.gaussian_spinor(C5_DIMS, latgen.seed_for("spinor", 5))
+        chi = latgen.gaussian_spinor(C5_DIMS, latgen.seed_for("spinor", 5, 1))
+        _FIELDS["c5"] = (u, psi, chi)
+    return _FIELDS["c5"]
+
+
+# ------------------------------------------------------------------------------------------------
+# headline: the batched sign function
+def c4_handles(ovl, torch, dev, latgen, store, two_row):
+    probs = []
+    cdt = torch.complex128 if store == "f64" else torch.complex64
+    for dims, u, src in c4_inputs(latgen):
+        g = ovl.GaugeField(torch.from_numpy(u).to(dev), store)
+        if two_row:
+            g.reconstruct()
+        probs.append((g, torch.from_numpy(src).to(dev).to(cdt)))
+    return probs
+
+
+def c4_bytes_per_step(store, two_row):
+    link = (BYTES_LINK_R12 if two_row else BYTES_LINK)[store]
+    total = 0.0
+    for dims, nrhs in C4_SHAPES:
+        v = int(np.prod(dims))
+        total += v * (link + nrhs * STEP_STREAMS * BYTES_SPIN[store])
+    return total
+
+
+def kernel_name(cfg, store, two_row, table=True):
+    spb, order, remap, rb = cfg
+    c, se, le = {"f64": ("double", "double2", "double2"), "f32": ("float", "float2", "float2"),
+                 "bf16": ("float", "float2", "bf16c")}[store]
+    if order == 2:
+        return f"step_slab_kernel<{c},{se},{le},NW={spb // 64},TABLE={int(table)},R12={int(two_row)}>"
+    if spb == 128:
+        return f"step2_kernel<{le},64,TABLE={int(table)},R12={int(two_row)}>"
+    nq = 8 if spb == 8 else 4
+    return (f"step_kernel<{c},{se},{le},SPB={spb},TABLE={int(table)},NQ={nq},"
+            f"R12={int(two_row)},RB={rb}>")
+
+
+def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
     t0 = time.time()
-    alpha = ovl.cheb_sign_coeffs(300, 0.05)
+    alpha = ovl.cheb_sign_coeffs(C4_DEGREE, C4_EPS)
     p32 = ovl.Polynomial(alpha, LMAX)
-    probs32, probs64 = [], []
-    shapes = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
-    n_rhs_total = 0
-    for i, (dims, nrhs) in enumerate(shapes):
-        u = torch.from_numpy(latgen.smeared_field(dims, latgen.seed_for("gauge", 4, i))).to(dev)
-        if nrhs == 12:
-            src = np.stack([latgen.point_source(dims, s, c) for s in range(4) for c in range(3)])
-        else:
-            src = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 4, i), nrhs=1)
-        s64 = torch.from_numpy(src).to(dev)
-        probs32.append((ovl.GaugeField(u, "f32"), s64.to(torch.complex64)))
-        probs64.append((ovl.GaugeField(u, "f64"), s64))
-        n_rhs_total += nrhs
-    log(f"batched inputs {time.time() - t0:.1f}s")
-    outs = [torch.empty_like(x) for _, x in probs32]
-    outs64 = [torch.empty_like(x) for _, x in probs64]
-    ms_b = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs32, outs), 5)
+    probs = c4_handles(ovl, torch, dev, latgen, "f32", two_row=True)
+    outs = [torch.empty_like(x) for _, x in probs]
+    n_rhs = sum(nrhs for _, nrhs in C4_SHAPES)
+    log(f"C4 inputs {time.time() - t0:.1f} s")
+    res = {}
+    if not profile:
+        cfg_default = ovl.batch_launch_config(probs)
+        ms_default = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs, outs), 3)
+        res["default_config"] = {"config": list(cfg_default), "ms_per_batch": round(ms_default, 3)}
+    us_tune = ovl.autotune(probs, p32, outs=outs)
+    cfg = ovl.batch_launch_config(probs)
+    log(f"C4 autotuned {cfg} ({us_tune:.1f} us per step in the tuner)")
+    # the timed loop: warm-up, then exactly `steps` batches, with the library's event pair around
+    # the consecutive plain steps of every evaluation (the dominant kernel's average duration)
+    for _ in range(warmup):
+        ovl.batch_sign_apply(p32, probs, outs)
+    torch.cuda.synchronize()
+    ovl.timing_read(0)
+    ovl.timing_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        ovl.batch_sign_apply(p32, probs, outs)
+    e1.record()
+    torch.cuda.synchronize()
+    ovl.timing_enable(False)
+    k_ms, k_n = ovl.timing_read(0)
+    ms = e0.elapsed_time(e1) / steps
+    log(f"C4 batched FP32 two-row: {ms:.3f} ms/batch, step kernel {1e3 * k_ms / k_n:.2f} us")
+    if profile:
+        return None
+    for g, _ in probs:
+        assert g.flags() == 0
+    res.update({"config": list(cfg), "ms_per_batch": ms, "kernel_ms": k_ms, "kernel_launches": k_n,
+                "tuner_us_per_step": round(us_tune, 2), "n_rhs": n_rhs})
+    res["speedup_tuned_vs_default"] = round(res["default_config"]["ms_per_batch"] / ms, 3)
+    del probs
+    # full link reads (tuned for that form), unbatched FP32 and plain FP64
+    probs_f = c4_handles(ovl, torch, dev, latgen, "f32", two_row=False)
+    ovl.autotune(probs_f, p32, outs=outs)
+    ms_full = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs_f, outs), 5)
+    res["full_link_reads"] = {"config": list(ovl.batch_launch_config(probs_f)),
+                              "ms_per_batch": round(ms_full, 3),
+                              "rhs_applies_per_s": round(n_rhs * 1e3 / ms_full, 2)}
     ms_u = gpu_ms(torch, lambda: [ovl.sign_apply(g, p32, x, out=o)
-                                  for (g, x), o in zip(probs32, outs)], 3)
+                                  for (g, x), o in zip(probs_f, outs)], 3)
+    del probs_f
+    probs64 = c4_handles(ovl, torch, dev, latgen, "f64", two_row=False)
+    outs64 = [torch.empty_like(x) for _, x in probs64]
     ms_64 = gpu_ms(torch, lambda: [ovl.sign_apply(g, p32, x, out=o)
                                    for (g, x), o in zip(probs64, outs64)], 2)
-    ovl.batch_sign_apply(p32, probs32, outs)
-    [ovl.sign_apply(g, p32, x, out=o) for (g, x), o in zip(probs64, outs64)]
-    torch.cuda.synchronize()
-    num = sum(float(torch.linalg.vector_norm(a.to(torch.complex128) - b) ** 2)
-              for a, b in zip(outs, outs64))
-    den = sum(float(torch.linalg.vector_norm(b) ** 2) for b in outs64)
-    # the same batch with two-row link reads (every field is SU(3))
-    for g, _ in probs32:
-        g.reconstruct()
-    ms_b2 = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs32, outs), 5)
-    ovl.batch_sign_apply(p32, probs32, outs)
-    torch.cuda.synchronize()
-    num2 = sum(float(torch.linalg.vector_norm(a.to(torch.complex128) - b) ** 2)
-               for a, b in zip(outs, outs64))
-    out["batched"] = {
-        "workload": "sign(K)psi, degree 299, eps 0.05, no deflation: 12 point sources on "
-                    "16^3x32 + 4 x 8^3x16 + 2 x 12^3x24 (own stout-smeared fields), FP32",
-        "rhs_applies_per_s": round(n_rhs_total * 1e3 / ms_b, 2),
-        "ms_per_batch": round(ms_b, 3),
-        "unbatched_f32_ms": round(ms_u, 3),
-        "plain_f64_ms": round(ms_64, 3),
-        "speedup_vs_unbatched_f32": round(ms_u / ms_b, 3),
-        "speedup_vs_plain_f64": round(ms_64 / ms_b, 3),
-        "rel_err_vs_f64_gpu": (num / den) ** 0.5,
-        "two_row_links": {"ms_per_batch": round(ms_b2, 3),
-                          "rhs_applies_per_s": round(n_rhs_total * 1e3 / ms_b2, 2),
-                          "speedup_vs_plain_f64": round(ms_64 / ms_b2, 3),
-                          "rel_err_vs_f64_gpu": (num2 / den) ** 0.5},
-    }
-    log(f"batched: {ms_b:.2f} ms/batch (two-row links {ms_b2:.2f}), unbatched {ms_u:.2f}, "
-        f"FP64 {ms_64:.2f}")
-    del probs32, probs64, outs, outs64
+    del probs64, outs64
+    res["unbatched_f32_ms"] = round(ms_u, 3)
+    res["plain_f64_ms"] = round(ms_64, 3)
+    res["speedup_vs_unbatched_f32"] = round(ms_u / ms, 3)
+    res["speedup_vs_plain_f64"] = round(ms_64 / ms, 3)
+    log(f"C4: full reads {ms_full:.2f} ms, unbatched {ms_u:.2f} ms, plain FP64 {ms_64:.2f} ms")
+    return res
 
-    # (2) BF16 links, FP32 spinors, 24 deflated modes (FP32 matrix-core projection), degree 399
+
+# ------------------------------------------------------------------------------------------------
+def measure_c3(ovl, torch, dev, latgen, low_modes, reps, profile=False):
+    """BF16 links, FP32 spinors/accumulation, FP64 reductions, degree 400 (N = 399), 24 deflated
+    modes found on the device, FP32 matrix-core projection."""
     t0 = time.time()
-    dims = (16, 16, 16, 32)
-    u = torch.from_numpy(latgen.smeared_field(dims, latgen.seed_for("gauge", 3))).to(dev)
-    psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 3))).to(dev)
-    g64 = ovl.GaugeField(u, "f64")
-    gbf = ovl.GaugeField(u, "bf16")
+    u = latgen.smeared_field(C3_DIMS, latgen.seed_for("gauge", 3))
+    psi = latgen.gaussian_spinor(C3_DIMS, latgen.seed_for("spinor", 3))
+    du = torch.from_numpy(u).to(dev)
+    g64 = ovl.GaugeField(du, "f64")
+    gbf = ovl.GaugeField(du, "bf16")
     # a 128-vector block holds the 48-mode doubler cluster around the 24th eigenvalue whole
-    lam, phi, res, eps = low_modes(g64, 24, LMAX, block=128, cut=1.0)
-    alpha = ovl.cheb_sign_coeffs(400, eps)
-    lmax_bf = LMAX * (1 + 2.0 ** -6)
-    pbf = ovl.Polynomial(alpha, lmax_bf)
-    p64 = ovl.Polynomial(alpha, lmax_bf)
+    t1 = time.time()
+    lam, phi, res_e, eps = low_modes(g64, C3_NEV, LMAX, block=128, cut=1.0)
+    t_eig = time.time() - t1
+    alpha = ovl.cheb_sign_coeffs(C3_DEGREE, eps)
+    pbf = ovl.Polynomial(alpha, LMAX_BF16)
     dbf = ovl.Deflation(phi, lam, "f32")
-    d64 = ovl.Deflation(phi, lam, "f64")
-    x32 = psi.to(torch.complex64)
+    x32 = torch.from_numpy(psi).to(dev).to(torch.complex64)
     y32 = torch.empty_like(x32)
-    y64 = torch.empty_like(psi)
-    log(f"BF16/24-mode set-up {time.time() - t0:.1f}s (eigen residual {res.max():.1e})")
-    ms_bf = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), 5)
-    ms_p64 = gpu_ms(torch, lambda: ovl.sign_apply(g64, p64, psi, defl=d64, out=y64), 3)
+    log(f"C3 set-up {time.time() - t0:.1f} s (eigen-solve {t_eig:.1f} s, residual {res_e.max():.1e})")
+    if profile:
+        for _ in range(reps):
+            ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
+        torch.cuda.synchronize()
+        return None
+    cfg = ovl.batch_launch_config((gbf, x32))
     ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
-    ovl.sign_apply(g64, p64, psi, defl=d64, out=y64)
     torch.cuda.synchronize()
-    err = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y64)
-                / torch.linalg.vector_norm(y64))
+    ovl.timing_read(0)
+    ovl.timing_enable(True)
+    ms_bf = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), reps, warmup=0)
+    ovl.timing_enable(False)
+    k_ms, k_n = ovl.timing_read(0)
+    d64 = ovl.Deflation(phi, lam, "f64")
+    p64 = ovl.Polynomial(alpha, LMAX_BF16)
+    x64 = torch.from_numpy(psi).to(dev)
+    y64 = torch.empty_like(x64)
+    ms_64 = gpu_ms(torch, lambda: ovl.sign_apply(g64, p64, x64, defl=d64, out=y64), 3)
     gbf.reconstruct()
-    ms_bf2 = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), 5)
-    ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
-    torch.cuda.synchronize()
-    err2 = float(torch.linalg.vector_norm(y32.to(torch.complex128) - y64)
-                 / torch.linalg.vector_norm(y64))
-    # the deflation projection alone (FP32 matrix cores), for its utilisation
+    ms_r12 = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), reps)
     ms_proj = gpu_ms(torch, lambda: ovl.defl_project(dbf, x32), 20)
-    proj_flops = 8.0 * 24 * 12 * int(np.prod(dims))    # complex MAC = 8 real flops
-    out["bf16_24modes"] = {
-        "workload": "sign(K)psi on 16^3x32 stout-smeared links stored in BF16, FP32 spinors and "
-                    "accumulation, degree 399, 24 deflated modes (FP32 matrix-core projection)",
-        "applies_per_s": round(1e3 / ms_bf, 2),
-        "plain_f64_applies_per_s": round(1e3 / ms_p64, 2),
-        "speedup_vs_plain_f64": round(ms_p64 / ms_bf, 3),
-        "rel_err_vs_f64_gpu_same_polynomial": err,
-        "lmax": lmax_bf, "eps": round(float(eps), 5), "eigen_residual_max": float(res.max()),
-        "projection_us": round(ms_proj * 1e3, 2),
-        "projection_mfma_TFLOPs": round(proj_flops / (ms_proj * 1e-3) / 1e12, 3),
-        "projection_mfma_frac_of_fp32_peak": round(proj_flops / (ms_proj * 1e-3) / 157.3e12, 5),
-        "projection_GBps": round(24 * 12 * int(np.prod(dims)) * 8 / (ms_proj * 1e-3) / 1e9, 1),
-        "two_row_links": {"applies_per_s": round(1e3 / ms_bf2, 2),
-                          "speedup_vs_plain_f64": round(ms_p64 / ms_bf2, 3),
-                          "rel_err_vs_f64_gpu_same_polynomial": err2},
-    }
-    log(f"BF16 24-mode: {ms_bf:.2f} ms/apply, FP64 {ms_p64:.2f} ms, err {err:.2e}")
-    del g64, gbf, dbf, d64, phi
-
-    # (3) force d Re<chi, p(X) psi>/dU at 24^3x48, degree 299, FP32, sqrt(N) checkpoints
-    t0 = time.time()
-    dims = (24, 24, 24, 48)
-    u = torch.from_numpy(latgen.random_su3_field(dims, latgen.seed_for("gauge", 5))).to(dev)
-    psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5))).to(dev)
-    chi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5, 1))).to(dev)
-    g32 = ovl.GaugeField(u, "f32")
-    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(300, 0.05), LMAX)
-    G = torch.empty((4, 3, 3) + tuple(psi.shape[-4:]), dtype=torch.complex64, device=dev)
-    x32, c32 = psi.to(torch.complex64), chi.to(torch.complex64)
-    log(f"force inputs {time.time() - t0:.1f}s")
-    ms_f = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, out=G), 2)
-    # one segment: every t_m is regenerated into HBM once (N vectors, 19 GB) instead of sqrt(N)
-    ms_all = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=299, out=G), 2)
-    g32.reconstruct()
-    ms_r12 = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, out=G), 2)
-    out["force"] = {
-        "workload": "d Re<chi, p(K/lmax) psi>/dU on 24^3x48 near-unit links, degree 299, FP32, "
-                    "checkpoint stride ceil(sqrt 299) = 18",
-        "ms_per_force": round(ms_f, 2),
-        "forces_per_s": round(1e3 / ms_f, 3),
-        "ms_per_force_stride_299": round(ms_all, 2),
-        "ms_per_force_two_row_links": round(ms_r12, 2),
-    }
-    log(f"force 24^3x48: {ms_f:.1f} ms (stride 299: {ms_all:.1f} ms)")
+    assert gbf.flags() == 0
+    vol = int(np.prod(C3_DIMS))
+    proj_flops = 8.0 * C3_NEV * 12 * vol    # complex multiply-add = 8 real flops
+    out = {"ms_per_apply": ms_bf, "kernel_ms": k_ms, "kernel_launches": k_n,
+           "config": list(cfg),
+           "plain_f64_ms_per_apply": round(ms_64, 3),
+           "speedup_vs_plain_f64": round(ms_64 / ms_bf, 3),
+           "two_row_links_ms_per_apply": round(ms_r12, 3),
+           "eps": round(float(eps), 5), "lmax": LMAX_BF16, "degree": len(alpha) - 1,
+           "eigen_solve_s": round(t_eig, 1), "eigen_residual_max": float(res_e.max()),
+           "projection_us": round(ms_proj * 1e3, 2),
+           "projection_mfma_TFLOPs": round(proj_flops / (ms_proj * 1e-3) / 1e12, 3),
+           "projection_frac_of_fp32_matrix_peak": round(proj_flops / (ms_proj * 1e-3) / 157.3e12, 5),
+           "projection_GBps": round(C3_NEV * 12 * vol * 8 / (ms_proj * 1e-3) / 1e9, 1)}
+    log(f"C3 BF16 24 modes: {ms_bf:.2f} ms/apply (two-row {ms_r12:.2f}), FP64 {ms_64:.2f} ms")
+    _FIELDS["c3"] = (u, psi, float(eps))
     return out
 
 
-def dw_inputs(latgen, torch, dev):
-    u = latgen.random_su3_field(DIMS_DW, latgen.seed_for("gauge", 5))
-    psi = latgen.gaussian_spinor(DIMS_DW, latgen.seed_for("spinor", 5))
-    return torch.from_numpy(u).to(dev), torch.from_numpy(psi).to(dev)
-
-
-def profile_dw(ovl, latgen, torch, dev, reps, two_row=False):
-    """K applications at 24^3x48 in the three storage precisions (the bench's D_W figures)."""
-    d_ub, d_pb = dw_inputs(latgen, torch, dev)
-    for store in ("f64", "f32", "bf16"):
-        gb = ovl.GaugeField(d_ub, store)
-        if two_row:
-            gb.reconstruct()
-        x = d_pb if store == "f64" else d_pb.to(torch.complex64)
-        y = torch.empty_like(x)
-        for _ in range(reps):
-            ovl.kernel_apply(gb, x, out=y)
-        torch.cuda.synchronize()
-        log(f"profile dw {store}: {reps} applies")
-        gb.close()
-
-
-def profile_proj(ovl, torch, dev, reps):
-    """FP32 matrix-core projection c = Phi^+ psi: 24 vectors of 16^3x32 (random basis)."""
-    dims = (16, 16, 16, 32)
-    gen = torch.Generator(device=dev).manual_seed(7)
-    shape = (24, 4, 3) + tuple(reversed(dims))
-    phi = torch.randn(shape, dtype=torch.complex128, device=dev, generator=gen)
-    psi = torch.randn(shape[1:], dtype=torch.complex64, device=dev, generator=gen)
-    d = ovl.Deflation(phi, np.linspace(-0.5, 0.5, 24), "f32")
-    for _ in range(reps):
-        ovl.defl_project(d, psi)
-    torch.cuda.synchronize()
-    log(f"profile proj: {reps} projections")
-
-
-def profile_force(ovl, latgen, torch, dev, reps):
-    """The FP32 force d Re<chi, p(X) psi>/dU at 24^3x48, degree 299 (the bench's force figure)."""
-    dims = (24, 24, 24, 48)
-    u = torch.from_numpy(latgen.random_su3_field(dims, latgen.seed_for("gauge", 5))).to(dev)
-    psi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5))).to(dev)
-    chi = torch.from_numpy(latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 5, 1))).to(dev)
-    g32 = ovl.GaugeField(u, "f32")
-    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(300, 0.05), LMAX)
-    G = torch.empty((4, 3, 3) + tuple(psi.shape[-4:]), dtype=torch.complex64, device=dev)
-    x32, c32 = psi.to(torch.complex64), chi.to(torch.complex64)
-    for _ in range(reps):
-        ovl.sign_force(g32, pf, c32, x32, out=G)
-    torch.cuda.synchronize()
-    log(f"profile force: {reps} forces")
-
-
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    import torch
-
-    if args.calibrate_copy:
-        # a plain device copy of known size: 256 MiB read + 256 MiB written per copy
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0").fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(2):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("copied 256 MiB twice")
-        return
-
-    import latgen
-    import paper_1510_06897_amd as ovl
-    from paper_1510_06897_amd.eigsolve import low_modes
-
-    ovl.load()
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.profile in ("dw", "dw2"):
-        profile_dw(ovl, latgen, torch, dev, args.steps, two_row=args.profile == "dw2")
-        return
-    if args.profile == "proj":
-        profile_proj(ovl, torch, dev, args.steps)
-        return
-    if args.profile == "force":
-        profile_force(ovl, latgen, torch, dev, args.steps)
-        return
-
-    # ---------------- inputs (untimed set-up) ----------------
+# ------------------------------------------------------------------------------------------------
+def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     t0 = time.time()
-    u = latgen.smeared_field(DIMS_C2, latgen.seed_for("gauge", 2))
-    psi = latgen.gaussian_spinor(DIMS_C2, latgen.seed_for("spinor", 2))
+    u, psi, chi = c5_inputs(latgen)
+    g32 = ovl.GaugeField(torch.from_numpy(u).to(dev), "f32")
+    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(C5_DEGREE, C5_EPS), LMAX)
+    G = torch.empty((4, 3, 3) + tuple(psi.shape[-4:]), dtype=torch.complex64, device=dev)
+    x32 = torch.from_numpy(psi).to(dev).to(torch.complex64)
+    c32 = torch.from_numpy(chi).to(dev).to(torch.complex64)
+    log(f"force inputs {time.time() - t0:.1f} s")
+    if profile:
+        for _ in range(reps):
+            ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G)
+        torch.cuda.synchronize()
+        return None
+    ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G)
+    torch.cuda.synchronize()
+    ovl.timing_read(1)
+    ovl.timing_enable(True)
+    ms_f = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G),
+                  reps, warmup=0)
+    ovl.timing_enable(False)
+    v_ms, v_n = ovl.timing_read(1)
+    # one segment: every t_m regenerated into HBM once (N vectors) instead of sqrt(N) checkpoints
+    ms_all = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_DEGREE,
+                                                  out=G), 1)
+    g32.reconstruct()
+    ms_r12 = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE,
+                                                  out=G), reps)
+    # bytes of the link-VJP launches: every pair reads a and t once (FP32 spinors), the FP64
+    # running sum of G is written by the first segment, read and written by the middle ones and
+    # read by the last, which writes G in FP32
+    vol = int(np.prod(C5_DIMS))
+    n = C5_DEGREE - 1
+    nseg = (n + C5_STRIDE - 1) // C5_STRIDE
+    vjp_bytes = vol * (n * 2 * BYTES_SPIN["f32"] + (nseg - 1) * 2 * 36 * 16 + 36 * 8)
+    out = {"ms_per_force": ms_f, "forces_per_s": round(1e3 / ms_f, 3),
+           "ms_per_force_stride_299": round(ms_all, 2),
+           "ms_per_force_two_row_links": round(ms_r12, 2),
+           "vjp_ms": v_ms, "vjp_launches": v_n, "vjp_launches_per_force": v_n // reps,
+           "vjp_bytes_per_force": vjp_bytes}
+    log(f"force 24^3x48: {ms_f:.1f} ms (link VJP {v_ms / reps:.1f} ms of it; "
+        f"two-row {ms_r12:.1f}, stride 299 {ms_all:.1f})")
+    return out
+
+
+# ------------------------------------------------------------------------------------------------
+def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
+    t0 = time.time()
+    u = latgen.smeared_field(C2_DIMS, latgen.seed_for("gauge", 2))
+    psi = latgen.gaussian_spinor(C2_DIMS, latgen.seed_for("spinor", 2))
     d_u = torch.from_numpy(u).to(dev)
     g64 = ovl.GaugeField(d_u, "f64")
     g32 = ovl.GaugeField(d_u, "f32")
     # the smooth synthetic fields keep K close to its free spectrum: 48 near-degenerate doubler
     # modes at |lambda| ~ 0.5, so the filtered block (64) must hold that whole cluster
-    lam, phi, res, eps = low_modes(g64, N_EV_C2, LMAX, block=64, cut=1.0)
-    alpha = ovl.cheb_sign_coeffs(DEGREE_C2, eps)
+    lam, phi, res_e, eps = low_modes(g64, C2_NEV, LMAX, block=64, cut=1.0)
+    alpha = ovl.cheb_sign_coeffs(C2_DEGREE, eps)
     poly = ovl.Polynomial(alpha, LMAX)
     defl64 = ovl.Deflation(phi, lam, "f64")
     defl32 = ovl.Deflation(phi, lam, "f32")
@@ -349,9 +374,7 @@ def main():
     psi32 = psi64.to(torch.complex64)
     out64 = torch.empty_like(psi64)
     out32 = torch.empty_like(psi32)
-    torch.cuda.synchronize()
-    log(f"set-up {time.time() - t0:.1f}s: eigen residual max {res.max():.1e}, "
-        f"|lambda| {abs(lam).min():.4f}..{abs(lam).max():.4f}, eps {eps:.4f}, N={len(alpha) - 1}")
+    log(f"C2 set-up {time.time() - t0:.1f} s (eps {eps:.4f})")
 
     def step(form, i):
         mu = MUS[i % 2]
@@ -360,268 +383,398 @@ def main():
         else:
             ovl.overlap_apply(g64, poly, psi64, mu, defl=defl64, out=out64)
 
-    def timed(form, steps, warmup, kernel_timing=False):
-        """ms per apply over `steps` applies; with kernel_timing also the step kernel's
-        (total ms, launches) from the library's event pairs recorded in the same loop"""
-        for i in range(warmup):
-            step(form, i)
+    for i in range(3):
+        step("f32", i)
+        step("f64", i)
+    torch.cuda.synchronize()
+    if profile:
+        for i in range(reps):
+            step("f32", i)
         torch.cuda.synchronize()
-        if kernel_timing:
-            ovl.timing_read()
-            ovl.timing_enable(True)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        w0 = time.perf_counter()
-        e0.record()
-        for i in range(steps):
-            step(form, i)
-        e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        kt = None
-        if kernel_timing:
-            ovl.timing_enable(False)
-            kt = ovl.timing_read()
-        return e0.elapsed_time(e1) / steps, wall, kt
-
-    if args.profile:
-        ms, _, _ = timed("f32", args.steps, args.warmup)
-        log(f"profile run: {ms:.3f} ms/step")
-        return
-
-    # dominant kernel: the fused stencil + Clenshaw step.  Inside the timed loop the library
-    # records one HIP event pair per apply on the apply's stream, around its run of plain
-    # recurrence steps (consecutive launches of that kernel)
-    ms32, wall32, (k_ms, k_n) = timed("f32", args.steps, max(2, args.warmup), kernel_timing=True)
-    k_avg_us = 1e3 * k_ms / k_n
-    log(f"FP32 overlap (C2): {ms32:.3f} ms/apply; step kernel {k_avg_us:.3f} us/launch")
-    # warm-up of at least two applies: the second one captures the step graph
-    ms64, _, _ = timed("f64", max(3, args.steps // 2), max(2, args.warmup))
-    log(f"FP64 overlap (C2): {ms64:.3f} ms/apply")
-
-    # the same operator on 12 sources in one call: one launch per step carries all of them
-    psi12 = torch.from_numpy(latgen.gaussian_spinor(DIMS_C2, latgen.seed_for("spinor", 2, 1),
+        return None
+    ms32 = gpu_ms(torch, lambda: [step("f32", i) for i in range(reps)], 1, warmup=0) / reps
+    ms64 = gpu_ms(torch, lambda: [step("f64", i) for i in range(reps)], 1, warmup=0) / reps
+    psi12 = torch.from_numpy(latgen.gaussian_spinor(C2_DIMS, latgen.seed_for("spinor", 2, 1),
                                                     nrhs=12)).to(dev).to(torch.complex64)
     out12 = torch.empty_like(psi12)
     ms12 = gpu_ms(torch, lambda: ovl.overlap_apply(g32, poly, psi12, MUS[0], defl=defl32,
-                                                   out=out12), max(3, args.steps // 4))
-    log(f"FP32 overlap (C2), 12 sources per call: {ms12:.3f} ms/call")
-
-    # D[mu] x = psi to 1e-10 on the same operator: FP64 CG, and FP32 CG inside FP64 correction
+                                                   out=out12), 5)
     solves = {}
-    if not args.no_extra:
-        for label, gi, di in (("f64", None, None), ("f32_inner", g32, defl32)):
-            for mu in (MUS[1],):
-                torch.cuda.synchronize()
-                t0s = time.perf_counter()
-                _, its, sres = ovl.overlap_solve(g64, poly, psi64, mu, defl=defl64, g_inner=gi,
-                                                 defl_inner=di, tol=1e-10)
-                torch.cuda.synchronize()
-                solves[f"{label}_mu{mu}"] = {"s": round(time.perf_counter() - t0s, 4),
-                                             "cg_iterations": its, "rel_residual": sres}
-        log(f"solves: {solves}")
-    vol = int(np.prod(DIMS_C2))
-    k_bytes = BYTES_STEP["f32"] * vol
-    k_gbps = k_bytes / (k_avg_us * 1e-6) / 1e9
-
-    # FP32 result against the FP32 GPU path and (below) the FP64 oracle
-    step("f64", 0)
-    step("f32", 0)
-    torch.cuda.synchronize()
-    err_32_vs_64 = float(torch.linalg.vector_norm(out32.to(torch.complex128) - out64)
-                         / torch.linalg.vector_norm(out64))
-
-    # ---------------- D_W (K) at 24^3x48 ----------------
-    t0 = time.time()
-    d_ub, d_pb = dw_inputs(latgen, torch, dev)
-    log(f"24^3x48 inputs {time.time() - t0:.1f}s")
-    vol_b = int(np.prod(DIMS_DW))
-    dw = {}
-    for store in ("f64", "f32", "bf16"):
-        gb = ovl.GaugeField(d_ub, store)
-        x = d_pb if store == "f64" else d_pb.to(torch.complex64)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            ovl.kernel_apply(gb, x, out=y)
+    for label, gi, di in (("f64", None, None), ("f32_inner", g32, defl32)):
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = 50
-        e0.record()
-        for _ in range(reps):
-            ovl.kernel_apply(gb, x, out=y)
-        e1.record()
+        t0s = time.perf_counter()
+        _, its, sres = ovl.overlap_solve(g64, poly, psi64, MUS[1], defl=defl64, g_inner=gi,
+                                         defl_inner=di, tol=1e-10)
         torch.cuda.synchronize()
-        us = 1e3 * e0.elapsed_time(e1) / reps
-        gbps = BYTES_DW[store] * vol_b / (us * 1e-6) / 1e9
-        dw[store] = {"us_per_apply": round(us, 2), "GBps": round(gbps, 1),
-                     "frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
-                     "bytes_per_site": BYTES_DW[store]}
-        log(f"K 24^3x48 {store}: {us:.1f} us, {gbps:.0f} GB/s")
-        # the same with two-row link reads (the field is SU(3); the check result is reported)
-        r12_dev = gb.reconstruct()
-        us2 = 1e3 * gpu_ms(torch, lambda: ovl.kernel_apply(gb, x, out=y), reps, warmup=3)
-        gbps2 = BYTES_DW_R12[store] * vol_b / (us2 * 1e-6) / 1e9
-        dw[store]["two_row_links"] = {"us_per_apply": round(us2, 2), "GBps": round(gbps2, 1),
-                                      "frac_of_8TBps": round(gbps2 / HBM_PEAK_GBPS, 4),
-                                      "bytes_per_site": BYTES_DW_R12[store],
-                                      "speedup": round(us / us2, 3),
-                                      "third_row_max_dev": r12_dev}
-        log(f"K 24^3x48 {store} two-row links: {us2:.1f} us")
-        gb.close()
+        solves[f"{label}_mu{MUS[1]}"] = {"s": round(time.perf_counter() - t0s, 4),
+                                         "cg_iterations": its, "rel_residual": sres}
+    assert g32.flags() == 0 and g64.flags() == 0
+    log(f"C2 overlap: FP32 {ms32:.3f} ms, FP64 {ms64:.3f} ms, 12 sources {ms12:.3f} ms")
+    _FIELDS["c2"] = (u, psi, float(eps))
+    return {"ms_per_apply_f32": round(ms32, 4), "ms_per_apply_f64": round(ms64, 4),
+            "applies_per_s_f32": round(1e3 / ms32, 1), "applies_per_s_f64": round(1e3 / ms64, 1),
+            "speedup_f32_over_f64": round(ms64 / ms32, 3),
+            "twelve_sources_ms_per_call": round(ms12, 4),
+            "twelve_sources_rhs_applies_per_s": round(12e3 / ms12, 1),
+            "eps": round(float(eps), 5), "degree": len(alpha) - 1,
+            "eigen_residual_max": float(res_e.max()), "solve_1e-10": solves}
 
-    # ---------------- sign(K) psi at 24^3x48: the recurrence in the HBM-bound regime ----------
-    sign_big = {}
-    p_big = ovl.Polynomial(ovl.cheb_sign_coeffs(DEGREE_C2, 0.05), LMAX * (1 + 2.0 ** -6))
+
+# ------------------------------------------------------------------------------------------------
+def measure_big(ovl, torch, dev, latgen, profile=None, reps=50):
+    """K and sign(K) psi at 24^3x48 (the force lattice; working set above the 256 MB Infinity
+    Cache) in FP64, FP32 and BF16-link storage, full and two-row link reads."""
+    u, psi, _ = c5_inputs(latgen)
+    d_u = torch.from_numpy(u).to(dev)
+    d_p = torch.from_numpy(psi).to(dev)
+    vol = int(np.prod(C5_DIMS))
+    dw, sign_big = {}, {}
+    p_big = ovl.Polynomial(ovl.cheb_sign_coeffs(C2_DEGREE, 0.05), LMAX_BF16)
     for store in ("f64", "f32", "bf16"):
-        gb = ovl.GaugeField(d_ub, store)
-        x = d_pb if store == "f64" else d_pb.to(torch.complex64)
+        gb = ovl.GaugeField(d_u, store)
+        x = d_p if store == "f64" else d_p.to(torch.complex64)
         y = torch.empty_like(x)
-        for _ in range(2):
+        if profile in ("dw", "dw2"):
+            if profile == "dw2":
+                gb.reconstruct()
+            for _ in range(reps):
+                ovl.kernel_apply(gb, x, out=y)
+            torch.cuda.synchronize()
+            gb.close()
+            continue
+        row = {}
+        for r12 in (False, True):
+            if r12:
+                gb.reconstruct()
+            us = 1e3 * gpu_ms(torch, lambda: ovl.kernel_apply(gb, x, out=y), reps, warmup=3)
+            gbps = dw_bytes(store, r12) * vol / (us * 1e-6) / 1e9
             ovl.sign_apply(gb, p_big, x, out=y)
-        torch.cuda.synchronize()
-        ovl.timing_read()
-        ovl.timing_enable(True)
-        ms = gpu_ms(torch, lambda: ovl.sign_apply(gb, p_big, x, out=y), 3, warmup=0)
-        ovl.timing_enable(False)
-        k_ms_b, k_n_b = ovl.timing_read()
-        us = 1e3 * k_ms_b / k_n_b
-        gbps = BYTES_STEP[store] * vol_b / (us * 1e-6) / 1e9
-        sign_big[store] = {"ms_per_apply": round(ms, 3), "step_kernel_us": round(us, 2),
-                           "step_GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
-                           "bytes_per_site": BYTES_STEP[store]}
-        log(f"sign 24^3x48 {store}: {ms:.2f} ms/apply, step kernel {us:.1f} us, {gbps:.0f} GB/s")
-        gb.reconstruct()
-        ovl.sign_apply(gb, p_big, x, out=y)
-        torch.cuda.synchronize()
-        ovl.timing_read()
-        ovl.timing_enable(True)
-        ms2 = gpu_ms(torch, lambda: ovl.sign_apply(gb, p_big, x, out=y), 3, warmup=0)
-        ovl.timing_enable(False)
-        k_ms_b, k_n_b = ovl.timing_read()
-        us2 = 1e3 * k_ms_b / k_n_b
-        gbps2 = BYTES_STEP_R12[store] * vol_b / (us2 * 1e-6) / 1e9
-        sign_big[store]["two_row_links"] = {
-            "ms_per_apply": round(ms2, 3), "step_kernel_us": round(us2, 2),
-            "step_GBps": round(gbps2, 1), "frac_of_8TBps": round(gbps2 / HBM_PEAK_GBPS, 4),
-            "bytes_per_site": BYTES_STEP_R12[store], "speedup": round(ms / ms2, 3)}
-        log(f"sign 24^3x48 {store} two-row links: {ms2:.2f} ms/apply")
+            torch.cuda.synchronize()
+            ovl.timing_read(0)
+            ovl.timing_enable(True)
+            ms = gpu_ms(torch, lambda: ovl.sign_apply(gb, p_big, x, out=y), 3, warmup=0)
+            ovl.timing_enable(False)
+            k_ms, k_n = ovl.timing_read(0)
+            kus = 1e3 * k_ms / k_n
+            sgbps = step_bytes(store, r12) * vol / (kus * 1e-6) / 1e9
+            key = "two_row_links" if r12 else "full_links"
+            row[key] = {"K_us_per_apply": round(us, 2), "K_GBps": round(gbps, 1),
+                        "K_frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
+                        "K_bytes_per_site": dw_bytes(store, r12),
+                        "sign_ms_per_apply": round(ms, 3), "step_kernel_us": round(kus, 2),
+                        "step_GBps": round(sgbps, 1),
+                        "step_frac_of_8TBps": round(sgbps / HBM_PEAK_GBPS, 4),
+                        "step_bytes_per_site": step_bytes(store, r12)}
+        dw[store] = row
+        log(f"24^3x48 {store}: K {row['full_links']['K_us_per_apply']} us "
+            f"(two-row {row['two_row_links']['K_us_per_apply']}), step "
+            f"{row['full_links']['step_kernel_us']} us")
         gb.close()
-    del d_ub, d_pb
+    return dw
 
-    # ---------------- measured HBM ceiling: a plain device copy of 4 GiB ----------------
-    # (read 4 GiB + write 4 GiB per copy); the stencil figures are also quoted against it
-    src_c = torch.empty(1 << 30, dtype=torch.float32, device=dev).fill_(1.0)
-    dst_c = torch.empty_like(src_c)
-    copy_ms = gpu_ms(torch, lambda: dst_c.copy_(src_c), 5)
-    copy_gbps = 2.0 * src_c.numel() * 4 / (copy_ms * 1e-3) / 1e9
-    del src_c, dst_c
-    log(f"device copy 4 GiB: {copy_ms:.2f} ms, {copy_gbps:.0f} GB/s")
-    for tbl in (dw, sign_big):
-        for v in tbl.values():
-            for w in (v, v["two_row_links"]):
-                key = "GBps" if "GBps" in w else "step_GBps"
-                w["frac_of_copy"] = round(w[key] / copy_gbps, 4)
 
-    extra = {} if args.no_extra else measure_extra(ovl, latgen, low_modes, torch, dev)
+def measure_streams(ovl, torch, dev):
+    """Plain device-memory streams of 4 GiB (read, copy, three-to-one) and torch's copy."""
+    nb = 4 << 30
+    src = torch.empty(3 * nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty(nb // 4, dtype=torch.float32, device=dev)
+    sink = torch.empty(8 << 20, dtype=torch.uint8, device=dev)
+    out = {}
+    for kind, name, moved in ((0, "read", 1), (1, "copy", 2), (2, "three_to_one", 4)):
+        d = sink if kind == 0 else dst
+        ms = gpu_ms(torch, lambda: ovl.stream_probe(kind, d, src, nb), 5, warmup=2)
+        out[name] = {"GBps": round(moved * nb / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8TBps": round(moved * nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    a = src[: nb // 4]
+    ms = gpu_ms(torch, lambda: dst.copy_(a), 5, warmup=2)
+    out["torch_copy"] = {"GBps": round(2 * nb / (ms * 1e-3) / 1e9, 1)}
+    log(f"streams 4 GiB: {out}")
+    return out
 
-    # ---------------- CPU oracle baseline (bounded sample) ----------------
-    cpu = None
-    err_vs_oracle = None
-    if not args.no_cpu:
-        from oracle import chebyshev as och
-        from oracle import deflation as odefl
-        from oracle import overlap as oov
-        # the oracle's inputs never come from the GPU: a Gaussian basis orthonormalised by the
-        # oracle stands in for the eigenvectors (same cost), with the GPU's eigenvalues replaced
-        # by a fixed synthetic set
-        phi_o = odefl.cgs2(latgen.gaussian_spinor(DIMS_C2, 777, nrhs=N_EV_C2))
-        lam_o = np.linspace(-0.52, 0.52, N_EV_C2) + 0.003
-        alpha_o = och.coeffs_sign_interp(DEGREE_C2, eps)
-        reps = 6   # about 10 s of single-core oracle work
-        from threadpoolctl import threadpool_limits
-        with threadpool_limits(limits=1):
-            c0 = time.perf_counter()
-            for i in range(reps):
-                ref = oov.overlap_apply(u, psi, MUS[i % 2], alpha_o, LMAX, phi_o, lam_o)
-            c_s = (time.perf_counter() - c0) / reps
-        cores = len(os.sched_getaffinity(0))
-        cpu = {"value": round(1.0 / c_s, 4), "unit": "sign(K)psi applies/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{reps} FP64 NumPy overlap applies (degree 199 + 12-vector deflation) on "
-                         f"the same 8^3x16 links and source, BLAS/OpenMP pools limited to 1 "
-                         f"thread ({cores} cores visible); {c_s:.2f} s/apply"}
-        log(f"oracle: {c_s:.2f} s/apply")
-        # the GPU on the oracle's inputs (last oracle apply used mu = MUS[1])
+
+# ------------------------------------------------------------------------------------------------
+# FP64 oracle leg: errors of every form against the oracle (on the exact FP64 inputs and on the
+# same rounded inputs) and the oracle's time on the host.  The oracle never receives anything the
+# GPU computed: its inputs come from latgen and its own coefficient rule and Gram-Schmidt.
+def _oracle_job(job):
+    """One oracle evaluation in a worker process (single-threaded NumPy)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import chebyshev as och
+    from oracle import overlap as oov
+    name, kind, args = job
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        if kind == "poly":
+            u, psi, alpha, lmax = args
+            y = och.poly_apply(u, psi, alpha, lmax)
+        elif kind == "sign":
+            u, psi, alpha, lmax, phi, lam = args
+            y = och.sign_apply(u, psi, alpha, lmax, phi, lam)
+        else:
+            u, psi, mu, alpha, lmax, phi, lam = args
+            y = oov.overlap_apply(u, psi, mu, alpha, lmax, phi, lam)
+    return name, y, time.perf_counter() - t0
+
+
+def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle import chebyshev as och
+    from oracle import deflation as odefl
+    r32, rbf = latgen.round_to_f32, latgen.round_to_bf16
+    jobs, gpu = [], {}
+    # C4: the headline form (FP32, two-row links, tuned batch launch) with the oracle's
+    # coefficients; sampled right-hand sides: point source 5 of the 16^3x32 lattice, the first
+    # 8^3x16 and the first 12^3x24 lattice
+    c4 = c4_inputs(latgen)
+    alpha4 = och.coeffs_sign_interp(C4_DEGREE, C4_EPS)
+    p4 = ovl.Polynomial(alpha4, LMAX)
+    probs = c4_handles(ovl, torch, dev, latgen, "f32", two_row=True)
+    outs = ovl.batch_sign_apply(p4, probs)
+    torch.cuda.synchronize()
+    for item, r in ((0, 5), (1, 0), (5, 0)):
+        dims, u, src = c4[item]
+        name = f"c4_{'x'.join(map(str, dims))}_rhs{r}"
+        gpu[name] = outs[item][r].cpu().to(torch.complex128).numpy()
+        jobs.append((name + "|exact", "poly", (u, src[r], alpha4, LMAX)))
+        jobs.append((name + "|same", "poly", (r32(u), r32(src[r]), alpha4, LMAX)))
+    del probs, outs
+    # C3: BF16 links; a Gaussian basis orthonormalised by the oracle stands in for the low modes
+    # (same cost), with fixed eigenvalues
+    if "c3" in _FIELDS:
+        u, psi, eps = _FIELDS["c3"]
+        phi_o = odefl.cgs2(latgen.gaussian_spinor(C3_DIMS, 30301, nrhs=C3_NEV))
+        lam_o = np.linspace(-0.5, 0.5, C3_NEV) + 0.004
+        alpha3 = och.coeffs_sign_interp(C3_DEGREE, eps)
+        gbf = ovl.GaugeField(torch.from_numpy(u).to(dev), "bf16")
+        d3 = ovl.Deflation(torch.from_numpy(phi_o).to(dev), lam_o, "f32")
+        p3 = ovl.Polynomial(alpha3, LMAX_BF16)
+        gpu["c3"] = ovl.sign_apply(gbf, p3, torch.from_numpy(psi).to(dev).to(torch.complex64),
+                                   defl=d3).cpu().to(torch.complex128).numpy()
+        jobs.append(("c3|exact", "sign", (u, psi, alpha3, LMAX_BF16, phi_o, lam_o)))
+        jobs.append(("c3|same", "sign", (rbf(u), r32(psi), alpha3, LMAX_BF16, r32(phi_o), lam_o)))
+        del gbf, d3
+    # C2: the deflated overlap operator, FP32 and FP64
+    if "c2" in _FIELDS:
+        u, psi, eps = _FIELDS["c2"]
+        phi_o = odefl.cgs2(latgen.gaussian_spinor(C2_DIMS, 777, nrhs=C2_NEV))
+        lam_o = np.linspace(-0.52, 0.52, C2_NEV) + 0.003
+        alpha2 = och.coeffs_sign_interp(C2_DEGREE, eps)
+        p2 = ovl.Polynomial(alpha2, LMAX)
+        du = torch.from_numpy(u).to(dev)
         dphi = torch.from_numpy(phi_o).to(dev)
-        p_o = ovl.Polynomial(alpha_o, LMAX)
-        d32 = ovl.Deflation(dphi, lam_o, "f32")
-        d64 = ovl.Deflation(dphi, lam_o, "f64")
-        o32 = ovl.overlap_apply(g32, p_o, psi32, MUS[(reps - 1) % 2], defl=d32).cpu().numpy()
-        o64 = ovl.overlap_apply(g64, p_o, psi64, MUS[(reps - 1) % 2], defl=d64).cpu().numpy()
-        nref = np.linalg.norm(ref)
-        # the oracle on the FP32-rounded links, source and basis isolates the kernel arithmetic
-        ref_r = oov.overlap_apply(latgen.round_to_f32(u), latgen.round_to_f32(psi),
-                                  MUS[(reps - 1) % 2], alpha_o, LMAX,
-                                  latgen.round_to_f32(phi_o), lam_o)
-        err_vs_oracle = {"f32": float(np.linalg.norm(o32 - ref) / nref),
-                         "f32_same_rounded_inputs": float(np.linalg.norm(o32 - ref_r)
-                                                          / np.linalg.norm(ref_r)),
-                         "f64": float(np.linalg.norm(o64 - ref) / nref)}
-        log(f"rel err vs oracle: {err_vs_oracle}")
+        x = torch.from_numpy(psi).to(dev)
+        for store in ("f32", "f64"):
+            g = ovl.GaugeField(du, store)
+            d = ovl.Deflation(dphi, lam_o, store)
+            xs = x if store == "f64" else x.to(torch.complex64)
+            gpu[f"c2_{store}"] = ovl.overlap_apply(g, p2, xs, MUS[1], defl=d).cpu().to(
+                torch.complex128).numpy()
+        jobs.append(("c2|exact", "overlap", (u, psi, MUS[1], alpha2, LMAX, phi_o, lam_o)))
+        jobs.append(("c2|same", "overlap", (r32(u), r32(psi), MUS[1], alpha2, LMAX, r32(phi_o),
+                                            lam_o)))
+    torch.cuda.synchronize()
+    # CPU baseline: the oracle on a bounded sample of the headline batch, one thread, in this
+    # process: full-degree applies on one 8^3x16 and one 12^3x24 source, and 60 of the 299
+    # K applications on one 16^3x32 source (scaled linearly to 299)
+    base = {}
+    with threadpool_limits(limits=1):
+        for item, nk in ((1, C4_DEGREE - 1), (5, C4_DEGREE - 1), (0, 60)):
+            dims, u, src = c4[item]
+            a = alpha4[: nk + 1]
+            t0 = time.perf_counter()
+            och.poly_apply(u, src[0], a, LMAX)
+            base[item] = (time.perf_counter() - t0) * (C4_DEGREE - 1) / nk
+    n_rhs = sum(nrhs for _, nrhs in C4_SHAPES)
+    t_batch = 12 * base[0] + 4 * base[1] + 2 * base[5]
+    sampled = sum(base[i] * (60 if i == 0 else C4_DEGREE - 1) / (C4_DEGREE - 1) for i in base)
+    cpu = {"value": round(n_rhs / t_batch, 5), "unit": "sign(K)psi right-hand-side applies/s",
+           "cores": 1, "kind": "oracle",
+           "sample": f"FP64 NumPy oracle (forward Chebyshev recurrence), one thread: degree 299 on "
+                     f"one 8^3x16 source ({base[1]:.1f} s) and one 12^3x24 source "
+                     f"({base[5]:.1f} s), 60 of 299 steps on one 16^3x32 source (scaled: "
+                     f"{base[0]:.1f} s); {sampled:.1f} s of CPU work; the batch of 18 sources "
+                     f"extrapolated to {t_batch:.0f} s ({len(os.sched_getaffinity(0))} cores "
+                     f"visible)"}
+    log(f"oracle baseline: {cpu['sample']}")
+    # the oracle evaluations for the errors, in parallel worker processes (spawned: they never
+    # touch the GPU)
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+        done = pool.map(_oracle_job, jobs, chunksize=1)
+    log(f"oracle leg: {len(jobs)} evaluations in {time.time() - t0:.0f} s")
+    refs = {name: (y, sec) for name, y, sec in done}
+    errs = {}
+    for key in gpu:
+        base_name = key if not key.startswith("c2_") else "c2"
+        ex, same = refs[base_name + "|exact"][0], refs[base_name + "|same"][0]
+        errs[key] = {"vs_oracle_exact_inputs": rel(gpu[key], ex),
+                     "vs_oracle_same_rounded_inputs": rel(gpu[key], same),
+                     "oracle_s": round(refs[base_name + "|exact"][1], 1)}
+    # C5: the stored oracle derivatives along seeded directions (tests/golden)
+    if os.path.exists(GOLDEN_FORCE) and "c5" in _FIELDS:
+        ref = json.load(open(GOLDEN_FORCE))
+        u, psi, chi = c5_inputs(latgen)
+        g32 = ovl.GaugeField(torch.from_numpy(u).to(dev), "f32")
+        pf = ovl.Polynomial(och.coeffs_sign_interp(ref["degree"], ref["eps"]), ref["lmax"])
+        G = ovl.sign_force(g32, pf, torch.from_numpy(chi).to(dev).to(torch.complex64),
+                           torch.from_numpy(psi).to(dev).to(torch.complex64),
+                           ckpt_stride=C5_STRIDE).cpu().to(torch.complex128).numpy()
+        del g32
+        e_ex, e_same = [], []
+        for k, seed in enumerate(ref["direction_seeds"]):
+            rng = np.random.Generator(np.random.PCG64(seed))
+            y = rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape)
+            dl = float(np.real(np.vdot(G, y)))
+            e_ex.append(abs(dl - ref["values"]["exact"][k]) / abs(ref["values"]["exact"][k]))
+            e_same.append(abs(dl - ref["values"]["f32_rounded"][k])
+                          / abs(ref["values"]["f32_rounded"][k]))
+        errs["c5_force"] = {"vs_oracle_exact_inputs": max(e_ex),
+                            "vs_oracle_same_rounded_inputs": max(e_same),
+                            "measure": "relative error of Re sum tr(G^+ Y) against the oracle's "
+                                       "forward-mode derivative along seeded Gaussian directions "
+                                       "Y (tests/golden/force_directional_24x24x24x48.json), "
+                                       "max over directions"}
+    for k, v in errs.items():
+        log(f"error vs oracle {k}: exact inputs {v['vs_oracle_exact_inputs']:.2e}, same rounded "
+            f"inputs {v['vs_oracle_same_rounded_inputs']:.2e}")
+    return cpu, errs
 
-    flags = g32.flags() | g64.flags()
-    value = 1e3 / ms32
+
+# ------------------------------------------------------------------------------------------------
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import latgen
+    import paper_1510_06897_amd as ovl
+    from paper_1510_06897_amd.eigsolve import low_modes
+
+    ovl.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.profile == "copy":
+        # a plain device copy of known size: 256 MiB read + 256 MiB written per copy
+        a = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            ovl.stream_probe(1, b, a, 256 << 20)
+        torch.cuda.synchronize()
+        log("copied 256 MiB twice")
+        return
+    if args.profile == "c4":
+        measure_c4(ovl, torch, dev, latgen, args.steps, args.warmup, profile=True)
+        return
+    if args.profile == "c3":
+        measure_c3(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
+        return
+    if args.profile == "force":
+        measure_force(ovl, torch, dev, latgen, args.steps, profile=True)
+        return
+    if args.profile == "c2":
+        measure_c2(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
+        return
+    if args.profile in ("dw", "dw2"):
+        measure_big(ovl, torch, dev, latgen, profile=args.profile, reps=args.steps)
+        return
+    if args.profile == "proj":
+        gen = torch.Generator(device=dev).manual_seed(7)
+        shape = (C3_NEV, 4, 3) + tuple(reversed(C3_DIMS))
+        phi = torch.randn(shape, dtype=torch.complex128, device=dev, generator=gen)
+        psi = torch.randn(shape[1:], dtype=torch.complex64, device=dev, generator=gen)
+        d = ovl.Deflation(phi, np.linspace(-0.5, 0.5, C3_NEV), "f32")
+        for _ in range(args.steps):
+            ovl.defl_project(d, psi)
+        torch.cuda.synchronize()
+        return
+
+    t_start = time.time()
+    c4 = measure_c4(ovl, torch, dev, latgen, args.steps, args.warmup)
+    extra = {}
+    if not args.no_extra:
+        extra["c3"] = measure_c3(ovl, torch, dev, latgen, low_modes, 5)
+        extra["c5_force"] = measure_force(ovl, torch, dev, latgen, 2)
+        extra["c2"] = measure_c2(ovl, torch, dev, latgen, low_modes, 20)
+        extra["k_and_sign_24x24x24x48"] = measure_big(ovl, torch, dev, latgen)
+        extra["streams_4GiB"] = measure_streams(ovl, torch, dev)
+    cpu, errs = (None, {})
+    if not args.no_cpu:
+        cpu, errs = oracle_leg(ovl, torch, dev, latgen, extra)
+
+    # ---- roofline of each form's dominant kernel (algorithmic bytes / average launch) ----
+    def roofline(kernel, bytes_per_launch, k_ms, k_n, tag=None):
+        avg_us = 1e3 * k_ms / k_n
+        ach = bytes_per_launch / (avg_us * 1e-6) / 1e9
+        return {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 1),
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                "traffic": counter_traffic(tag) if tag else None,
+                "avg_launch_us": round(avg_us, 3), "launches": k_n,
+                "bytes_per_launch": int(bytes_per_launch)}
+
+    c4_bytes = c4_bytes_per_step("f32", True)
+    rl = roofline(kernel_name(c4["config"], "f32", True), c4_bytes, c4["kernel_ms"],
+                  c4["kernel_launches"], tag="step_kernel_c4_batched")
+    rl["bytes_model"] = ("per step: every lattice's links once (two rows, 192 B/site) + "
+                         "3.5 FP32 spinor streams (96 B each) per site and right-hand side")
+    if "c3" in extra:
+        c3 = extra["c3"]
+        c3["roofline"] = roofline(kernel_name(c3["config"], "bf16", False, False),
+                                  step_bytes("bf16") * int(np.prod(C3_DIMS)), c3.pop("kernel_ms"),
+                                  c3.pop("kernel_launches"))
+        c3["roofline"]["note"] = "62.9 MB per launch: the working set stays in the 256 MB Infinity Cache"
+        c3["applies_per_s"] = round(1e3 / c3["ms_per_apply"], 2)
+        c3["ms_per_apply"] = round(c3["ms_per_apply"], 3)
+        c3["errors"] = errs.get("c3")
+    if "c5_force" in extra:
+        f = extra["c5_force"]
+        nv = f.pop("vjp_launches")
+        f["roofline"] = roofline("link_vjp_kernel<float,float2,float2>",
+                                 f["vjp_bytes_per_force"] / f["vjp_launches_per_force"],
+                                 f.pop("vjp_ms"), nv)
+        f["roofline"]["bytes_model"] = ("per force: every (b_{m+1}, t_m) pair's two FP32 spinors "
+                                        "once, the FP64 running sum of G between segments, G once")
+        f["ms_per_force"] = round(f["ms_per_force"], 2)
+        f["errors"] = errs.get("c5_force")
+    if "c2" in extra:
+        extra["c2"]["errors"] = {k: errs.get(f"c2_{k}") for k in ("f32", "f64")}
+
+    n_rhs = c4["n_rhs"]
+    ms = c4["ms_per_batch"]
     line = {
         "metric": METRIC,
-        "value": round(value, 2),
-        "unit": "sign(K)psi applies/s",
+        "value": round(n_rhs * 1e3 / ms, 2),
+        "unit": "sign(K)psi right-hand-side applies/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": max(2, args.warmup),   # the second apply captures the step graph
-        "ms_per_step": round(ms32, 4),
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "overlap D[mu] psi on 8^3x16 stout-smeared links (rho=0.1, 3 steps), "
-                        "Chebyshev degree 199 in K/lmax + 12 deflated low modes of K, "
-                        "mu in {0.01, 0.05}, FP32 storage + FP32 accumulation",
-            "lattice": "8x8x8x16", "degree": len(alpha) - 1, "n_ev": N_EV_C2,
-            "lmax": LMAX, "eps": round(float(eps), 5), "eigen_residual_max": float(res.max()),
+            "workload": "batched sign(K) psi, Chebyshev degree 300 (299 K applications, eps 0.05, "
+                        "no deflation): 12 spin-colour point sources on 16^3x32 + 4 x 8^3x16 + "
+                        "2 x 12^3x24 (one Gaussian source each), every lattice its own 3-step "
+                        "stout-smeared (rho 0.1) synthetic SU(3) field; FP32 storage and "
+                        "arithmetic, two-row link reads, one launch per K application for the "
+                        "whole batch, autotuned launch configuration",
+            "lattices": ["16x16x16x32 x12 rhs", "8x8x8x16 x4", "12x12x12x24 x2"],
+            "degree": C4_DEGREE - 1, "lmax": LMAX, "launch_config": c4["config"],
         },
-        "fp64_plain": {"value": round(1e3 / ms64, 2), "ms_per_step": round(ms64, 4),
-                       "speedup_f32_over_f64": round(ms64 / ms32, 3)},
-        "rel_err": {"f32_vs_f64_gpu": err_32_vs_64, "vs_oracle": err_vs_oracle},
-        "c2_solve_1e-10": solves,
-        "c2_12_sources": {"ms_per_call": round(ms12, 4),
-                          "rhs_applies_per_s": round(12e3 / ms12, 2),
-                          "note": "same operator, polynomial and deflation, 12 Gaussian sources "
-                                  "in one call (one launch per step for all of them)"},
-        "status_flags": flags,
-        "roofline": {
-            "kernel": "step_kernel<float,float2,float2> (fused stencil + Clenshaw step)",
-            "bound": "hbm",
-            "achieved": round(k_gbps, 1),
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": round(k_gbps / HBM_PEAK_GBPS, 4),
-            "traffic": counter_traffic("step_kernel_f32_overlap_8x8x8x16"),
-            "avg_launch_us": round(k_avg_us, 3),
-            "launches": k_n,
-            "bytes_per_launch": k_bytes,
-        },
+        "roofline": rl,
         "cpu_baseline": cpu,
-        "hbm_copy_4GiB": {"GBps": round(copy_gbps, 1), "frac_of_8TBps": round(copy_gbps / HBM_PEAK_GBPS, 4),
-                          "note": "torch copy_ of a 4 GiB buffer, read + write bytes"},
-        "dw_24x24x24x48": dw,
-        "sign_24x24x24x48": {"workload": "sign(K)psi on 24^3x48 near-unit links, degree 199, "
-                                         "eps 0.05, no deflation, one source",
-                             **sign_big},
+        "rel_err": {k: v for k, v in errs.items() if k.startswith("c4_")} or None,
+        "c4_batched": {k: v for k, v in c4.items() if k not in ("kernel_ms", "kernel_launches")},
+        **extra,
+        "wall_s": round(time.time() - t_start, 1),
     }
-    line.update(extra)
+    line["c4_batched"]["ms_per_batch"] = round(ms, 4)
     print(json.dumps(line), flush=True)
 
 

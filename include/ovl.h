@@ -215,6 +215,43 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const voi
 int ovl_sign_residual(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, const void *in,
                       int nrhs, int spin_dt, double *r_out, void *stream);
 
+/* ---- low modes of K (the deflation basis) ------------------------------------------------------ */
+
+/* The n_ev eigenpairs of K = gamma5 (D_W - m_W) with the smallest |lambda|, which the deflation
+ * term of Sec. 2, eq. 3 removes from the polynomial (the paper precomputes them once per gauge
+ * field by a polynomial-preconditioned Lanczos method, Sec. 2).  Method: Chebyshev-filtered
+ * subspace iteration on a block of `block` vectors: the filter T_degree((2 K^2 - (cut^2 + lmax^2))
+ * / (lmax^2 - cut^2)) is bounded by 1 for cut <= |lambda| <= lmax and grows fastest towards
+ * lambda = 0; each iteration orthonormalises the block (scaled SVQB from its FP64 Gram matrix;
+ * numerically dependent directions are replaced by fresh random vectors), does a Rayleigh-Ritz
+ * step with K itself (so +lambda and -lambda separate), orders the Ritz pairs by ||K v|| and
+ * stops when the first n_ev residuals ||K phi - lambda phi|| are below tol or after max_iter
+ * iterations.  Every K application runs in the fused stencil kernel with `block` right-hand sides;
+ * Gram products, block rotations and residual norms are FP64 device kernels; the block x block
+ * Hermitian eigen-problems are solved on the host (Householder tridiagonalisation + implicit QL).
+ * The start block is complex Gaussian from a counter-based generator keyed by `seed`.
+ *   g        gauge handle with FP64 link storage;  m_W the Wilson mass of K
+ *   block    1 <= n_ev < block <= min(256, 12 V); it must exceed the size of any near-degenerate
+ *            cluster of eigenvalues that straddles the n_ev-th one
+ *   phi_out  caller-owned device [n_ev][4][3][T][Z][Y][X] complex double (orthonormal);
+ *   lambda_out, resid_out  host arrays of n_ev doubles (ascending |lambda| up to the ordering by
+ *            ||K phi||); eps_next_out (nullable) = |lambda| of the first Ritz value beyond n_ev
+ *            divided by lmax (the lower end of the polynomial's interval); iters_out (nullable).
+ * Allocates about 5 * block * 12 V complex doubles of work space for the call; synchronises the
+ * stream.  Errors: EINVAL, EDTYPE (links not FP64), EDIMS, ENONFINITE, ENOMEM, EHIP; EDIVERGED
+ * when the residuals are above tol after max_iter iterations (the outputs hold the last
+ * iterate). */
+int ovl_low_modes(const ovl_gauge *g, int n_ev, int block, double lmax, double cut, int degree,
+                  int max_iter, double tol, uint64_t seed, double m_W, void *phi_out,
+                  double *lambda_out, double *resid_out, double *eps_next_out, int *iters_out,
+                  void *stream);
+
+/* The host eigen-solver of ovl_low_modes on its own (no device involved): a (n x n, row-major,
+ * interleaved complex double) Hermitian -> w (n ascending eigenvalues) and q (n x n row-major
+ * complex, eigenvectors in the columns).  Errors: EINVAL (NULL, n outside [1, 4096], not
+ * Hermitian to 1e-12), EDIVERGED (no convergence). */
+int ovl_hermitian_eigh(int n, const double *a, double *w, double *q);
+
 /* ---- overlap inversion ---------------------------------------------------------------------- */
 
 /* Solve D[mu] x = b for one FP64 vector (Sec. 2: the overlap operator exists to be inverted; the

@@ -46,6 +46,9 @@ SIGNATURES = {
     "ovl_sign_residual": (_i, [_vp, _vp, _vp, _vp, _i, _i, _dp, _vp]),
     "ovl_overlap_solve": (_i, [_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _d, _i,
                                ctypes.POINTER(_i), _dp, _vp]),
+    "ovl_low_modes": (_i, [_vp, _i, _i, _d, _d, _i, _i, _d, ctypes.c_uint64, _d, _vp, _dp, _dp,
+                           _dp, ctypes.POINTER(_i), _vp]),
+    "ovl_hermitian_eigh": (_i, [_i, _dp, _dp, _dp]),
     "ovl_autotune": (_i, [_vp, _i, _vp, _i, ctypes.c_char_p, _dp, _vp]),
     "ovl_autotune_load": (_i, [ctypes.c_char_p]),
     "ovl_launch_config": (_i, [_vp, _i, _i, ctypes.POINTER(_i)]),

@@ -1224,6 +1224,168 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Dense block algebra of the low-mode eigen-solve (FP64 complex, blocks of m vectors of n complex
+// elements stored one vector after the other).
+//
+// Gram products  G[j][i] = sum_k conj(A_i[k]) B_j[k]  (the inner products <A_i, B_j>).  A
+// workgroup of 256 threads owns a 32 x 32 tile of (i, j) and a slice of k; each thread keeps a
+// 2 x 2 sub-tile in registers while the 32 A and 32 B vectors of the tile stream through LDS in
+// chunks of kGramKC elements.  Slices are summed by gram_reduce_kernel in a fixed order.
+constexpr int kGramT = 32;   // tile edge
+constexpr int kGramKC = 32;  // k chunk staged in LDS
+__global__ void __launch_bounds__(256)
+    gram_partial_kernel(const double2 *__restrict__ A, int ma, const double2 *__restrict__ B,
+                        int mb, int64_t n, int64_t slice, double2 *__restrict__ partial) {
+  __shared__ double2 sa[kGramT][kGramKC + 1];
+  __shared__ double2 sb[kGramT][kGramKC + 1];
+  const int i0 = blockIdx.x * kGramT, j0 = blockIdx.y * kGramT;
+  const int64_t kbeg = (int64_t)blockIdx.z * slice;
+  const int64_t kend = kbeg + slice < n ? kbeg + slice : n;
+  const int ti = (threadIdx.x & 15) * 2, tj = (threadIdx.x >> 4) * 2;
+  double acc[2][2][2] = {};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kGramKC) {
+    // stage 32 x 32 elements of A and of B: 4 loads per thread each, consecutive k per lane
+    for (int e = threadIdx.x; e < kGramT * kGramKC; e += 256) {
+      const int r = e / kGramKC, c = e % kGramKC;
+      const int64_t k = k0 + c;
+      const bool kin = k < kend;
+      sa[r][c] = (kin && i0 + r < ma) ? A[(int64_t)(i0 + r) * n + k] : make_double2(0.0, 0.0);
+      sb[r][c] = (kin && j0 + r < mb) ? B[(int64_t)(j0 + r) * n + k] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < kGramKC; ++c) {
+      const double2 a0 = sa[ti][c], a1 = sa[ti + 1][c];
+      const double2 b0 = sb[tj][c], b1 = sb[tj + 1][c];
+      const double2 av[2] = {a0, a1}, bv[2] = {b0, b1};
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          // conj(a) b
+          acc[x][y][0] = fma(av[x].x, bv[y].x, fma(av[x].y, bv[y].y, acc[x][y][0]));
+          acc[x][y][1] = fma(av[x].x, bv[y].y, fma(-av[x].y, bv[y].x, acc[x][y][1]));
+        }
+    }
+    __syncthreads();
+  }
+  const int64_t tiles = (int64_t)gridDim.x * gridDim.y;
+  const int64_t tile = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      partial[((int64_t)blockIdx.z * tiles + tile) * (kGramT * kGramT) + (tj + y) * kGramT + ti + x] =
+          make_double2(acc[x][y][0], acc[x][y][1]);
+}
+
+// G[j][i] (j < mb, i < ma) = sum over the slices of the partial tiles, in slice order
+__global__ void __launch_bounds__(256)
+    gram_reduce_kernel(const double2 *__restrict__ partial, int ma, int mb, int nslice,
+                       double2 *__restrict__ G) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= ma * mb) return;
+  const int j = idx / ma, i = idx % ma;
+  const int gx = (ma + kGramT - 1) / kGramT, gy = (mb + kGramT - 1) / kGramT;
+  const int64_t tiles = (int64_t)gx * gy;
+  const int64_t tile = (int64_t)(j / kGramT) * gx + i / kGramT;
+  const int off = (j % kGramT) * kGramT + i % kGramT;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < nslice; ++z) {
+    const double2 v = partial[((int64_t)z * tiles + tile) * (kGramT * kGramT) + off];
+    re += v.x;
+    im += v.y;
+  }
+  G[(int64_t)j * ma + i] = make_double2(re, im);
+}
+
+// Block rotation  Out_j[k] = sum_i C[i][j] V_i[k]  (j < mo, i < mi; C complex, row-major mi x mo),
+// Out must not overlap V.  A thread owns one k and kRotJ consecutive outputs j, C's column tile in
+// LDS; every V_i[k] read feeds kRotJ multiply-adds.
+constexpr int kRotJ = 32;
+constexpr int kRotI = 64;  // rows of C staged per pass
+__global__ void __launch_bounds__(256)
+    rotate_kernel(const double2 *__restrict__ V, int mi, int64_t n, const double2 *__restrict__ C,
+                  int mo, double2 *__restrict__ Out) {
+  __shared__ double2 cs[kRotI][kRotJ];  // rows i0 .. i0 + kRotI - 1 of the tile's columns
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * kRotJ;
+  double acc[kRotJ][2];
+#pragma unroll
+  for (int j = 0; j < kRotJ; ++j) acc[j][0] = acc[j][1] = 0.0;
+  for (int i0 = 0; i0 < mi; i0 += kRotI) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kRotI * kRotJ; e += 256) {
+      const int r = e / kRotJ, c = e % kRotJ;
+      cs[r][c] = (i0 + r < mi && j0 + c < mo) ? C[(int64_t)(i0 + r) * mo + j0 + c]
+                                              : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (k < n) {
+      const int iend = mi - i0 < kRotI ? mi - i0 : kRotI;
+      for (int r = 0; r < iend; ++r) {
+        const double2 v = V[(int64_t)(i0 + r) * n + k];
+#pragma unroll
+        for (int j = 0; j < kRotJ; ++j) {
+          const double2 c = cs[r][j];
+          acc[j][0] = fma(c.x, v.x, fma(-c.y, v.y, acc[j][0]));
+          acc[j][1] = fma(c.x, v.y, fma(c.y, v.x, acc[j][1]));
+        }
+      }
+    }
+  }
+  if (k >= n) return;
+#pragma unroll
+  for (int j = 0; j < kRotJ; ++j)
+    if (j0 + j < mo) Out[(int64_t)(j0 + j) * n + k] = make_double2(acc[j][0], acc[j][1]);
+}
+
+// partial[b][j] = sum over block b's elements of |W_j[k] - lam_j V_j[k]|^2 (lam null: |W_j|^2)
+__global__ void __launch_bounds__(256)
+    resid_partial_kernel(const double2 *__restrict__ W, const double2 *__restrict__ V,
+                         const double *__restrict__ lam, int64_t n, double *__restrict__ partial) {
+  __shared__ double lds[16];
+  const int j = blockIdx.y;
+  const double l = lam ? lam[j] : 0.0;
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) {
+    double2 w = W[(int64_t)j * n + k];
+    if (lam) {
+      const double2 v = V[(int64_t)j * n + k];
+      w.x -= l * v.x;
+      w.y -= l * v.y;
+    }
+    s += w.x * w.x + w.y * w.y;
+  }
+  double v1[1] = {s};
+  block_sum<1>(v1, lds);
+  if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = v1[0];
+}
+
+// Seeded complex Gaussian block (a + ib, a, b ~ N(0, 1)) from a counter-based generator:
+// element e of the block draws two 64-bit words splitmix64(seed, 2e), splitmix64(seed, 2e + 1)
+// (the SplitMix64 finaliser of Steele, Lea and Flood, 2014) turned into uniforms in (0, 1] and
+// then into a normal pair by the Box-Muller transform.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+__global__ void gaussian_block_kernel(double2 *out, int64_t count, uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const uint64_t base = splitmix64(seed);
+  const uint64_t w0 = splitmix64(base ^ (uint64_t)(2 * e));
+  const uint64_t w1 = splitmix64(base ^ (uint64_t)(2 * e + 1));
+  const double u1 = ((w0 >> 11) + 1) * 0x1.0p-53;  // (0, 1]
+  const double u2 = (w1 >> 11) * 0x1.0p-53;         // [0, 1)
+  const double r = sqrt(-2.0 * log(u1));
+  const double t = 2.0 * M_PI * u2;
+  out[e] = make_double2(r * cos(t), r * sin(t));
+}
+
+// ---------------------------------------------------------------------------------------------
 // Bandwidth ceilings of the device memory: plain streams of 16-byte elements, each element touched
 // once, four loads in flight per thread (grid-stride).  Read: every element is loaded and folded
 // into a per-thread value (stored once per thread so the loads stay live).  Copy: dst = src.

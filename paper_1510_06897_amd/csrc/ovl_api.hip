@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <complex>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <type_traits>
 #include <mutex>
@@ -1898,6 +1899,407 @@ int ovl_sign_residual(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
   return OVL_OK;
 }
 
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// low modes of K (the deflation basis of Sec. 2, eq. 3)
+namespace {
+
+using cplx = std::complex<double>;
+
+// Eigen-decomposition of a Hermitian n x n matrix A (row-major): Householder reduction to
+// Hermitian tridiagonal form, a diagonal phase similarity that makes the tridiagonal real, the
+// implicit QL iteration with Wilkinson-type shifts on the real tridiagonal (accumulating its
+// rotations), and back-transformation.  w ascending; the eigenvectors are the columns of Q
+// (row-major).  Returns false if the QL iteration does not converge.
+bool hermitian_eigh(int n, std::vector<cplx> A, std::vector<double> &w, std::vector<cplx> &Q) {
+  auto a = [&](int i, int j) -> cplx & { return A[(size_t)i * n + j]; };
+  std::vector<cplx> hv((size_t)n * n, cplx(0.0, 0.0));  // Householder vector of step k in column k
+  std::vector<bool> has(n, false);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int L = n - k - 1;
+    double xn2 = 0.0;
+    for (int i = 0; i < L; ++i) xn2 += std::norm(a(k + 1 + i, k));
+    const double xn = std::sqrt(xn2);
+    if (xn == 0.0) continue;
+    const cplx x0 = a(k + 1, k);
+    const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0, 0.0);
+    const cplx alpha = -ph * xn;  // H x = alpha e_1
+    std::vector<cplx> v(L);
+    for (int i = 0; i < L; ++i) v[i] = a(k + 1 + i, k);
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < L; ++i) vn2 += std::norm(v[i]);
+    if (vn2 == 0.0) continue;
+    const double vn = std::sqrt(vn2);
+    for (int i = 0; i < L; ++i) v[i] /= vn;
+    // trailing block B <- H B H with H = 1 - 2 v v^+:  p = B v, beta = v^+ p, w = p - beta v,
+    // B <- B - 2 v w^+ - 2 w v^+
+    std::vector<cplx> pv(L, 0.0);
+    for (int i = 0; i < L; ++i) {
+      cplx t = 0.0;
+      for (int j = 0; j < L; ++j) t += a(k + 1 + i, k + 1 + j) * v[j];
+      pv[i] = t;
+    }
+    cplx beta = 0.0;
+    for (int i = 0; i < L; ++i) beta += std::conj(v[i]) * pv[i];
+    for (int i = 0; i < L; ++i) pv[i] -= beta.real() * v[i];
+    for (int i = 0; i < L; ++i)
+      for (int j = 0; j < L; ++j)
+        a(k + 1 + i, k + 1 + j) -= 2.0 * (v[i] * std::conj(pv[j]) + pv[i] * std::conj(v[j]));
+    a(k + 1, k) = alpha;
+    a(k, k + 1) = std::conj(alpha);
+    for (int i = 1; i < L; ++i) a(k + 1 + i, k) = a(k, k + 1 + i) = 0.0;
+    for (int i = 0; i < L; ++i) hv[(size_t)(k + 1 + i) * n + k] = v[i];
+    has[k] = true;
+  }
+  // phases that make the sub-diagonal real and non-negative: T' = D^+ T D
+  std::vector<cplx> phi(n, cplx(1.0, 0.0));
+  std::vector<double> d(n), e(n, 0.0);
+  for (int k = 0; k < n; ++k) d[k] = a(k, k).real();
+  for (int k = 0; k + 1 < n; ++k) {
+    const cplx t = a(k + 1, k);
+    const double m = std::abs(t);
+    phi[k + 1] = m > 0.0 ? phi[k] * (t / m) : phi[k];
+    e[k] = m;
+  }
+  // implicit QL on (d, e), rotations accumulated into Z (real, row-major)
+  std::vector<double> Z((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    int iter = 0, m;
+    do {
+      for (m = l; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
+      }
+      if (m != l) {
+        if (iter++ == 100) return false;
+        double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+        double r = std::hypot(g, 1.0);
+        g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+        double s2 = 1.0, c = 1.0, p = 0.0;
+        int i;
+        for (i = m - 1; i >= l; --i) {
+          double f = s2 * e[i];
+          const double b = c * e[i];
+          e[i + 1] = (r = std::hypot(f, g));
+          if (r == 0.0) {
+            d[i + 1] -= p;
+            e[m] = 0.0;
+            break;
+          }
+          s2 = f / r;
+          c = g / r;
+          g = d[i + 1] - p;
+          r = (d[i] - g) * s2 + 2.0 * c * b;
+          d[i + 1] = g + (p = s2 * r);
+          g = c * r - b;
+          for (int k = 0; k < n; ++k) {
+            f = Z[(size_t)k * n + i + 1];
+            Z[(size_t)k * n + i + 1] = s2 * Z[(size_t)k * n + i] + c * f;
+            Z[(size_t)k * n + i] = c * Z[(size_t)k * n + i] - s2 * f;
+          }
+        }
+        if (r == 0.0 && i >= l) continue;
+        d[l] -= p;
+        e[l] = g;
+        e[m] = 0.0;
+      }
+    } while (m != l);
+  }
+  // Q = H_0 H_1 ... (D Z), columns ordered by eigenvalue
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int x, int y) { return d[x] < d[y]; });
+  Q.assign((size_t)n * n, cplx(0.0, 0.0));
+  w.resize(n);
+  for (int jn = 0; jn < n; ++jn) {
+    w[jn] = d[order[jn]];
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + jn] = phi[i] * Z[(size_t)i * n + order[jn]];
+  }
+  for (int k = n - 3; k >= 0; --k) {
+    if (!has[k]) continue;
+    for (int j = 0; j < n; ++j) {  // column j <- (1 - 2 v v^+) column j on rows k+1 ..
+      cplx t = 0.0;
+      for (int i = k + 1; i < n; ++i) t += std::conj(hv[(size_t)i * n + k]) * Q[(size_t)i * n + j];
+      for (int i = k + 1; i < n; ++i) Q[(size_t)i * n + j] -= 2.0 * hv[(size_t)i * n + k] * t;
+    }
+  }
+  return true;
+}
+
+// device block algebra of the eigen-solve
+struct BlockOps {
+  hipStream_t s;
+  int64_t n;           // complex elements per vector (12 V)
+  double2 *partial;    // Gram slices
+  size_t partial_cap;  // elements
+  double2 *gdev;       // Gram result / rotation matrix (m x m)
+  double *rpart;       // residual partials [m][kResBlocks]
+};
+constexpr int kResBlocks = 512;
+
+// H[i][j] = <A_i, B_j> on the host (synchronises the stream)
+int block_gram(BlockOps &o, const double2 *A, int ma, const double2 *B, int mb,
+               std::vector<cplx> &H) {
+  const int gx = (ma + kGramT - 1) / kGramT, gy = (mb + kGramT - 1) / kGramT;
+  const int64_t tiles = (int64_t)gx * gy;
+  int nslice = (int)std::max<int64_t>(1, std::min<int64_t>(512, 4096 / tiles));
+  nslice = (int)std::min<int64_t>(nslice, (o.partial_cap / (tiles * kGramT * kGramT)));
+  nslice = std::max(nslice, 1);
+  int64_t slice = (o.n + nslice - 1) / nslice;
+  slice = (slice + kGramKC - 1) / kGramKC * kGramKC;
+  nslice = (int)((o.n + slice - 1) / slice);
+  gram_partial_kernel<<<dim3(gx, gy, nslice), 256, 0, o.s>>>(A, ma, B, mb, o.n, slice, o.partial);
+  HIP_TRY(hipGetLastError());
+  gram_reduce_kernel<<<(ma * mb + 255) / 256, 256, 0, o.s>>>(o.partial, ma, mb, nslice, o.gdev);
+  HIP_TRY(hipGetLastError());
+  std::vector<double2> h((size_t)ma * mb);
+  HIP_TRY(hipMemcpyAsync(h.data(), o.gdev, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, o.s));
+  HIP_TRY(hipStreamSynchronize(o.s));
+  H.assign((size_t)ma * mb, cplx(0.0, 0.0));
+  for (int j = 0; j < mb; ++j)
+    for (int i = 0; i < ma; ++i) H[(size_t)i * mb + j] = cplx(h[(size_t)j * ma + i].x, h[(size_t)j * ma + i].y);
+  return OVL_OK;
+}
+
+// Out_j = sum_i C[i][j] V_i (C host, mi x mo row-major)
+int block_rotate(BlockOps &o, const double2 *V, int mi, const std::vector<cplx> &C, int mo,
+                 double2 *Out) {
+  std::vector<double2> h((size_t)mi * mo);
+  for (size_t k = 0; k < h.size(); ++k) h[k] = make_double2(C[k].real(), C[k].imag());
+  HIP_TRY(hipMemcpyAsync(o.gdev, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, o.s));
+  rotate_kernel<<<dim3((unsigned)((o.n + 255) / 256), (mo + kRotJ - 1) / kRotJ), 256, 0, o.s>>>(
+      V, mi, o.n, o.gdev, mo, Out);
+  HIP_TRY(hipGetLastError());
+  // the staging of C must not be rewritten before the rotation has read it
+  HIP_TRY(hipStreamSynchronize(o.s));
+  return OVL_OK;
+}
+
+// r[j] = ||W_j - lam_j V_j|| (lam empty: ||W_j||) for j < m (synchronises the stream)
+int block_resid(BlockOps &o, const double2 *W, const double2 *V, const std::vector<double> &lam,
+                int m, std::vector<double> &r) {
+  double *lam_dev = nullptr;
+  if (!lam.empty()) {
+    HIP_TRY(hipMemcpyAsync(o.gdev, lam.data(), sizeof(double) * m, hipMemcpyHostToDevice, o.s));
+    lam_dev = (double *)o.gdev;
+  }
+  const int nb = (int)std::min<int64_t>(kResBlocks, (o.n + 255) / 256);
+  resid_partial_kernel<<<dim3(nb, m), 256, 0, o.s>>>(W, V, lam_dev, o.n, o.rpart);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h((size_t)m * nb);
+  HIP_TRY(hipMemcpyAsync(h.data(), o.rpart, sizeof(double) * h.size(), hipMemcpyDeviceToHost, o.s));
+  HIP_TRY(hipStreamSynchronize(o.s));
+  r.assign(m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    double t = 0.0;
+    for (int b = 0; b < nb; ++b) t += h[(size_t)j * nb + b];
+    r[j] = std::sqrt(t);
+  }
+  return OVL_OK;
+}
+
+// out = c K in + a src + b w for a block of nrhs vectors (FP64), one fused launch
+int block_k(const ovl_gauge *g, double2 *out, const double2 *in, double c, const double2 *src,
+            double a, const double2 *w, double b, int nrhs, double m_W, hipStream_t s) {
+  StepArgs<false> p = single_args(g, nrhs);
+  p.item.psi = src;
+  p.item.buf[0] = const_cast<double2 *>(in);
+  p.item.buf[1] = const_cast<double2 *>(w);
+  p.item.buf[2] = out;
+  p.v_role = ROLE_B0;
+  p.w_role = w ? ROLE_B1 : ROLE_NONE;
+  p.out_role = ROLE_B2;
+  p.y_g5 = 1;
+  p.kd = c * (4.0 - m_W);
+  p.kh = -0.5 * c;
+  p.a = src ? a : 0.0;
+  p.t = w ? b : 0.0;
+  return dispatch_single(P_F64, p, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+// Chebyshev-filtered subspace iteration on K for the n_ev eigenpairs of smallest |lambda|: the
+// filter T_degree((2 K^2 - (cut^2 + lmax^2)) / (lmax^2 - cut^2)) grows fastest towards K = 0 and
+// is bounded by 1 on cut <= |lambda| <= lmax; each iteration orthonormalises the block (scaled
+// SVQB from its Gram matrix), applies Rayleigh-Ritz with K itself (so +lambda and -lambda
+// separate), orders the Ritz pairs by ||K v||, checks the residuals and filters the block.
+int ovl_low_modes(const ovl_gauge *g, int n_ev, int block, double lmax, double cut, int degree,
+                  int max_iter, double tol, uint64_t seed, double m_W, void *phi_out,
+                  double *lambda_out, double *resid_out, double *eps_next_out, int *iters_out,
+                  void *stream) {
+  g_err[0] = 0;
+  if (!g || !phi_out || !lambda_out || !resid_out) return fail(OVL_EINVAL, "NULL argument");
+  if (g->store_dt != OVL_F64) return fail(OVL_EDTYPE, "the eigen-solve needs FP64 link storage");
+  const int m = block;
+  if (n_ev < 1 || m <= n_ev || m > 256 || (int64_t)m > (int64_t)12 * g->g.V)
+    return fail(OVL_EINVAL, "need 1 <= n_ev < block <= min(256, 12 V) (n_ev %d, block %d)", n_ev, m);
+  if (!std::isfinite(lmax) || !std::isfinite(cut) || !std::isfinite(m_W) || !std::isfinite(tol))
+    return fail(OVL_ENONFINITE, "non-finite parameter");
+  if (!(cut > 0.0) || !(lmax > cut) || degree < 1 || degree > 10000 || max_iter < 1 || !(tol > 0.0))
+    return fail(OVL_EINVAL, "need 0 < cut < lmax, degree in [1, 10000], max_iter >= 1, tol > 0");
+  if (!fits_u32(12ull * g->g.V, OVL_F64)) return fail(OVL_EDIMS, "lattice too large");
+  hipStream_t s = as_stream(stream);
+  const int64_t n = (int64_t)12 * g->g.V;
+  const size_t vb = (size_t)m * n * sizeof(double2);
+  const size_t vbp = (vb + 255) / 256 * 256;
+  const int64_t tiles = (int64_t)((m + kGramT - 1) / kGramT) * ((m + kGramT - 1) / kGramT);
+  const size_t part_elems = (size_t)tiles * kGramT * kGramT * 512;
+  Scratch sc;
+  int rc = scratch_alloc(sc, 5 * vbp + part_elems * sizeof(double2) +
+                                 (size_t)m * m * sizeof(double2) + (size_t)m * kResBlocks * 8 + 1024, s);
+  if (rc) return rc;
+  char *base = (char *)sc.p;
+  double2 *buf[5];
+  for (int k = 0; k < 5; ++k) buf[k] = (double2 *)(base + k * vbp);
+  BlockOps o{s, n, (double2 *)(base + 5 * vbp), part_elems, nullptr, nullptr};
+  o.gdev = (double2 *)((char *)o.partial + part_elems * sizeof(double2));
+  o.rpart = (double *)((char *)o.gdev + (size_t)m * m * sizeof(double2));
+  double2 *V = buf[0], *W = buf[1], *T0 = buf[2], *T1 = buf[3], *T2 = buf[4];
+  uint64_t draws = 0;  // fresh draws of the seeded generator
+  auto fill = [&](double2 *dst, int64_t count) -> int {
+    gaussian_block_kernel<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(dst, count, seed + draws++);
+    HIP_TRY(hipGetLastError());
+    return OVL_OK;
+  };
+  if ((rc = fill(V, (int64_t)m * n))) return rc;
+  std::vector<double> lam, res;
+  const double bq = lmax * lmax, aq = cut * cut;
+  const double c1 = 2.0 / (bq - aq), c0 = -(aq + bq) / (bq - aq);
+  int it = 0;
+  for (;; ++it) {
+    // orthonormalise: G = V^+ V, D = diag(G)^-1/2, D G D = Q diag(l) Q^+, V <- (D Q l^-1/2)^T V;
+    // directions with l below 1e-12 l_max are dropped and refilled from the generator
+    for (int pass = 0, good = 0; good < 2; ++pass) {
+      if (pass > 8) return fail(OVL_EDIVERGED, "block orthonormalisation failed");
+      std::vector<cplx> G, Q;
+      std::vector<double> l;
+      if ((rc = block_gram(o, V, m, V, m, G))) return rc;
+      std::vector<double> d(m);
+      for (int i = 0; i < m; ++i) {
+        const double gi = G[(size_t)i * m + i].real();
+        if (!std::isfinite(gi)) return fail(OVL_ENONFINITE, "non-finite block vector");
+        d[i] = gi > 0.0 ? 1.0 / std::sqrt(gi) : 0.0;
+      }
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) G[(size_t)i * m + j] *= d[i] * d[j];
+      if (!hermitian_eigh(m, G, l, Q)) return fail(OVL_EDIVERGED, "Gram eigen-decomposition failed");
+      int weak = 0;
+      while (weak < m && !(l[weak] > 1e-12 * l[m - 1])) ++weak;
+      const int keep = m - weak;
+      std::vector<cplx> C((size_t)m * keep);
+      for (int i = 0; i < m; ++i)
+        for (int k = 0; k < keep; ++k)
+          C[(size_t)i * keep + k] = d[i] * Q[(size_t)i * m + weak + k] / std::sqrt(l[weak + k]);
+      if ((rc = block_rotate(o, V, m, C, keep, T0))) return rc;
+      std::swap(V, T0);
+      if (weak) {
+        if ((rc = fill(V + (int64_t)keep * n, (int64_t)weak * n))) return rc;
+        good = 0;
+      } else {
+        ++good;
+      }
+    }
+    // Rayleigh-Ritz with K: H = V^+ K V, ordered by ||K v|| (directions that have not converged
+    // mix +lambda and -lambda and have Rayleigh quotients near zero)
+    if ((rc = block_k(g, W, V, 1.0, nullptr, 0.0, nullptr, 0.0, m, m_W, s))) return rc;
+    std::vector<cplx> H, M, Y;
+    if ((rc = block_gram(o, V, m, W, m, H))) return rc;
+    if ((rc = block_gram(o, W, m, W, m, M))) return rc;
+    for (int i = 0; i < m; ++i)
+      for (int j = i; j < m; ++j) {
+        const cplx h = 0.5 * (H[(size_t)i * m + j] + std::conj(H[(size_t)j * m + i]));
+        H[(size_t)i * m + j] = h;
+        H[(size_t)j * m + i] = std::conj(h);
+      }
+    std::vector<double> w;
+    if (!hermitian_eigh(m, H, w, Y)) return fail(OVL_EDIVERGED, "Ritz eigen-decomposition failed");
+    std::vector<double> kn(m, 0.0);
+    for (int k = 0; k < m; ++k) {
+      cplx t = 0.0;
+      for (int i = 0; i < m; ++i) {
+        cplx row = 0.0;
+        for (int j = 0; j < m; ++j) row += M[(size_t)i * m + j] * Y[(size_t)j * m + k];
+        t += std::conj(Y[(size_t)i * m + k]) * row;
+      }
+      kn[k] = t.real();
+    }
+    std::vector<int> order(m);
+    for (int k = 0; k < m; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return kn[a] < kn[b]; });
+    std::vector<cplx> C((size_t)m * m);
+    lam.assign(m, 0.0);
+    for (int k = 0; k < m; ++k) {
+      lam[k] = w[order[k]];
+      for (int i = 0; i < m; ++i) C[(size_t)i * m + k] = Y[(size_t)i * m + order[k]];
+    }
+    if ((rc = block_rotate(o, V, m, C, m, T0))) return rc;
+    std::swap(V, T0);
+    if ((rc = block_rotate(o, W, m, C, m, T0))) return rc;
+    std::swap(W, T0);
+    if ((rc = block_resid(o, W, V, lam, m, res))) return rc;
+    double worst = 0.0;
+    for (int k = 0; k < n_ev; ++k) worst = std::max(worst, res[k]);
+    if (worst < tol || it + 1 >= max_iter) break;
+    // filter: t_0 = V, t_1 = Z V, t_{j+1} = 2 Z t_j - t_{j-1}, Z x = c1 K (K x) + c0 x
+    if ((rc = block_k(g, T0, V, 1.0, nullptr, 0.0, nullptr, 0.0, m, m_W, s))) return rc;
+    if ((rc = block_k(g, T1, T0, c1, V, c0, nullptr, 0.0, m, m_W, s))) return rc;
+    double2 *tp = V, *tc = T1;
+    double2 *spare = T2;
+    for (int j = 2; j <= degree; ++j) {
+      if ((rc = block_k(g, T0, tc, 1.0, nullptr, 0.0, nullptr, 0.0, m, m_W, s))) return rc;
+      // t_{j} = 2 c1 K y + 2 c0 t_{j-1} - t_{j-2}, written over t_{j-2}
+      if ((rc = block_k(g, tp, T0, 2.0 * c1, tc, 2.0 * c0, tp, -1.0, m, m_W, s))) return rc;
+      std::swap(tp, tc);
+    }
+    // the filtered block becomes V; the other two buffers are work space again
+    V = tc;
+    T1 = tp;
+    T2 = spare;
+  }
+  HIP_TRY(hipMemcpyAsync(phi_out, V, sizeof(double2) * (size_t)n_ev * n, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double worst = 0.0;
+  for (int k = 0; k < n_ev; ++k) {
+    lambda_out[k] = lam[k];
+    resid_out[k] = res[k];
+    worst = std::max(worst, res[k]);
+  }
+  if (eps_next_out) *eps_next_out = std::fabs(lam[n_ev]) / lmax;
+  if (iters_out) *iters_out = it + 1;
+  if (!(worst < tol))
+    return fail(OVL_EDIVERGED, "residual %.3e above %.3e after %d iterations", worst, tol, it + 1);
+  return OVL_OK;
+}
+
+// Hermitian eigen-decomposition of the eigen-solve, on host memory (no device involved)
+int ovl_hermitian_eigh(int n, const double *a, double *w, double *q) {
+  g_err[0] = 0;
+  if (!a || !w || !q) return fail(OVL_EINVAL, "NULL argument");
+  if (n < 1 || n > 4096) return fail(OVL_EINVAL, "n = %d out of range [1, 4096]", n);
+  std::vector<cplx> A((size_t)n * n), Q;
+  for (size_t k = 0; k < A.size(); ++k) A[k] = cplx(a[2 * k], a[2 * k + 1]);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (std::abs(A[(size_t)i * n + j] - std::conj(A[(size_t)j * n + i])) >
+          1e-12 * (1.0 + std::abs(A[(size_t)i * n + j])))
+        return fail(OVL_EINVAL, "matrix is not Hermitian at (%d, %d)", i, j);
+  std::vector<double> wv;
+  if (!hermitian_eigh(n, A, wv, Q)) return fail(OVL_EDIVERGED, "QL iteration did not converge");
+  for (int i = 0; i < n; ++i) w[i] = wv[i];
+  for (size_t k = 0; k < Q.size(); ++k) {
+    q[2 * k] = Q[k].real();
+    q[2 * k + 1] = Q[k].imag();
+  }
+  return OVL_OK;
+}
 
 // Times one plain Clenshaw step of the problem set (stencil input `in`, own-site reads of `in`
 // as source and recurrence vector, output `out`: the memory streams of an odd-k step) in every

@@ -169,3 +169,38 @@ def test_two_row_reference_helper():
     w = complete_third_row(bad * 1.0)
     m = np.moveaxis(w[0].reshape(3, 3, -1), -1, 0)
     assert np.abs(m @ np.conj(np.swapaxes(m, 1, 2)) - np.eye(3)).max() < 1e-14
+
+
+@pytest.mark.parametrize("n,kind", [(1, "random"), (2, "random"), (7, "random"), (64, "random"),
+                                    (128, "random"), (40, "degenerate"), (16, "diagonal"),
+                                    (30, "real")])
+def test_hermitian_eigh_host(lib, n, kind):
+    """The eigen-solve's host Hermitian eigen-decomposition against LAPACK (NumPy): eigenvalues,
+    A Q = Q diag(w) and Q^+ Q = 1 to rounding, also for repeated eigenvalues and inputs that are
+    already diagonal or real."""
+    import numpy as np
+    rng = np.random.default_rng(n)
+    if kind == "diagonal":
+        a = np.diag(rng.standard_normal(n)).astype(np.complex128)
+    else:
+        x = rng.standard_normal((n, n)) + (0 if kind == "real" else 1j) * rng.standard_normal((n, n))
+        a = x + x.conj().T
+        if kind == "degenerate":   # eigenvalues 0, 1, 2 each with multiplicity > 1
+            q, _ = np.linalg.qr(x)
+            a = q @ np.diag(np.arange(n) % 3).astype(np.complex128) @ q.conj().T
+            a = 0.5 * (a + a.conj().T)
+    a = np.ascontiguousarray(a.astype(np.complex128))
+    w = np.zeros(n)
+    q = np.zeros((n, n), dtype=np.complex128)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.ovl_hermitian_eigh(n, a.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                  q.ctypes.data_as(dp)) == 0
+    scale = max(1.0, np.abs(a).max())
+    assert np.abs(w - np.linalg.eigvalsh(a)).max() < 1e-13 * scale * n
+    assert np.abs(a @ q - q * w[None, :]).max() < 1e-13 * scale * n
+    assert np.abs(q.conj().T @ q - np.eye(n)).max() < 1e-13 * n
+    bad = a.copy()
+    if n > 1:
+        bad[0, 1] += 1.0
+        assert lib.ovl_hermitian_eigh(n, bad.ctypes.data_as(dp), w.ctypes.data_as(dp),
+                                      q.ctypes.data_as(dp)) == -1

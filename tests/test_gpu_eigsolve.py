@@ -1,31 +1,86 @@
-"""GPU set-up eigen-solve (the low modes of K that Sec. 2 precomputes once per gauge field):
-eigenvalues against the oracle's dense LAPACK diagonalisation, residuals through the library's K."""
+"""The library's eigen-solve for the deflation basis (ovl_low_modes: the low modes of K that
+Sec. 2 precomputes once per gauge field): eigenvalues against the oracle's dense LAPACK
+diagonalisation (4^4) and its ARPACK Lanczos values (8^3x16, stored by
+tests/golden/make_low_modes_c2.py), residuals recomputed by the oracle's K on the returned
+vectors, orthonormality."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import latgen
+from oracle import wilson as ow
 from oracle.eigen import dense_eigs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+LMAX = 6.5
 
 
-def test_low_modes_match_dense_4x4x4x4():
+@pytest.fixture(scope="module")
+def ovl():
     if not torch.cuda.is_available():
         pytest.fail("no GPU visible")
-    import paper_1510_06897_amd as ovl
+    import paper_1510_06897_amd as m
+    m.load()
+    return m
+
+
+def oracle_residuals(u, lam, phi):
+    return np.array([np.linalg.norm(ow.kop(u, phi[i]) - lam[i] * phi[i]) for i in range(len(lam))])
+
+
+def test_low_modes_match_dense_4x4x4x4(ovl):
     from paper_1510_06897_amd.eigsolve import low_modes
     dims = (4, 4, 4, 4)
     u = latgen.smeared_field(dims, 5)
     lam_ref, _ = dense_eigs(u)
     g = ovl.GaugeField(torch.from_numpy(u).cuda(), "f64")
-    lam, phi, res, eps = low_modes(g, 8, 6.5, block=64, cut=1.0, degree=20, iters=30)
+    lam, phi, res, eps = low_modes(g, 8, LMAX, block=64, cut=1.0, degree=20, iters=30, strict=True)
     assert res.max() < 1e-10
     assert np.allclose(np.sort(np.abs(lam)), np.sort(np.abs(lam_ref[:8])), atol=1e-10)
-    assert abs(eps * 6.5 - abs(lam_ref[8])) < 1e-6
-    # residual recomputed through the library operator, and orthonormality
+    # the signed eigenvalues too: every returned value is one of the dense spectrum's
+    for x in lam:
+        assert np.abs(lam_ref - x).min() < 1e-10
+    assert abs(eps * LMAX - abs(lam_ref[8])) < 1e-6
+    p = phi.cpu().numpy()
+    assert oracle_residuals(u, lam, p).max() < 1e-9
+    gram = p.reshape(8, -1).conj() @ p.reshape(8, -1).T
+    assert np.abs(gram - np.eye(8)).max() < 1e-12
+    # the same vectors through the library's own K
     k = ovl.kernel_apply(g, phi)
     r = torch.linalg.vector_norm((k - torch.from_numpy(lam).cuda()[:, None, None, None, None, None, None] * phi).reshape(8, -1), dim=1)
     assert float(r.max()) < 1e-10
-    gram = phi.reshape(8, -1).conj() @ phi.reshape(8, -1).T
-    assert float((gram - torch.eye(8, device=gram.device)).abs().max()) < 1e-12
+
+
+def test_low_modes_8x8x8x16_against_arpack(ovl):
+    """The 12 deflated modes of the 8^3x16 overlap workload and the first undeflated |lambda|."""
+    from paper_1510_06897_amd.eigsolve import low_modes
+    ref = json.load(open(os.path.join(HERE, "golden", "low_modes_8x8x8x16.json")))
+    dims = tuple(ref["dims"])
+    u = latgen.smeared_field(dims, ref["gauge_seed"])
+    g = ovl.GaugeField(torch.from_numpy(u).cuda(), "f64")
+    # the smooth fields keep 48 near-degenerate doubler modes at |lambda| ~ 0.5: block 64
+    lam, phi, res, eps = low_modes(g, 12, LMAX, block=64, cut=1.0, strict=True)
+    lam_ref = np.array(ref["lambda"])
+    assert np.abs(np.sort(np.abs(lam)) - np.sort(np.abs(lam_ref[:12]))).max() < 1e-9
+    assert abs(eps * LMAX - abs(lam_ref[12])) < 1e-8
+    assert oracle_residuals(u, lam, phi.cpu().numpy()).max() < 1e-9
+
+
+def test_low_modes_validation(ovl):
+    from paper_1510_06897_amd.eigsolve import low_modes
+    dims = (2, 2, 2, 2)
+    u = latgen.random_su3_field(dims, 1)
+    g32 = ovl.GaugeField(torch.from_numpy(u).cuda(), "f32")
+    with pytest.raises(ValueError):
+        low_modes(g32, 2, LMAX)
+    g = ovl.GaugeField(torch.from_numpy(u).cuda(), "f64")
+    with pytest.raises(ovl.OvlError) as e:
+        low_modes(g, 4, LMAX, block=4)          # block must exceed n_ev
+    assert e.value.status == "OVL_EINVAL"
+    with pytest.raises(ovl.OvlError) as e:
+        low_modes(g, 2, LMAX, block=8, cut=7.0)  # cut above lmax
+    assert e.value.status == "OVL_EINVAL"
