@@ -201,6 +201,38 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G_dev, const void *chi, const 
 int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const void *chi,
                    const void *psi, int ckpt_stride, int spin_dt, void *stream);
 
+/* ---- stout smearing of the links (Sec. 2) and its chain rule (HMC, Sec. 1) ------------------- */
+
+/* The links entering K are smoothed by 3 steps of over-improved stout smearing with rho = 0.1,
+ * eps = -0.25 (Sec. 2).  One step replaces every link at once by U'_mu(x) = exp(M) U_mu(x), with
+ * M the traceless anti-Hermitian part of Omega = C_mu(x) U_mu(x)^+ (M = (Omega - Omega^+)/2 -
+ * tr(Omega - Omega^+)/6) and C_mu(x) the sum over the paths from x to x + mu that close a loop
+ * with the link: the 6 plaquette staples with weight rho (5 - 2 eps)/3 and the 18 staples of the
+ * 2 x 1 rectangles with weight -rho (1 - eps)/12 (the over-improved gauge action; eps = 1 gives
+ * plain stout smearing, eps = 0 the tree-level Symanzik weights).  exp(M) is evaluated in FP64
+ * (Taylor series after scaling to norm 1/2, then squaring).
+ *   U_in, U_out  caller-owned device arrays U[mu][a][b][T][Z][Y][X], complex double (the caller
+ *                layout of ovl_gauge_create); they must not overlap; U_in is unchanged.
+ *   steps        0 .. 64 (0 copies U_in).
+ * Allocates two link fields of work space for steps >= 2.  Asynchronous on `stream`.
+ * Errors: EINVAL (NULL, steps out of range), EDIMS, ENONFINITE (rho or eps), EALIAS, ENOMEM,
+ * EHIP. */
+int ovl_stout_smear(const int32_t dims[4], void *U_out, const void *U_in, double rho, double eps,
+                    int steps, void *stream);
+
+/* Chain rule through ovl_stout_smear: given G_smeared = dL/dRe U' + i dL/dIm U' of a real
+ * function L of the smeared links U' = stout^steps(U_thin) (for example the output of
+ * ovl_sign_force on a gauge handle made from U'), writes G_thin = dL/dRe U + i dL/dIm U of the
+ * thin links.  The forward levels are recomputed; each step backwards forms dL/dC_mu(x) per link
+ * (through the Frechet derivative of exp, FP64 Taylor series) and then gathers, for every link,
+ * the contributions of all staples that contain it (no atomics: deterministic).
+ *   G_thin, G_smeared, U_thin  caller-owned device arrays in the layout above, complex double,
+ *                pairwise non-overlapping; G_smeared and U_thin are unchanged.
+ * Allocates steps + 3 link fields of work space.  Asynchronous on `stream`.  Errors as
+ * ovl_stout_smear. */
+int ovl_stout_backward(const int32_t dims[4], void *G_thin, const void *G_smeared,
+                       const void *U_thin, double rho, double eps, int steps, void *stream);
+
 /* ---- diagnostics of the approximation -------------------------------------------------------- */
 
 /* The exact sign function squares to one, which gives the overlap operator of Sec. 2 (eq. 1) its

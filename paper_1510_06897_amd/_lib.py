@@ -59,6 +59,8 @@ SIGNATURES = {
     "ovl_timing_enable": (_i, [_i]),
     "ovl_timing_read": (_i, [_i, _dp, ctypes.POINTER(ctypes.c_int64)]),
     "ovl_stream_probe": (_i, [_i, _vp, _vp, ctypes.c_int64, _vp]),
+    "ovl_stout_smear": (_i, [_i32x4, _vp, _vp, _d, _d, _i, _vp]),
+    "ovl_stout_backward": (_i, [_i32x4, _vp, _vp, _vp, _d, _d, _i, _vp]),
     "ovl_version": (ctypes.c_char_p, []),
 }
 

@@ -447,3 +447,59 @@ def stream_probe(kind: int, dst, src, nbytes: int):
     """One plain device-memory stream (bandwidth ceiling): read, copy or three-to-one, on the
     current stream (see ovl_stream_probe)."""
     call("ovl_stream_probe", int(kind), _ptr(dst), _ptr(src), int(nbytes), _stream())
+
+
+# ------------------------------------------------------------------------------------------------
+# stout smearing of the links (Sec. 2: 3 steps of over-improved stout smearing, rho = 0.1,
+# eps = -0.25) and its chain rule (the HMC force on the thin links, Sec. 1)
+def _check_links64(u, name="U"):
+    if not u.is_cuda or u.dim() != 7 or tuple(u.shape[:3]) != (4, 3, 3):
+        raise ValueError(f"{name} must be a CUDA tensor of shape (4, 3, 3, T, Z, Y, X)")
+    if u.dtype != torch.complex128 or not u.is_contiguous():
+        raise ValueError(f"{name} must be contiguous complex128")
+    return (int(u.shape[6]), int(u.shape[5]), int(u.shape[4]), int(u.shape[3]))
+
+
+def stout_smear(u, rho: float = 0.1, eps: float = -0.25, steps: int = 3, out=None):
+    """Links after `steps` stout steps with the over-improved staples of weight eps (eps = 1:
+    plain stout smearing); FP64 in and out."""
+    dims = _check_links64(u)
+    out = torch.empty_like(u) if out is None else out
+    _check_links64(out, "out")
+    call("ovl_stout_smear", _dims_arr(dims), _ptr(out), _ptr(u), float(rho), float(eps),
+         int(steps), _stream())
+    return out
+
+
+def stout_backward(u_thin, g_smeared, rho: float = 0.1, eps: float = -0.25, steps: int = 3,
+                   out=None):
+    """dL/dRe U + i dL/dIm U of the thin links from the same derivative of the smeared links."""
+    dims = _check_links64(u_thin, "U_thin")
+    if _check_links64(g_smeared, "G_smeared") != dims:
+        raise ValueError("G_smeared and U_thin differ in shape")
+    out = torch.empty_like(u_thin) if out is None else out
+    _check_links64(out, "out")
+    call("ovl_stout_backward", _dims_arr(dims), _ptr(out), _ptr(g_smeared), _ptr(u_thin),
+         float(rho), float(eps), int(steps), _stream())
+    return out
+
+
+class StoutFunction(torch.autograd.Function):
+    """U_smeared = stout(U); backward carries dL/dU_smeared to the thin links (torch's complex
+    gradient convention dL/dRe + i dL/dIm).  Composes with SignFunction for the force of
+    Re<chi, p(X[stout(U)]) psi> on U."""
+
+    @staticmethod
+    def forward(ctx, u, rho: float = 0.1, eps: float = -0.25, steps: int = 3):
+        u = u.detach().contiguous()
+        ctx.save_for_backward(u)
+        ctx.par = (float(rho), float(eps), int(steps))
+        return stout_smear(u, *ctx.par)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (u,) = ctx.saved_tensors
+        g = grad.contiguous()
+        if g.dtype != torch.complex128:
+            g = g.to(torch.complex128)
+        return stout_backward(u, g, *ctx.par), None, None, None

@@ -19,6 +19,7 @@
 
 #include "../../include/ovl.h"
 #include "kernels.hpp"
+#include "stout.hpp"
 
 namespace ovl {
 bool cheb_sign_coeffs(int degree, double eps, std::vector<double> &alpha);
@@ -2517,6 +2518,116 @@ int ovl_timing_read(int kind, double *total_ms, int64_t *launches) {
   *launches = n;
   *total_ms = tot;
   g_timing_events.swap(keep);
+  return OVL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Stout smearing of the links (Sec. 2: 3 steps of over-improved stout smearing, rho = 0.1,
+// eps = -0.25) and its chain rule for the HMC force (Sec. 1).  FP64 links and derivatives in the
+// caller layout; the staple weights are rho (5 - 2 eps)/3 (plaquettes) and -rho (1 - eps)/12
+// (rectangles).
+namespace {
+
+bool spans_overlap(const void *a, const void *b, size_t n) {
+  const char *x = (const char *)a, *y = (const char *)b;
+  return x < y + n && y < x + n;
+}
+
+int check_stout(const int32_t dims[4], double rho, double eps, int steps, Geom &geo) {
+  int rc = check_dims(dims, geo);
+  if (rc) return rc;
+  if (!std::isfinite(rho) || !std::isfinite(eps)) return fail(OVL_ENONFINITE, "non-finite rho or eps");
+  if (steps < 0 || steps > 64) return fail(OVL_EINVAL, "steps = %d out of range [0, 64]", steps);
+  return OVL_OK;
+}
+
+void stout_weights(double rho, double eps, double &wp, double &wr) {
+  wp = rho * (5.0 - 2.0 * eps) / 3.0;
+  wr = -rho * (1.0 - eps) / 12.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ovl_stout_smear(const int32_t dims[4], void *U_out, const void *U_in, double rho, double eps,
+                    int steps, void *stream) {
+  g_err[0] = 0;
+  if (!U_out || !U_in) return fail(OVL_EINVAL, "NULL argument");
+  Geom geo;
+  int rc = check_stout(dims, rho, eps, steps, geo);
+  if (rc) return rc;
+  const size_t bytes = (size_t)36 * geo.V * sizeof(double2);
+  if (spans_overlap(U_out, U_in, bytes)) return fail(OVL_EALIAS, "U_out overlaps U_in");
+  hipStream_t s = as_stream(stream);
+  if (steps == 0) {
+    HIP_TRY(hipMemcpyAsync(U_out, U_in, bytes, hipMemcpyDeviceToDevice, s));
+    return OVL_OK;
+  }
+  double wp, wr;
+  stout_weights(rho, eps, wp, wr);
+  // levels ping-pong through two work fields; the last step writes U_out
+  Scratch sc;
+  const size_t fb = (bytes + 255) / 256 * 256;
+  if (steps > 1 && (rc = scratch_alloc(sc, 2 * fb, s))) return rc;
+  const dim3 grid((unsigned)((geo.V + 255) / 256), 4);
+  const double2 *cur = (const double2 *)U_in;
+  for (int k = 0; k < steps; ++k) {
+    double2 *dst = k == steps - 1 ? (double2 *)U_out : (double2 *)((char *)sc.p + (k % 2) * fb);
+    stout_step_kernel<<<grid, 256, 0, s>>>(cur, dst, wp, wr, geo);
+    HIP_TRY(hipGetLastError());
+    cur = dst;
+  }
+  return OVL_OK;
+}
+
+int ovl_stout_backward(const int32_t dims[4], void *G_thin, const void *G_smeared,
+                       const void *U_thin, double rho, double eps, int steps, void *stream) {
+  g_err[0] = 0;
+  if (!G_thin || !G_smeared || !U_thin) return fail(OVL_EINVAL, "NULL argument");
+  Geom geo;
+  int rc = check_stout(dims, rho, eps, steps, geo);
+  if (rc) return rc;
+  const size_t bytes = (size_t)36 * geo.V * sizeof(double2);
+  if (spans_overlap(G_thin, G_smeared, bytes) || spans_overlap(G_thin, U_thin, bytes) ||
+      spans_overlap(G_smeared, U_thin, bytes))
+    return fail(OVL_EALIAS, "G_thin, G_smeared and U_thin must not overlap");
+  hipStream_t s = as_stream(stream);
+  if (steps == 0) {
+    HIP_TRY(hipMemcpyAsync(G_thin, G_smeared, bytes, hipMemcpyDeviceToDevice, s));
+    return OVL_OK;
+  }
+  double wp, wr;
+  stout_weights(rho, eps, wp, wr);
+  // work fields: levels 1 .. steps-1 of the forward smearing, Gamma, the direct part and two
+  // derivative fields between the steps
+  const size_t fb = (bytes + 255) / 256 * 256;
+  const int nlev = steps - 1;
+  const int nder = steps >= 3 ? 2 : (steps == 2 ? 1 : 0);
+  Scratch sc;
+  if ((rc = scratch_alloc(sc, (size_t)(nlev + 2 + nder) * fb, s))) return rc;
+  char *base = (char *)sc.p;
+  auto field = [&](int i) { return (double2 *)(base + (size_t)i * fb); };
+  double2 *gam = field(nlev), *dir = field(nlev + 1);
+  const dim3 grid((unsigned)((geo.V + 255) / 256), 4);
+  std::vector<const double2 *> lev(steps);
+  lev[0] = (const double2 *)U_thin;
+  for (int k = 1; k < steps; ++k) {
+    stout_step_kernel<<<grid, 256, 0, s>>>(lev[k - 1], field(k - 1), wp, wr, geo);
+    HIP_TRY(hipGetLastError());
+    lev[k] = field(k - 1);
+  }
+  const double2 *gin = (const double2 *)G_smeared;
+  for (int k = steps - 1; k >= 0; --k) {
+    double2 *gout = k == 0 ? (double2 *)G_thin : field(nlev + 2 + (nder == 2 ? 1 - (k & 1) : 0));
+    stout_back_local_kernel<<<grid, 256, 0, s>>>(lev[k], gin, gam, dir, wp, wr, geo);
+    HIP_TRY(hipGetLastError());
+    stout_back_gather_kernel<<<grid, 256, 0, s>>>(lev[k], gam, dir, gout, wp, wr, geo);
+    HIP_TRY(hipGetLastError());
+    gin = gout;
+  }
   return OVL_OK;
 }
 

@@ -1,0 +1,405 @@
+// Stout smearing of the gauge links on the device and its chain-rule derivative (FP64).
+//
+// The links entering K are smoothed by three steps of over-improved stout smearing with
+// rho = 0.1 and eps = -0.25 (Sec. 2).  One step replaces every link at once by
+//   U'_mu(x) = exp(M) U_mu(x),   M = TA(Omega) = (Omega - Omega^+)/2 - tr(Omega - Omega^+)/6,
+//   Omega = C_mu(x) U_mu(x)^+,
+// where C_mu(x) sums the paths from x to x + mu that close a loop with the link: the three-link
+// plaquette staples with weight rho c_p and the five-link staples of the 2 x 1 rectangles with
+// weight rho c_r, c_p = (5 - 2 eps)/3, c_r = -(1 - eps)/12 (the over-improved gauge action; eps = 1
+// leaves the plaquette alone: plain stout smearing).
+//
+// Links are read and written in the caller layout U[mu][a][b][site] (complex double), so one
+// wave reads one matrix element of 64 consecutive sites per load.  A thread owns one link
+// (site, mu); the workgroup's 256 threads share mu, so the path loops below are uniform over a
+// wave.  exp(M) is a Taylor series after scaling M to norm <= 1/2, followed by squaring; the
+// derivative of exp comes from the same series for the Frechet derivative (the directional
+// derivative of every power, carried along the squarings).
+#pragma once
+
+#include "common.hpp"
+
+namespace ovl {
+
+// ---------------------------------------------------------------------------------------------
+// 3 x 3 complex FP64 matrices in registers
+struct M3 {
+  cx<double> e[3][3];
+};
+
+__device__ __forceinline__ M3 m3_zero() {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.e[i][j] = mk<double>(0.0, 0.0);
+  return r;
+}
+__device__ __forceinline__ M3 m3_unit() {
+  M3 r = m3_zero();
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.e[i][i] = mk<double>(1.0, 0.0);
+  return r;
+}
+// A B
+__device__ __forceinline__ M3 m3_mul(const M3 &a, const M3 &b) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<double> s = mk<double>(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = cmadd(s, a.e[i][k], b.e[k][j]);
+      r.e[i][j] = s;
+    }
+  return r;
+}
+// A^+ B
+__device__ __forceinline__ M3 m3_dmul(const M3 &a, const M3 &b) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<double> s = mk<double>(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = cjmadd(s, a.e[k][i], b.e[k][j]);
+      r.e[i][j] = s;
+    }
+  return r;
+}
+// A B^+
+__device__ __forceinline__ M3 m3_muld(const M3 &a, const M3 &b) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cx<double> s = mk<double>(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = cjmadd(s, b.e[j][k], a.e[i][k]);
+      r.e[i][j] = s;
+    }
+  return r;
+}
+__device__ __forceinline__ M3 m3_dag(const M3 &a) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.e[i][j] = mk<double>(a.e[j][i].re, -a.e[j][i].im);
+  return r;
+}
+// a + s b
+__device__ __forceinline__ M3 m3_axpy(const M3 &a, double s, const M3 &b) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      r.e[i][j] = mk<double>(fma(s, b.e[i][j].re, a.e[i][j].re), fma(s, b.e[i][j].im, a.e[i][j].im));
+  return r;
+}
+__device__ __forceinline__ M3 m3_scale(const M3 &a, double s) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.e[i][j] = scale(a.e[i][j], s);
+  return r;
+}
+__device__ __forceinline__ double m3_frob(const M3 &a) {
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s += a.e[i][j].re * a.e[i][j].re + a.e[i][j].im * a.e[i][j].im;
+  return sqrt(s);
+}
+
+// element (a, b) of link `dir` at `site`: U[dir][a][b][site]
+__device__ __forceinline__ M3 load_m3(const double2 *__restrict__ U, int dir, int site, int V) {
+  M3 r;
+  const double2 *p = U + (int64_t)dir * 9 * V + site;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const double2 v = p[(int64_t)(3 * i + j) * V];
+      r.e[i][j] = mk<double>(v.x, v.y);
+    }
+  return r;
+}
+__device__ __forceinline__ void store_m3(double2 *__restrict__ U, int dir, int site, int V,
+                                         const M3 &m) {
+  double2 *p = U + (int64_t)dir * 9 * V + site;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) p[(int64_t)(3 * i + j) * V] = make_double2(m.e[i][j].re, m.e[i][j].im);
+}
+
+// ---------------------------------------------------------------------------------------------
+// exp(A) and the Frechet derivative L(A, F) = d/dt exp(A + t F) at t = 0.
+//   Scale: X = A / 2^s with ||X||_F <= 1/2.  Series: T_0 = 1, T_{k+1} = X T_k / (k + 1) gives
+//   exp(X) = sum T_k; the derivative of X^k along F obeys D_{k+1} = F X^k + X D_k, so with
+//   S_k = D_k / k!:  S_1 = F, S_{k+1} = (F T_k + X S_k) / (k + 1) and L(X, F) = sum S_k.
+//   Square: exp(2Y) = exp(Y)^2 and L(2Y, 2G) = L(Y, G) exp(Y) + exp(Y) L(Y, G).
+// 18 terms leave a remainder below 0.5^19 / 19! (1e-23) of the scaled series.
+constexpr int kExpTerms = 18;
+
+__device__ __forceinline__ int exp_scaling(const M3 &a) {
+  double n = m3_frob(a);
+  int s = 0;
+  while (n > 0.5 && s < 40) {
+    n *= 0.5;
+    ++s;
+  }
+  return s;
+}
+
+__device__ inline M3 m3_exp(const M3 &a) {
+  const int s = exp_scaling(a);
+  const M3 x = m3_scale(a, ldexp(1.0, -s));
+  M3 e = m3_unit(), t = m3_unit();
+  for (int k = 1; k <= kExpTerms; ++k) {
+    t = m3_scale(m3_mul(x, t), 1.0 / k);
+    e = m3_axpy(e, 1.0, t);
+  }
+  for (int i = 0; i < s; ++i) e = m3_mul(e, e);
+  return e;
+}
+
+// exp(A) into *e and L(A, F) into *l
+__device__ inline void m3_exp_frechet(const M3 &a, const M3 &f, M3 *e_out, M3 *l_out) {
+  const int s = exp_scaling(a);
+  const double sc = ldexp(1.0, -s);
+  const M3 x = m3_scale(a, sc), g = m3_scale(f, sc);
+  M3 e = m3_unit(), t = m3_unit();
+  M3 l = m3_zero(), d = m3_zero();
+  for (int k = 1; k <= kExpTerms; ++k) {
+    // S_k = (F T_{k-1} + X S_{k-1}) / k, T_k = X T_{k-1} / k  (S_0 = 0, T_0 = 1)
+    const M3 dn = m3_scale(m3_axpy(m3_mul(g, t), 1.0, m3_mul(x, d)), 1.0 / k);
+    t = m3_scale(m3_mul(x, t), 1.0 / k);
+    d = dn;
+    e = m3_axpy(e, 1.0, t);
+    l = m3_axpy(l, 1.0, d);
+  }
+  for (int i = 0; i < s; ++i) {
+    l = m3_axpy(m3_mul(l, e), 1.0, m3_mul(e, l));
+    e = m3_mul(e, e);
+  }
+  *e_out = e;
+  *l_out = l;
+}
+
+// traceless anti-Hermitian part: (W - W^+)/2 - tr(W - W^+)/6
+__device__ __forceinline__ M3 m3_ta(const M3 &w) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      r.e[i][j] = mk<double>(0.5 * (w.e[i][j].re - w.e[j][i].re), 0.5 * (w.e[i][j].im + w.e[j][i].im));
+  const double tr_im = (r.e[0][0].im + r.e[1][1].im + r.e[2][2].im) / 3.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.e[i][i].im -= tr_im;
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Staple paths.  For a link along mu, a plane mu-nu (nu != mu) and an orientation s = +1 or -1 of
+// nu, four paths lead from x to x + mu:
+//   shape 0  plaquette            (nu,s)  (mu,+)  (nu,-s)
+//   shape 1  2 x 1, link first    (nu,s)  (mu,+)  (mu,+)  (nu,-s) (mu,-)
+//   shape 2  2 x 1, link second   (mu,-)  (nu,s)  (mu,+)  (mu,+)  (nu,-s)
+//   shape 3  1 x 2                (nu,s)  (nu,s)  (mu,+)  (nu,-s) (nu,-s)
+// A step (d,+) from position z takes the factor U_d(x + z) and moves to z + e_d; a step (d,-)
+// moves to z - e_d and takes U_d(x + z - e_d)^+.  Together with the link these are the 6
+// plaquettes and 18 rectangles that contain it.
+__device__ __forceinline__ int path_len(int shape) { return shape == 0 ? 3 : 5; }
+
+__device__ __forceinline__ void path_step(int mu, int nu, int s, int shape, int k, int &dir,
+                                          int &sgn) {
+  // (direction selector, sign) per position: 0 = mu, 1 = nu; sign in units of s for nu
+  int sel, sg;
+  switch (shape) {
+    case 0: sel = (k == 1) ? 0 : 1; sg = (k == 0) ? 1 : (k == 1 ? 1 : -1); break;
+    case 1: sel = (k == 1 || k == 2 || k == 4) ? 0 : 1; sg = (k == 3 || k == 4) ? -1 : 1; break;
+    case 2: sel = (k == 1 || k == 4) ? 1 : 0; sg = (k == 0 || k == 4) ? -1 : 1; break;
+    default: sel = (k == 2) ? 0 : 1; sg = (k >= 3) ? -1 : 1; break;
+  }
+  dir = sel == 0 ? mu : nu;
+  sgn = sel == 0 ? sg : sg * s;
+}
+
+struct SiteCoord {
+  int c[4];
+};
+__device__ __forceinline__ SiteCoord site_coord(int site, const Geom &g) {
+  SiteCoord r;
+  int v = site;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    r.c[d] = v % g.L[d];
+    v /= g.L[d];
+  }
+  return r;
+}
+// site index of x + off (periodic)
+__device__ __forceinline__ int site_at(const SiteCoord &x, const int off[4], const Geom &g) {
+  int idx = 0;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    int v = (x.c[d] + off[d]) % g.L[d];
+    if (v < 0) v += g.L[d];
+    idx += v * g.stride[d];
+  }
+  return idx;
+}
+// factor of path step (dir, sgn) taken at position `pos` (updated to the position after the step)
+__device__ __forceinline__ M3 path_factor(const double2 *__restrict__ U, const SiteCoord &x,
+                                          int pos[4], int dir, int sgn, const Geom &g) {
+  if (sgn > 0) {
+    const M3 f = load_m3(U, dir, site_at(x, pos, g), g.V);
+    pos[dir] += 1;
+    return f;
+  }
+  pos[dir] -= 1;
+  return m3_dag(load_m3(U, dir, site_at(x, pos, g), g.V));
+}
+
+// C_mu(x) = sum over the paths of their products, plaquette paths weighted wp, rectangles wr
+__device__ inline M3 staple_sum(const double2 *__restrict__ U, const SiteCoord &x, int mu, double wp,
+                                double wr, const Geom &g) {
+  M3 c = m3_zero();
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == mu) continue;
+    for (int s = 1; s >= -1; s -= 2)
+      for (int shape = 0; shape < 4; ++shape) {
+        const double w = shape == 0 ? wp : wr;
+        if (w == 0.0) continue;
+        int pos[4] = {0, 0, 0, 0};
+        int dir, sgn;
+        path_step(mu, nu, s, shape, 0, dir, sgn);
+        M3 p = path_factor(U, x, pos, dir, sgn, g);
+        for (int k = 1; k < path_len(shape); ++k) {
+          path_step(mu, nu, s, shape, k, dir, sgn);
+          p = m3_mul(p, path_factor(U, x, pos, dir, sgn, g));
+        }
+        c = m3_axpy(c, w, p);
+      }
+  }
+  return c;
+}
+
+// One smearing step: out_mu(x) = exp(TA(C_mu(x) U_mu(x)^+)) U_mu(x).  Grid (ceil(V / 256), 4).
+__global__ void __launch_bounds__(256)
+    stout_step_kernel(const double2 *__restrict__ U, double2 *__restrict__ out, double wp, double wr,
+                      Geom g) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int mu = blockIdx.y;
+  if (site >= g.V) return;
+  const SiteCoord x = site_coord(site, g);
+  const M3 c = staple_sum(U, x, mu, wp, wr, g);
+  const M3 u = load_m3(U, mu, site, g.V);
+  const M3 e = m3_exp(m3_ta(m3_muld(c, u)));
+  store_m3(out, mu, site, g.V, m3_mul(e, u));
+}
+
+// Backward of one step, the part local to each link.  With G' = dL/dRe U' + i dL/dIm U' of the
+// step's output (same convention throughout):
+//   dL/dE = G' U^+,  dL/dM = L(M^+, dL/dE)  (the adjoint of the Frechet derivative of exp at M),
+//   dL/dOmega = (g - g^+)/2 - (i/3) Im tr(g) for g = dL/dM  (M = TA(Omega)),
+//   Gamma = dL/dC = dL/dOmega U,   direct = E^+ G' + (dL/dOmega)^+ C.
+// Writes Gamma and the direct part of dL/dU.
+__global__ void __launch_bounds__(256)
+    stout_back_local_kernel(const double2 *__restrict__ U, const double2 *__restrict__ gout,
+                            double2 *__restrict__ gamma, double2 *__restrict__ direct, double wp,
+                            double wr, Geom g) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int mu = blockIdx.y;
+  if (site >= g.V) return;
+  const SiteCoord x = site_coord(site, g);
+  const M3 c = staple_sum(U, x, mu, wp, wr, g);
+  const M3 u = load_m3(U, mu, site, g.V);
+  const M3 m = m3_ta(m3_muld(c, u));
+  const M3 gp = load_m3(gout, mu, site, g.V);
+  // exp(M^+) = exp(-M) = E^+ (M is anti-Hermitian), and dL/dM = L(M^+, G' U^+)
+  M3 ed, gm;
+  m3_exp_frechet(m3_scale(m, -1.0), m3_muld(gp, u), &ed, &gm);
+  const M3 go = m3_ta(gm);
+  store_m3(gamma, mu, site, g.V, m3_mul(go, u));
+  store_m3(direct, mu, site, g.V, m3_axpy(m3_mul(ed, gp), 1.0, m3_dmul(go, c)));
+}
+
+// Backward of one step, the staple part, gathered per link (site y, direction d): every path of
+// every link (x, nu') whose step k is link d at y contributes  w A^+ Gamma_nu'(x) B^+  (its
+// adjoint when the step runs backwards), A and B the products of the steps before and after k.
+// out = direct + that sum: dL/dU of the step's input.  Grid (ceil(V / 256), 4).
+__global__ void __launch_bounds__(256)
+    stout_back_gather_kernel(const double2 *__restrict__ U, const double2 *__restrict__ gamma,
+                             const double2 *__restrict__ direct, double2 *__restrict__ out,
+                             double wp, double wr, Geom g) {
+  const int site = blockIdx.x * 256 + threadIdx.x;
+  const int d = blockIdx.y;
+  if (site >= g.V) return;
+  const SiteCoord y = site_coord(site, g);
+  M3 acc = load_m3(direct, d, site, g.V);
+  for (int mu = 0; mu < 4; ++mu)
+    for (int nu = 0; nu < 4; ++nu) {
+      if (nu == mu) continue;
+      for (int s = 1; s >= -1; s -= 2)
+        for (int shape = 0; shape < 4; ++shape) {
+          const double w = shape == 0 ? wp : wr;
+          if (w == 0.0) continue;
+          const int len = path_len(shape);
+          // positions of the steps relative to the path start
+          int zpos[4] = {0, 0, 0, 0};
+          for (int k = 0; k < len; ++k) {
+            int dir, sgn;
+            path_step(mu, nu, s, shape, k, dir, sgn);
+            // link of step k: U_dir(x + zpos) forwards, U_dir(x + zpos - e_dir) backwards
+            int lpos[4] = {zpos[0], zpos[1], zpos[2], zpos[3]};
+            if (sgn < 0) lpos[dir] -= 1;
+            if (dir == d) {
+              // the path start x = y - lpos
+              int xo[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) xo[q] = -lpos[q];
+              SiteCoord x;
+              const int xs = site_at(y, xo, g);
+              x = site_coord(xs, g);
+              int pos[4] = {0, 0, 0, 0};
+              M3 a = m3_unit();
+              for (int j = 0; j < k; ++j) {
+                int dj, sj;
+                path_step(mu, nu, s, shape, j, dj, sj);
+                a = m3_mul(a, path_factor(U, x, pos, dj, sj, g));
+              }
+              // skip step k itself
+              {
+                int dj, sj;
+                path_step(mu, nu, s, shape, k, dj, sj);
+                pos[dj] += sj;
+              }
+              M3 b = m3_unit();
+              for (int j = k + 1; j < len; ++j) {
+                int dj, sj;
+                path_step(mu, nu, s, shape, j, dj, sj);
+                b = m3_mul(b, path_factor(U, x, pos, dj, sj, g));
+              }
+              const M3 gm = load_m3(gamma, mu, xs, g.V);
+              M3 t = m3_muld(m3_dmul(a, gm), b);  // A^+ Gamma B^+
+              if (sgn < 0) t = m3_dag(t);
+              acc = m3_axpy(acc, w, t);
+            }
+            zpos[dir] += sgn;
+          }
+        }
+    }
+  store_m3(out, d, site, g.V, acc);
+}
+
+}  // namespace ovl

@@ -204,3 +204,24 @@ def test_hermitian_eigh_host(lib, n, kind):
         bad[0, 1] += 1.0
         assert lib.ovl_hermitian_eigh(n, bad.ctypes.data_as(dp), w.ctypes.data_as(dp),
                                       q.ctypes.data_as(dp)) == -1
+
+
+def test_stout_validation_before_hip(lib):
+    """ovl_stout_smear / ovl_stout_backward reject bad arguments on the host (fake device
+    addresses: nothing reaches the GPU)."""
+    dims = (ctypes.c_int32 * 4)(4, 4, 4, 4)
+    fb = 36 * 256 * 16                                       # one FP64 link field of 4^4
+    a, b, c = ctypes.c_void_p(1 << 40), ctypes.c_void_p((1 << 40) + 2 * fb), ctypes.c_void_p((1 << 40) + 4 * fb)
+    assert lib.ovl_stout_smear(dims, None, a, 0.1, -0.25, 3, None) == -1
+    assert lib.ovl_stout_smear(dims, b, a, 0.1, -0.25, 65, None) == -1
+    assert lib.ovl_stout_smear(dims, b, a, 0.1, -0.25, -1, None) == -1
+    assert lib.ovl_stout_smear(dims, b, a, float("inf"), -0.25, 3, None) == -7
+    assert lib.ovl_stout_smear(dims, b, a, 0.1, float("nan"), 3, None) == -7
+    assert lib.ovl_stout_smear(dims, ctypes.c_void_p((1 << 40) + fb // 2), a, 0.1, -0.25, 3, None) == -4
+    bad = (ctypes.c_int32 * 4)(4, 0, 4, 4)
+    assert lib.ovl_stout_smear(bad, b, a, 0.1, -0.25, 3, None) == -2
+    assert lib.ovl_stout_backward(dims, c, b, None, 0.1, -0.25, 3, None) == -1
+    assert lib.ovl_stout_backward(dims, c, b, c, 0.1, -0.25, 3, None) == -4
+    assert lib.ovl_stout_backward(dims, c, c, a, 0.1, -0.25, 3, None) == -4
+    assert lib.ovl_stout_backward(dims, c, b, a, 0.1, -0.25, 99, None) == -1
+    assert b"steps" in lib.ovl_last_error()
