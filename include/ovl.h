@@ -157,6 +157,22 @@ int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, voi
 int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
                       int dagger, void *out, const void *in, int nrhs, int spin_dt, void *stream);
 
+/* ovl_overlap_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments, same kernels
+ * and launch configuration, same results.  Its work space (one recurrence vector, norm and
+ * projection partials and deflation coefficients: about nrhs * 12 V * sizeof(element) bytes plus
+ * a few percent) lives in one 64 MiB array of static device memory that every GPU the library
+ * runs on holds until the process ends; its address is looked up once per device.  The call
+ * makes no hipMalloc, hipFree or other allocation (and no step graph).  Every word of the work
+ * space that the call reads it has written before in the same call, so nothing needs clearing.
+ * All calls on one GPU share the array: calls that overlap in time on one GPU (other streams,
+ * other threads) race on it.  Errors: as ovl_overlap_apply, plus EINVAL when the evaluation needs
+ * more than 64 MiB of work space (for example FP64 single right-hand sides above about 340K
+ * sites). */
+int ovl_overlap_apply_noalloc(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                              int dagger, void *out, const void *in, int nrhs, int spin_dt,
+                              void *stream);
+
 /* Batched form of ovl_sign_apply (no deflation; Sec. 2, eq. 3): up to 16 lattice problems --
  * each its own gauge field, volume and right-hand-side count -- evaluated with one polynomial in
  * one kernel launch per K application, so small volumes fill the GPU together and the
@@ -299,13 +315,47 @@ int ovl_hermitian_eigh(int n, const double *a, double *w, double *q);
  *          overlap applications);
  *   iters_out, resid_out (nullable) receive the inner iterations used and the final relative
  *          residual.
- * Synchronises the stream at every inner iteration (the CG scalars are formed on the host);
- * allocates 2 FP64 and 6 inner-precision vectors of work space.  Errors: EINVAL, EDIMS, EDTYPE,
+ * The CG coefficients stay on the device (FP64 inner products feed the vector updates
+ * directly); the host reads ||r||^2 two iterations behind the stream to decide when to stop, so
+ * an inner CG may run up to two iterations past its tolerance.  Synchronises the stream once
+ * per outer pass; allocates 2 FP64 and 6 inner-precision vectors of work space.  Errors: EINVAL, EDIMS, EDTYPE,
  * EALIAS, ENONFINITE, ENOMEM, EHIP; EDIVERGED if the residual target is not reached within
  * max_iter (x then holds the last iterate) or CG loses positivity. */
 int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
                       void *x, const void *b, const ovl_gauge *g_in, const ovl_defl *d_in,
                       double tol, int max_iter, int *iters_out, double *resid_out, void *stream);
+
+/* Solve D[mu] x = b for one FP64 vector by GMRESR with relaxed nested sign functions, the
+ * paper's outer solver form (Sec. 2: a recursive GMRES outer method around a low-accuracy inner
+ * inversion whose bulk needs only a low-accuracy sign function; Sec. 3: overlap inversions to a
+ * relative accuracy of 1e-13 in mixed precision).  Outer step k: z_k ~ D^-1 r_k from conjugate
+ * gradients on the normal equations in the precision of (g_in, d_in) (FP32 spinors with FP32 or
+ * BF16 links; FP64 with (g, d) when g_in is NULL), stopped at relative normal-equation residual
+ * inner_tol, with the polynomial of p truncated to the lowest degree whose dropped coefficients
+ * sum to at most inner_poly_tol (|T_m| <= 1 bounds the truncation error; 0 keeps p); then
+ * c_k = D z_k in FP64, orthogonalised against c_0 .. c_{k-1} by classical Gram-Schmidt applied
+ * twice (z_k follows with the same coefficients), normalised, and x += <c_k, r> z_k,
+ * r -= <c_k, r> c_k.  relax != 0: the FP64 product of step k uses p truncated at tail
+ * 0.1 tol ||b|| / ||r_k|| (a coarser polynomial as the residual falls; the inexact products
+ * perturb the final residual by about tol/10).  At the end the residual b - D x is recomputed
+ * with the full polynomial; if it misses tol, GMRESR restarts from x without relaxation (at most
+ * three cycles).  All Krylov coefficients stay on the device; the host reads ||r|| once per outer
+ * step and two iterations behind the stream inside the inner CG.
+ *   g, p, d, mu, x, b, g_in, d_in  as ovl_overlap_solve (x is overwritten, starts from 0);
+ *   tol            target ||b - D x|| / ||b|| with the full polynomial (> 0);
+ *   inner_tol      0 < inner_tol < 1;  inner_poly_tol >= 0;
+ *   max_outer      1 .. 1024 directions per cycle (two FP64 vectors each are kept);
+ *   max_inner      bound on the total inner CG iterations;
+ *   outer_out, inner_out, resid_out (nullable): outer steps and inner iterations used, the final
+ *                  relative residual with the full polynomial.
+ * Allocates 2 + 2 max_outer FP64 and 6 inner-precision vectors of work space; synchronises the
+ * stream.  Errors: as ovl_overlap_solve; EDIVERGED when tol is not reached within the bounds or a
+ * direction is numerically dependent on the previous ones (x then holds the last iterate). */
+int ovl_overlap_solve_gmresr(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                             void *x, const void *b, const ovl_gauge *g_in, const ovl_defl *d_in,
+                             double tol, double inner_tol, double inner_poly_tol, int relax,
+                             int max_outer, int max_inner, int *outer_out, int *inner_out,
+                             double *resid_out, void *stream);
 
 /* ---- launch tuning ------------------------------------------------------------------------ */
 

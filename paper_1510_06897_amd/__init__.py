@@ -9,6 +9,6 @@ from .api import (  # noqa: F401
     M_W, Deflation, GaugeField, Polynomial, SignFunction, autotune, autotune_load,
     batch_launch_config, batch_sign_apply, cheb_sign_coeffs, defl_correct, defl_project, graph_enable, kernel_apply,
     kernel_axpby,
-    launch_config, overlap_apply, overlap_solve, sign_apply, sign_force, sign_residual, stout_backward, stout_smear, StoutFunction, stream_probe, timing_enable,
+    launch_config, overlap_apply, overlap_solve, overlap_solve_gmresr, sign_apply, sign_force, sign_residual, stout_backward, stout_smear, StoutFunction, stream_probe, timing_enable,
     timing_read, wilson_apply, wilson_link_vjp,
 )

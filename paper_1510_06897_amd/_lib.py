@@ -38,6 +38,7 @@ SIGNATURES = {
     "ovl_kernel_axpby": (_i, [_vp, _vp, _vp, _d, _vp, _d, _vp, _d, _i, _i, _d, _vp]),
     "ovl_sign_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_overlap_apply": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
+    "ovl_overlap_apply_noalloc": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
     "ovl_batch_sign_apply": (_i, [_vp, _i, _vp, _i, ctypes.c_char_p, _vp]),
     "ovl_defl_project": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "ovl_defl_correct": (_i, [_vp, _vp, _vp, _dp, _i, _i, _vp]),
@@ -46,6 +47,8 @@ SIGNATURES = {
     "ovl_sign_residual": (_i, [_vp, _vp, _vp, _vp, _i, _i, _dp, _vp]),
     "ovl_overlap_solve": (_i, [_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _d, _i,
                                ctypes.POINTER(_i), _dp, _vp]),
+    "ovl_overlap_solve_gmresr": (_i, [_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _d, _d, _d, _i, _i,
+                                      _i, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp, _vp]),
     "ovl_low_modes": (_i, [_vp, _i, _i, _d, _d, _i, _i, _d, ctypes.c_uint64, _d, _vp, _dp, _dp,
                            _dp, ctypes.POINTER(_i), _vp]),
     "ovl_hermitian_eigh": (_i, [_i, _dp, _dp, _dp]),

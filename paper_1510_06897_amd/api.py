@@ -274,6 +274,28 @@ def overlap_solve(g: GaugeField, poly: Polynomial, b, mu: float, defl: Deflation
     return x, it.value, res.value
 
 
+def overlap_solve_gmresr(g: GaugeField, poly: Polynomial, b, mu: float, defl: Deflation = None,
+                         g_inner: GaugeField = None, defl_inner: Deflation = None,
+                         tol: float = 1e-13, inner_tol: float = 0.1, inner_poly_tol: float = 1e-3,
+                         relax: bool = True, max_outer: int = 64, max_inner: int = 20000,
+                         out=None):
+    """x with D[mu] x = b (FP64) by GMRESR around inner CG solves in the precision of g_inner
+    with a truncated sign polynomial (ovl_overlap_solve_gmresr).  Returns (x, outer steps, inner
+    iterations, relative residual with the full polynomial)."""
+    if b.dtype != torch.complex128:
+        raise TypeError("b must be complex128")
+    _check_spinor(b, g.dims)
+    x = _out_like(b, out)
+    no, ni = ctypes.c_int(0), ctypes.c_int(0)
+    res = ctypes.c_double(0)
+    call("ovl_overlap_solve_gmresr", g.handle, poly._h, defl._h if defl is not None else None,
+         float(mu), _ptr(x), _ptr(b), g_inner.handle if g_inner is not None else None,
+         defl_inner._h if defl_inner is not None else None, float(tol), float(inner_tol),
+         float(inner_poly_tol), 1 if relax else 0, int(max_outer), int(max_inner),
+         ctypes.byref(no), ctypes.byref(ni), ctypes.byref(res), _stream())
+    return x, no.value, ni.value, res.value
+
+
 def _batch_items(problems, outs=None):
     """ovl_batch_item array for a list of (GaugeField, psi) problems, with their outputs."""
     if not 1 <= len(problems) <= 16:

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <type_traits>
 #include <mutex>
 #include <string>
@@ -20,6 +21,7 @@
 #include "../../include/ovl.h"
 #include "kernels.hpp"
 #include "stout.hpp"
+#include "solver.hpp"
 
 namespace ovl {
 bool cheb_sign_coeffs(int degree, double eps, std::vector<double> &alpha);
@@ -1423,6 +1425,57 @@ int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
 }  // extern "C"
 
 // ---------------------------------------------------------------------------------------------
+// Work space of the entry point that allocates nothing (ovl_overlap_apply_noalloc): one
+// file-scope device array, present on every device the library runs on until the process ends.
+// Host code never passes the array's name to a kernel or a copy: on the host it is only a
+// stand-in for the symbol.  Its device address is looked up once per device, with that device
+// current, and kept in g_noalloc_ptr.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::once_flag g_noalloc_once[kMaxDevices];
+void *g_noalloc_ptr[kMaxDevices];
+hipError_t g_noalloc_err[kMaxDevices];
+
+int noalloc_space(void **ptr) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(OVL_EINVAL, "device %d out of range", dev);
+  std::call_once(g_noalloc_once[dev], [dev] {
+    void *p = nullptr;
+    g_noalloc_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc_ptr[dev] = g_noalloc_err[dev] == hipSuccess ? p : nullptr;
+  });
+  HIP_TRY(g_noalloc_err[dev]);
+  if (!g_noalloc_ptr[dev]) return fail(OVL_EHIP, "no device address for the static work space");
+  *ptr = g_noalloc_ptr[dev];
+  return OVL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ovl_overlap_apply_noalloc(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                              int dagger, void *out, const void *in, int nrhs, int spin_dt,
+                              void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if ((rc = check_poly(p)) || (rc = check_defl(g, d, prec))) return rc;
+  if (!std::isfinite(mu)) return fail(OVL_ENONFINITE, "mu is not finite");
+  SignSpace space;
+  if ((rc = noalloc_space(&space.fixed))) return rc;
+  space.fixed_cap = kNoAllocBytes;
+  SignJob j{g, const_cast<ovl_defl *>(d), in, out, nrhs};
+  return run_sign_jobs<false>(&j, 1, p, dagger ? MODE_OVERLAP_DAG : MODE_OVERLAP, mu, dagger ? 1 : 0,
+                              spin_dt, prec, as_stream(stream), space);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
 // overlap inversion
 namespace {
 
@@ -1465,37 +1518,142 @@ int vdot(const SolveVecs &w, const void *a, const void *b, int V, std::complex<d
   return OVL_OK;
 }
 
+// <a, b> = a^+ b with FP64 accumulation into the device slot dst (no synchronisation)
+int vdot_dev(const SolveVecs &w, const void *a, const void *b, int V, double2 *dst) {
+  return w.f64 ? project((const double2 *)a, 1, (const double2 *)b, 0, 1, V, w.partial, w.nblk,
+                         dst, w.s)
+               : project((const float2 *)a, 1, (const float2 *)b, 0, 1, V, w.partial, w.nblk,
+                         dst, w.s);
+}
+
+// Host-side view of device scalars that lags the stream by a few launches: value i is copied
+// into pinned memory behind an event, and read once the stream has passed it, so the host never
+// waits for the iteration it has just enqueued.
+struct ScalarLag {
+  static constexpr int K = 4;
+  double *pin = nullptr;
+  hipEvent_t ev[K] = {};
+  int live = 0;
+  ~ScalarLag() {
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (pin) (void)hipHostFree(pin);
+  }
+  int init() {
+    HIP_TRY(hipHostMalloc((void **)&pin, sizeof(double) * K));
+    for (auto &e : ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return OVL_OK;
+  }
+  // enqueue the copy of slot->x as value number i
+  int push(const double2 *slot, int i, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(pin + i % K, &slot->x, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ev[i % K], s));
+    return OVL_OK;
+  }
+  // value number i (waits for its event)
+  int get(int i, double &v) {
+    HIP_TRY(hipEventSynchronize(ev[i % K]));
+    v = pin[i % K];
+    return OVL_OK;
+  }
+};
+
 // CG on D^+ D x = D^+ rhs (x = 0 on entry) in the precision of (g, d); stops when
-// ||D^+ (rhs - D x)|| <= tol ||D^+ rhs|| or after max_iter iterations (each two overlap applies)
+// ||D^+ (rhs - D x)|| <= tol ||D^+ rhs|| or after max_iter iterations (each two overlap
+// applications).  The CG coefficients stay on the device (slots: rr ping-pong, <p, q>); the host
+// reads ||r||^2 two iterations behind the stream, so it may run up to two iterations past the
+// first one that met the tolerance.  `slots` holds 3 double2, `flag` one int (cleared here).
 int cgnr(const SolveVecs &w, const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
          int dt, void *x, const void *rhs, void *r, void *pv, void *q, void *t, double tol,
-         int max_iter, int &iters, void *stream) {
+         int max_iter, int &iters, double2 *slots, int *flag, void *stream) {
   iters = 0;
   const int V = g->g.V;
-  int rc = ovl_overlap_apply(g, p, d, mu, 1, r, rhs, 1, dt, stream);  // r = c = D^+ rhs
+  hipStream_t s = w.s;
+  ScalarLag lag;
+  int rc = lag.init();
   if (rc) return rc;
-  if ((rc = vaxpby(w, nullptr, 0.0, nullptr, 0.0, x))) return rc;  // x = 0
-  if ((rc = vaxpby(w, r, 1.0, nullptr, 0.0, pv))) return rc;      // p = r
-  std::complex<double> z;
-  if ((rc = vdot(w, r, r, V, z))) return rc;
-  double rr = z.real();
-  const double stop = tol * tol * rr;
-  while (rr > stop && iters < max_iter) {
+  if ((rc = ovl_overlap_apply(g, p, d, mu, 1, r, rhs, 1, dt, stream))) return rc;  // r = D^+ rhs
+  if ((rc = vaxpby(w, nullptr, 0.0, nullptr, 0.0, x))) return rc;                   // x = 0
+  if ((rc = vaxpby(w, r, 1.0, nullptr, 0.0, pv))) return rc;                        // p = r
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+  double2 *rr_slot[2] = {slots, slots + 1};
+  double2 *pq = slots + 2;
+  if ((rc = vdot_dev(w, r, r, V, rr_slot[0]))) return rc;
+  if ((rc = lag.push(rr_slot[0], 0, s))) return rc;
+  double rr0;
+  if ((rc = lag.get(0, rr0))) return rc;
+  if (!(rr0 > 0.0)) return OVL_OK;  // D^+ rhs = 0: x = 0 solves it
+  if (!std::isfinite(rr0)) return fail(OVL_ENONFINITE, "non-finite right-hand side");
+  const double stop = tol * tol * rr0;
+  constexpr int kLag = 2;
+  const unsigned nb = vec_blocks(w.n);
+  bool done = false;
+  for (int it = 0; it < max_iter && !done; ++it) {
     if ((rc = ovl_overlap_apply(g, p, d, mu, 0, t, pv, 1, dt, stream))) return rc;  // t = D p
     if ((rc = ovl_overlap_apply(g, p, d, mu, 1, q, t, 1, dt, stream))) return rc;   // q = D^+ t
-    if ((rc = vdot(w, pv, q, V, z))) return rc;
-    if (!(z.real() > 0.0) || !std::isfinite(z.real()))
-      return fail(OVL_EDIVERGED, "CG lost positivity (<p, D^+ D p> = %g)", z.real());
-    const double a = rr / z.real();
-    if ((rc = vaxpby(w, x, 1.0, pv, a, x))) return rc;   // x += a p
-    if ((rc = vaxpby(w, r, 1.0, q, -a, r))) return rc;   // r -= a q
-    if ((rc = vdot(w, r, r, V, z))) return rc;
-    const double rr_new = z.real();
-    if ((rc = vaxpby(w, r, 1.0, pv, rr_new / rr, pv))) return rc;  // p = r + beta p
-    rr = rr_new;
-    ++iters;
+    if ((rc = vdot_dev(w, pv, q, V, pq))) return rc;
+    double2 *ro = rr_slot[it % 2], *rn = rr_slot[(it + 1) % 2];
+    if (w.f64) {
+      cg_xr_kernel<double, double2><<<nb, 256, 0, s>>>((double2 *)x, (double2 *)r, (const double2 *)pv,
+                                                       (const double2 *)q, ro, pq, flag, w.n);
+    } else {
+      cg_xr_kernel<float, float2><<<nb, 256, 0, s>>>((float2 *)x, (float2 *)r, (const float2 *)pv,
+                                                     (const float2 *)q, ro, pq, flag, w.n);
+    }
+    HIP_TRY(hipGetLastError());
+    if ((rc = vdot_dev(w, r, r, V, rn))) return rc;
+    if (w.f64)
+      cg_p_kernel<double, double2><<<nb, 256, 0, s>>>((double2 *)pv, (const double2 *)r, rn, ro, w.n);
+    else
+      cg_p_kernel<float, float2><<<nb, 256, 0, s>>>((float2 *)pv, (const float2 *)r, rn, ro, w.n);
+    HIP_TRY(hipGetLastError());
+    if ((rc = lag.push(rn, it + 1, s))) return rc;
+    iters = it + 1;
+    if (it + 1 - kLag >= 1) {
+      double v;
+      if ((rc = lag.get(it + 1 - kLag, v))) return rc;
+      done = v <= stop;
+    }
   }
+  if (!done) {  // the last values, which the loop did not read yet
+    for (int i = std::max(1, iters + 1 - kLag); i <= iters && !done; ++i) {
+      double v;
+      if ((rc = lag.get(i, v))) return rc;
+      done = v <= stop;
+    }
+  }
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (!done && (hflag & SOLVE_FLAG_CURVATURE))
+    return fail(OVL_EDIVERGED, "CG lost positivity (<p, D^+ D p> not positive)");
   return OVL_OK;
+}
+
+// a copy of p truncated to the lowest odd degree M whose tail sum_{m > M} |alpha_m| is at most
+// tol (|T_m| <= 1 on [-1, 1] bounds the truncation error by the tail); nullptr when p itself is
+// needed.  The copy has its own serial (its own deflation weights).
+ovl_poly *truncated_poly(const ovl_poly *p, double tol) {
+  const int N = (int)p->alpha.size() - 1;
+  if (!(tol > 0.0)) return nullptr;
+  double tail = 0.0;
+  int M = N;
+  // walk down while the dropped coefficients stay within tol
+  while (M > 1) {
+    const double drop = std::fabs(p->alpha[M]) + (M - 1 >= 1 ? std::fabs(p->alpha[M - 1]) : 0.0);
+    if (tail + drop > tol) break;
+    tail += drop;
+    M -= 2;
+  }
+  if (M >= N) return nullptr;
+  ovl_poly *q = new (std::nothrow) ovl_poly();
+  if (!q) return nullptr;
+  q->alpha.assign(p->alpha.begin(), p->alpha.begin() + M + 1);
+  q->lmax = p->lmax;
+  q->m_W = p->m_W;
+  q->bound = p->bound + tail;
+  q->serial = g_poly_serial.fetch_add(1);
+  return q;
 }
 
 }  // namespace
@@ -1533,13 +1691,15 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
   const int nblk = project_blocks(V);
   const size_t part = ((size_t)nblk * sizeof(double2) + 255) / 256 * 256;
   Scratch sc;
-  if ((rc = scratch_alloc(sc, 2 * v64 + 6 * vin + part + 256, s))) return rc;
+  if ((rc = scratch_alloc(sc, 2 * v64 + 6 * vin + part + 512, s))) return rc;
   char *base = (char *)sc.p;
   void *r64 = base, *t64 = base + v64;
   char *ib = base + 2 * v64;
   void *rhs = ib, *dx = ib + vin, *r = ib + 2 * vin, *pv = ib + 3 * vin, *q = ib + 4 * vin,
        *t = ib + 5 * vin;
   SolveVecs w64{true, n, s, (double2 *)(ib + 6 * vin), nblk, (double2 *)(ib + 6 * vin + part)};
+  double2 *slots = (double2 *)(ib + 6 * vin + part + 256);  // CG scalars (3) and the flag word
+  int *flag = (int *)(slots + 4);
   SolveVecs wi = w64;
   wi.f64 = in64;
   std::complex<double> z;
@@ -1569,7 +1729,7 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
     const double tol_in = std::min(0.1, std::max(0.5 * tol / resid, floor));
     int its = 0;
     if ((rc = cgnr(wi, gi, p, di, mu, dt_in, dx, rhs, r, pv, q, t, tol_in, max_iter - total, its,
-                   stream)))
+                   slots, flag, stream)))
       return rc;
     total += its;
     if (in64)
@@ -1581,6 +1741,181 @@ int ovl_overlap_solve(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
   if (iters_out) *iters_out = total;
   if (resid_out) *resid_out = resid;
   if (!(resid <= tol)) return fail(OVL_EDIVERGED, "relative residual %.3e > %.3e after %d iterations", resid, tol, total);
+  return OVL_OK;
+}
+
+// D[mu] x = b by GMRESR (generalised conjugate residuals with a variable preconditioner): each
+// outer step solves D z = r approximately with CG on the normal equations in the inner precision
+// and with a truncated ("relaxed") polynomial, forms c = D z in FP64, orthogonalises c against the
+// previous directions (classical Gram-Schmidt twice; z follows with the same coefficients),
+// normalises, and takes x += <c, r> z, r -= <c, r> c.  All coefficients stay on the device; the
+// host reads ||r|| once per outer step.  With relax, the outer product of step k uses the
+// polynomial truncated at tail 0.1 tol ||b|| / ||r_k|| (coarser as the residual falls).  The
+// final residual is recomputed with the full polynomial; if it misses tol, GMRESR restarts from
+// x without relaxation (at most 3 cycles).
+int ovl_overlap_solve_gmresr(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                             void *x, const void *b, const ovl_gauge *g_in, const ovl_defl *d_in,
+                             double tol, double inner_tol, double inner_poly_tol, int relax,
+                             int max_outer, int max_inner, int *outer_out, int *inner_out,
+                             double *resid_out, void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, x, b, 1, OVL_F64, prec);
+  if (rc) return rc;
+  if (prec != P_F64) return fail(OVL_EDTYPE, "the outer gauge handle must store FP64 links");
+  if ((rc = check_poly(p)) || (rc = check_defl(g, d, prec))) return rc;
+  if (!std::isfinite(mu) || !std::isfinite(tol) || !std::isfinite(inner_tol) ||
+      !std::isfinite(inner_poly_tol))
+    return fail(OVL_ENONFINITE, "non-finite mu or tolerance");
+  if (!(tol > 0.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || !(inner_poly_tol >= 0.0) ||
+      max_outer < 1 || max_outer > 1024 || max_inner < 1)
+    return fail(OVL_EINVAL, "need tol > 0, 0 < inner_tol < 1, inner_poly_tol >= 0, "
+                "1 <= max_outer <= 1024, max_inner >= 1");
+  const ovl_gauge *gi = g_in ? g_in : g;
+  const ovl_defl *di = g_in ? d_in : d;
+  if (g_in) {
+    if (std::memcmp(g_in->g.L, g->g.L, sizeof(g->g.L)) != 0)
+      return fail(OVL_EDIMS, "inner gauge handle has other extents");
+    if (g_in->store_dt == OVL_F64) return fail(OVL_EDTYPE, "inner gauge handle stores FP64 links");
+    if ((rc = check_defl(g_in, d_in, P_F32))) return rc;
+  }
+  const bool in64 = gi->store_dt == OVL_F64;
+  const int dt_in = in64 ? OVL_F64 : OVL_F32;
+  hipStream_t s = as_stream(stream);
+  const int V = g->g.V;
+  const int64_t n = (int64_t)12 * V;
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t v64 = up((size_t)n * 16), vin = up((size_t)n * (in64 ? 16 : 8));
+  const int nblk = project_blocks(V);
+  const size_t part = up((size_t)nblk * max_outer * sizeof(double2));
+  const size_t slot_bytes = up(sizeof(double2) * (size_t)(max_outer + 8) + 64);
+  // direction bases C and Z: max_outer vectors each, exactly n elements apart (the projection
+  // kernels read a basis as one [m][12][V] array)
+  const size_t vb = up((size_t)max_outer * n * sizeof(double2));
+  Scratch sc;
+  if ((rc = scratch_alloc(sc, 2 * v64 + 2 * vb + 6 * vin + part + slot_bytes, s))) return rc;
+  char *base = (char *)sc.p;
+  double2 *r64 = (double2 *)base, *t64 = (double2 *)(base + v64);
+  double2 *Cb = (double2 *)(base + 2 * v64), *Zb = (double2 *)(base + 2 * v64 + vb);
+  char *ib = base + 2 * v64 + 2 * vb;
+  void *rhs = ib, *dz = ib + vin, *r = ib + 2 * vin, *pv = ib + 3 * vin, *q = ib + 4 * vin,
+       *t = ib + 5 * vin;
+  double2 *partial = (double2 *)(ib + 6 * vin);
+  double2 *slots = (double2 *)(ib + 6 * vin + part);
+  // slots: [0, max_outer) Gram-Schmidt coefficients, then |c|^2, <c, r>, |r|^2, CG scalars (3)
+  double2 *beta = slots, *cnrm = slots + max_outer, *alph = cnrm + 1, *rr = cnrm + 2,
+          *cg_slots = cnrm + 3;
+  int *flag = (int *)(cnrm + 7);
+  SolveVecs w64{true, n, s, partial, nblk, rr};
+  SolveVecs wi = w64;
+  wi.f64 = in64;
+  const unsigned nb64 = vec_blocks(n);
+  // polynomials: the inner one truncated at inner_poly_tol; relaxed outer ones by truncation level
+  std::vector<std::unique_ptr<ovl_poly>> owned;
+  const ovl_poly *p_in = p;
+  if (ovl_poly *q0 = truncated_poly(p, inner_poly_tol)) {
+    owned.emplace_back(q0);
+    p_in = q0;
+  }
+  std::map<int, const ovl_poly *> relaxed;  // truncation exponent -> polynomial
+  auto outer_poly = [&](double tail) -> const ovl_poly * {
+    if (!(tail > 0.0)) return p;
+    const int e = (int)std::floor(std::log10(std::min(tail, 0.1)));  // tails 10^e
+    auto it = relaxed.find(e);
+    if (it != relaxed.end()) return it->second;
+    const ovl_poly *pp = p;
+    if (ovl_poly *q1 = truncated_poly(p, std::pow(10.0, e))) {
+      owned.emplace_back(q1);
+      pp = q1;
+    }
+    relaxed[e] = pp;
+    return pp;
+  };
+  auto host_norm = [&](const void *a, double &out) -> int {
+    std::complex<double> z;
+    int e = vdot(w64, a, a, V, z);
+    out = std::sqrt(std::max(0.0, z.real()));
+    return e;
+  };
+  double nb;
+  if ((rc = host_norm(b, nb))) return rc;
+  if (!std::isfinite(nb)) return fail(OVL_ENONFINITE, "non-finite right-hand side");
+  if ((rc = vaxpby(w64, nullptr, 0.0, nullptr, 0.0, x))) return rc;
+  int outer = 0, inner = 0;
+  double resid = nb > 0.0 ? 1.0 : 0.0;
+  for (int cycle = 0; cycle < 3 && nb > 0.0; ++cycle) {
+    // r = b - D x (full polynomial)
+    if (cycle == 0) {
+      if ((rc = vaxpby(w64, b, 1.0, nullptr, 0.0, r64))) return rc;
+    } else {
+      if ((rc = ovl_overlap_apply(g, p, d, mu, 0, t64, x, 1, OVL_F64, stream))) return rc;
+      if ((rc = vaxpby(w64, b, 1.0, t64, -1.0, r64))) return rc;
+    }
+    double rn;
+    if ((rc = host_norm(r64, rn))) return rc;
+    if (rn / nb <= tol) {
+      resid = rn / nb;
+      break;
+    }
+    const bool rel = relax != 0 && cycle == 0;
+    for (int k = 0; k < max_outer && rn / nb > tol && inner < max_inner; ++k) {
+      // inner: D z ~ r / |r| in the inner precision with the truncated polynomial
+      if (in64)
+        scale_convert_kernel<double2, double2><<<nb64, 256, 0, s>>>(r64, (double2 *)rhs, 1.0 / rn, n);
+      else
+        scale_convert_kernel<double2, float2><<<nb64, 256, 0, s>>>(r64, (float2 *)rhs, 1.0 / rn, n);
+      HIP_TRY(hipGetLastError());
+      int its = 0;
+      if ((rc = cgnr(wi, gi, p_in, di, mu, dt_in, dz, rhs, r, pv, q, t, inner_tol,
+                     max_inner - inner, its, cg_slots, flag, stream)))
+        return rc;
+      inner += its;
+      double2 *ck = Cb + (size_t)k * n;
+      double2 *zk = Zb + (size_t)k * n;
+      if (in64)
+        scale_convert_kernel<double2, double2><<<nb64, 256, 0, s>>>((const double2 *)dz, zk, 1.0, n);
+      else
+        scale_convert_kernel<float2, double2><<<nb64, 256, 0, s>>>((const float2 *)dz, zk, 1.0, n);
+      HIP_TRY(hipGetLastError());
+      // c = D z in FP64 (relaxed: truncated polynomial)
+      const ovl_poly *pk = rel ? outer_poly(0.1 * tol * nb / rn) : p;
+      if ((rc = ovl_overlap_apply(g, pk, d, mu, 0, ck, zk, 1, OVL_F64, stream))) return rc;
+      // classical Gram-Schmidt twice against the previous directions
+      HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+      for (int pass = 0; pass < 2 && k > 0; ++pass) {
+        if ((rc = project(Cb, k, ck, 0, 1, V, partial, nblk, beta, s))) return rc;
+        gcr_orth_kernel<<<nb64, 256, 0, s>>>(ck, Cb, k, beta, n);
+        HIP_TRY(hipGetLastError());
+        gcr_orth_kernel<<<nb64, 256, 0, s>>>(zk, Zb, k, beta, n);
+        HIP_TRY(hipGetLastError());
+      }
+      if ((rc = project(ck, 1, ck, 0, 1, V, partial, nblk, cnrm, s))) return rc;
+      gcr_normalise_kernel<<<nb64, 256, 0, s>>>(ck, zk, cnrm, flag, n);
+      HIP_TRY(hipGetLastError());
+      if ((rc = project(ck, 1, r64, 0, 1, V, partial, nblk, alph, s))) return rc;
+      gcr_update_kernel<<<nb64, 256, 0, s>>>((double2 *)x, r64, zk, ck, alph, n);
+      HIP_TRY(hipGetLastError());
+      ++outer;
+      if ((rc = host_norm(r64, rn))) return rc;
+      int hflag = 0;
+      HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (hflag) return fail(OVL_EDIVERGED, "GMRESR direction %d is dependent on the previous ones", k);
+    }
+    // the true residual with the full polynomial
+    if ((rc = ovl_overlap_apply(g, p, d, mu, 0, t64, x, 1, OVL_F64, stream))) return rc;
+    if ((rc = vaxpby(w64, b, 1.0, t64, -1.0, r64))) return rc;
+    double tn;
+    if ((rc = host_norm(r64, tn))) return rc;
+    resid = tn / nb;
+    if (resid <= tol || inner >= max_inner) break;
+  }
+  if (outer_out) *outer_out = outer;
+  if (inner_out) *inner_out = inner;
+  if (resid_out) *resid_out = resid;
+  if (!(resid <= tol))
+    return fail(OVL_EDIVERGED, "relative residual %.3e > %.3e after %d outer / %d inner iterations",
+                resid, tol, outer, inner);
   return OVL_OK;
 }
 

@@ -804,7 +804,8 @@ def test_two_row_links_kernel(ovl, tmp_path, store, dims, spb, tiles):
         pytest.skip("two sites per lane take FP32 spinors")
     prec = {"f64": 0, "f32": 1, "bf16": 2}[store]
     cache = tmp_path / "r12.txt"
-    cache.write_text(" ".join(map(str, dims)) + f" {prec} 2 {spb} {tiles} 1 0\n")
+    # the tuning key includes the link read mode: an entry for two-row reads (r12 = 1)
+    cache.write_text(f"B {prec} 1 1 {' '.join(map(str, dims))} 2 {spb} {tiles} 1 1 0\n")
     assert ovl.autotune_load(str(cache)) == 1
     u = latgen.random_su3_field(dims, 10185, noise=0.5)
     psi = latgen.gaussian_spinor(dims, 20185, nrhs=2)

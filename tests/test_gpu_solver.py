@@ -91,3 +91,58 @@ def test_solve_errors(ovl):
     with pytest.raises(ovl.OvlError) as e:
         ovl.overlap_solve(g32, p, b, 0.05)
     assert e.value.status == "OVL_EDTYPE"
+
+
+@pytest.mark.parametrize("inner,relax", [("f32", True), ("bf16", True), (None, False)])
+def test_gmresr_to_1e13_against_oracle(ovl, problem, inner, relax):
+    """GMRESR with inner CG in FP32 (FP32 or BF16 links) on a truncated polynomial and relaxed
+    FP64 outer products, to the paper's overlap accuracy 1e-13 (Sec. 3); the residual with the
+    oracle's operator and the distance to the oracle's CG solution."""
+    dims, u, b, phi, lam, alpha, x_ref = problem
+    print(f"gmresr inner={inner} relax={relax}", flush=True)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f64")
+    gi = ovl.GaugeField(dev(u), inner) if inner else None
+    di = ovl.Deflation(dev(phi), lam, "f32") if inner else None
+    x, n_out, n_in, res = ovl.overlap_solve_gmresr(g, p, dev(b), 0.05, defl=d, g_inner=gi,
+                                                   defl_inner=di, tol=1e-13, relax=relax)
+    got = x.cpu().numpy()
+    assert res <= 1e-13 and n_out > 0 and n_in > 0
+    r = b - oov.overlap_apply(u, got, 0.05, alpha, LMAX, phi, lam)
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 3e-13
+    assert rel_err(got, x_ref) < 1e-10
+    assert g.flags() == 0
+
+
+def test_gmresr_dense_2x2x2x2(ovl):
+    dims = (2, 2, 2, 2)
+    u = latgen.random_su3_field(dims, 10503)
+    b = latgen.gaussian_spinor(dims, 20503)
+    alpha = och.coeffs_sign_interp(21, 0.1)
+    ref = np.linalg.solve(osol.dense_overlap(u, 0.1, alpha, LMAX), b.reshape(-1)).reshape(b.shape)
+    g = ovl.GaugeField(dev(u), "f64")
+    gi = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    x, n_out, _, res = ovl.overlap_solve_gmresr(g, p, dev(b), 0.1, g_inner=gi, tol=1e-13,
+                                                inner_poly_tol=1e-2)
+    assert res <= 1e-13
+    assert rel_err(x.cpu().numpy(), ref) < 1e-11
+
+
+def test_gmresr_errors(ovl):
+    dims = (2, 2, 2, 4)
+    u = latgen.random_su3_field(dims, 10504)
+    b = dev(latgen.gaussian_spinor(dims, 20504))
+    alpha = och.coeffs_sign_interp(15, 0.1)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.overlap_solve_gmresr(g, p, b, 0.05, out=b)
+    assert e.value.status == "OVL_EALIAS"
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.overlap_solve_gmresr(g, p, b, 0.05, inner_tol=1.5)
+    assert e.value.status == "OVL_EINVAL"
+    with pytest.raises(ovl.OvlError) as e:
+        ovl.overlap_solve_gmresr(g, p, b, 0.01, tol=1e-15, max_outer=1, max_inner=3)
+    assert e.value.status == "OVL_EDIVERGED"
