@@ -338,6 +338,24 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     g32.reconstruct()
     ms_r12 = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE,
                                                   out=G), reps)
+    # the HMC chain on thin links (Sec. 1; Sec. 2: 3 steps of over-improved stout smearing,
+    # rho 0.1, eps -0.25): smear on the device, force on the smeared links, chain rule back
+    u_thin = torch.from_numpy(latgen.random_su3_field(C5_DIMS, latgen.seed_for("gauge", 5))).to(dev)
+    us = torch.empty_like(u_thin)
+    ms_smear = gpu_ms(torch, lambda: ovl.stout_smear(u_thin, 0.1, -0.25, 3, out=us), 2)
+    g_s = ovl.GaugeField(us, "f32")
+    ms_fs = gpu_ms(torch, lambda: ovl.sign_force(g_s, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G), 1)
+    g64 = G.to(torch.complex128)
+    gt = torch.empty_like(u_thin)
+    ms_back = gpu_ms(torch, lambda: ovl.stout_backward(u_thin, g64, 0.1, -0.25, 3, out=gt), 2)
+    assert torch.isfinite(torch.view_as_real(gt)).all()
+    del u_thin, us, g_s, g64, gt
+    chain = {"stout_smear_3_steps_ms": round(ms_smear, 2), "force_on_smeared_links_ms": round(ms_fs, 2),
+             "stout_chain_rule_3_steps_ms": round(ms_back, 2),
+             "thin_link_force_ms": round(ms_smear + ms_fs + ms_back, 2),
+             "smearing": "over-improved stout, rho 0.1, eps -0.25, 3 steps (FP64 on the device)"}
+    log(f"force chain on thin links: smear {ms_smear:.1f} ms, force {ms_fs:.1f} ms, chain rule "
+        f"{ms_back:.1f} ms")
     # bytes of the link-VJP launches: every pair reads a and t once (FP32 spinors), the FP64
     # running sum of G is written by the first segment, read and written by the middle ones and
     # read by the last, which writes G in FP32
@@ -349,7 +367,7 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
            "ms_per_force_stride_299": round(ms_all, 2),
            "ms_per_force_two_row_links": round(ms_r12, 2),
            "vjp_ms": v_ms, "vjp_launches": v_n, "vjp_launches_per_force": v_n // reps,
-           "vjp_bytes_per_force": vjp_bytes}
+           "vjp_bytes_per_force": vjp_bytes, "hmc_chain_thin_links": chain}
     log(f"force 24^3x48: {ms_f:.1f} ms (link VJP {v_ms / reps:.1f} ms of it; "
         f"two-row {ms_r12:.1f}, stride 299 {ms_all:.1f})")
     return out
@@ -400,14 +418,25 @@ def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     ms12 = gpu_ms(torch, lambda: ovl.overlap_apply(g32, poly, psi12, MUS[0], defl=defl32,
                                                    out=out12), 5)
     solves = {}
-    for label, gi, di in (("f64", None, None), ("f32_inner", g32, defl32)):
+    for label, gi, di in (("cg_f64", None, None), ("cg_f32_inner", g32, defl32)):
         torch.cuda.synchronize()
         t0s = time.perf_counter()
         _, its, sres = ovl.overlap_solve(g64, poly, psi64, MUS[1], defl=defl64, g_inner=gi,
-                                         defl_inner=di, tol=1e-10)
+                                         defl_inner=di, tol=1e-13)
         torch.cuda.synchronize()
-        solves[f"{label}_mu{MUS[1]}"] = {"s": round(time.perf_counter() - t0s, 4),
-                                         "cg_iterations": its, "rel_residual": sres}
+        solves[label] = {"s": round(time.perf_counter() - t0s, 4), "cg_iterations": its,
+                         "rel_residual": sres}
+    # the paper's solver form: GMRESR around FP32 inner CG on a truncated polynomial, relaxed
+    # FP64 outer products (Sec. 2), to the paper's overlap accuracy 1e-13 (Sec. 3)
+    for label, relax in (("gmresr_f32_inner_relaxed", True), ("gmresr_f32_inner", False)):
+        torch.cuda.synchronize()
+        t0s = time.perf_counter()
+        _, n_out, n_in, sres = ovl.overlap_solve_gmresr(g64, poly, psi64, MUS[1], defl=defl64,
+                                                        g_inner=g32, defl_inner=defl32, tol=1e-13,
+                                                        relax=relax)
+        torch.cuda.synchronize()
+        solves[label] = {"s": round(time.perf_counter() - t0s, 4), "outer_steps": n_out,
+                         "inner_cg_iterations": n_in, "rel_residual": sres}
     assert g32.flags() == 0 and g64.flags() == 0
     log(f"C2 overlap: FP32 {ms32:.3f} ms, FP64 {ms64:.3f} ms, 12 sources {ms12:.3f} ms")
     _FIELDS["c2"] = (u, psi, float(eps))
@@ -417,7 +446,8 @@ def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
             "twelve_sources_ms_per_call": round(ms12, 4),
             "twelve_sources_rhs_applies_per_s": round(12e3 / ms12, 1),
             "eps": round(float(eps), 5), "degree": len(alpha) - 1,
-            "eigen_residual_max": float(res_e.max()), "solve_1e-10": solves}
+            "eigen_residual_max": float(res_e.max()),
+            "solve_mu0.05_to_1e-13": solves}
 
 
 # ------------------------------------------------------------------------------------------------
@@ -608,6 +638,8 @@ def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
     for key in gpu:
         base_name = key if not key.startswith("c2_") else "c2"
         ex, same = refs[base_name + "|exact"][0], refs[base_name + "|same"][0]
+        if key.endswith("_f64"):
+            same = ex   # FP64 storage: the device sees the exact inputs
         errs[key] = {"vs_oracle_exact_inputs": rel(gpu[key], ex),
                      "vs_oracle_same_rounded_inputs": rel(gpu[key], same),
                      "oracle_s": round(refs[base_name + "|exact"][1], 1)}
