@@ -157,6 +157,22 @@ int ovl_sign_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, voi
 int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
                       int dagger, void *out, const void *in, int nrhs, int spin_dt, void *stream);
 
+/* ovl_overlap_apply for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): same arguments, same kernels
+ * and launch configuration, same results.  Its work space (one recurrence vector, norm and
+ * projection partials and deflation coefficients: about nrhs * 12 V * sizeof(element) bytes plus
+ * a few percent) lives in one 64 MiB array of static device memory that every GPU the library
+ * runs on holds until the process ends; its address is looked up once per device.  The call
+ * makes no hipMalloc, hipFree or other allocation (and no step graph).  Every word of the work
+ * space that the call reads it has written before in the same call, so nothing needs clearing.
+ * All calls on one GPU share the array: calls that overlap in time on one GPU (other streams,
+ * other threads) race on it.  Errors: as ovl_overlap_apply, plus EINVAL when the evaluation needs
+ * more than 64 MiB of work space (for example FP64 single right-hand sides above about 340K
+ * sites). */
+int ovl_overlap_apply_noalloc(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                              int dagger, void *out, const void *in, int nrhs, int spin_dt,
+                              void *stream);
+
 /* Batched form of ovl_sign_apply (no deflation; Sec. 2, eq. 3): up to 16 lattice problems --
  * each its own gauge field, volume and right-hand-side count -- evaluated with one polynomial in
  * one kernel launch per K application, so small volumes fill the GPU together and the

@@ -38,6 +38,7 @@ SIGNATURES = {
     "ovl_kernel_axpby": (_i, [_vp, _vp, _vp, _d, _vp, _d, _vp, _d, _i, _i, _d, _vp]),
     "ovl_sign_apply": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _vp]),
     "ovl_overlap_apply": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
+    "ovl_overlap_apply_noalloc": (_i, [_vp, _vp, _vp, _d, _i, _vp, _vp, _i, _i, _vp]),
     "ovl_batch_sign_apply": (_i, [_vp, _i, _vp, _i, ctypes.c_char_p, _vp]),
     "ovl_defl_project": (_i, [_vp, _vp, _vp, _i, _i, _vp]),
     "ovl_defl_correct": (_i, [_vp, _vp, _vp, _dp, _i, _i, _vp]),

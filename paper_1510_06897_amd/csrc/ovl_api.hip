@@ -1422,6 +1422,56 @@ int ovl_overlap_apply(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
                   dagger ? 1 : 0, out, in, nrhs, spin_dt, prec, as_stream(stream));
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Work space of the entry point that allocates nothing (ovl_overlap_apply_noalloc): one
+// file-scope device array, present on every device the library runs on until the process ends.
+// Host code never passes the array's name to a kernel or a copy: on the host it is only a
+// stand-in for the symbol.  Its device address is looked up once per device, with that device
+// current, and kept in g_noalloc_ptr.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::once_flag g_noalloc_once[kMaxDevices];
+void *g_noalloc_ptr[kMaxDevices];
+hipError_t g_noalloc_err[kMaxDevices];
+
+int noalloc_space(void **ptr) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(OVL_EINVAL, "device %d out of range", dev);
+  std::call_once(g_noalloc_once[dev], [dev] {
+    void *p = nullptr;
+    g_noalloc_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_noalloc_ptr[dev] = g_noalloc_err[dev] == hipSuccess ? p : nullptr;
+  });
+  HIP_TRY(g_noalloc_err[dev]);
+  if (!g_noalloc_ptr[dev]) return fail(OVL_EHIP, "no device address for the static work space");
+  *ptr = g_noalloc_ptr[dev];
+  return OVL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ovl_overlap_apply_noalloc(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, double mu,
+                              int dagger, void *out, const void *in, int nrhs, int spin_dt,
+                              void *stream) {
+  g_err[0] = 0;
+  Prec prec;
+  int rc = check_spinor_call(g, out, in, nrhs, spin_dt, prec);
+  if (rc) return rc;
+  if ((rc = check_poly(p)) || (rc = check_defl(g, d, prec))) return rc;
+  if (!std::isfinite(mu)) return fail(OVL_ENONFINITE, "mu is not finite");
+  SignSpace space;
+  if ((rc = noalloc_space(&space.fixed))) return rc;
+  space.fixed_cap = kNoAllocBytes;
+  SignJob j{g, const_cast<ovl_defl *>(d), in, out, nrhs};
+  return run_sign_jobs<false>(&j, 1, p, dagger ? MODE_OVERLAP_DAG : MODE_OVERLAP, mu, dagger ? 1 : 0,
+                              spin_dt, prec, as_stream(stream), space);
+}
 
 }  // extern "C"
 
