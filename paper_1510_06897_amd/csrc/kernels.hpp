@@ -1103,6 +1103,29 @@ __global__ void __launch_bounds__(256) su3_row2_dev_kernel(const LE *U, int V, d
 }
 
 // ---------------------------------------------------------------------------------------------
+// Site of lane sl in workgroup gb of a VJP launch (64 sites per workgroup): memory order, or
+// (ty > 0) the t-streaming tile order of the step kernels -- whole x lines, ty x tz in (y, z),
+// consecutive workgroups walking t -- so the t neighbours a workgroup reads were loaded shortly
+// before by the workgroup of the previous slice, and most y and z neighbours lie in its own
+// tile (measured: 3% faster than memory order at 24^3 x 48).
+__device__ __forceinline__ int vjp_site(int gb, int sl, const Ext4 &ex, int ty, int tz) {
+  if (ty <= 0) return gb * 64 + sl;
+  const int slice = ex.lx * ty * tz;
+  const int nsub = slice / 64;
+  int tb = gb;
+  const int sub = tb % nsub;
+  tb /= nsub;
+  const int t = tb % ex.lt;
+  const int tile = tb / ex.lt;
+  const int nty = ex.ly / ty;
+  const int local = sub * 64 + sl;
+  const int x = local % ex.lx;
+  const int rr = local / ex.lx;
+  const int y = (tile % nty) * ty + rr % ty;
+  const int z = (tile / nty) * tz + rr / ty;
+  return x + ex.sy * y + ex.sz * z + ex.st * t;
+}
+
 // Link vector-Jacobian products of the hopping term, summed over a segment of vector pairs.
 // For L = Re<a, D_W t> (a read with gamma5 when a_g5), with h^-(f) the half-spinor of
 // (1 - gamma_mu) f and h^+(f) of (1 + gamma_mu) f:
@@ -1120,16 +1143,17 @@ __global__ void __launch_bounds__(256) su3_row2_dev_kernel(const LE *U, int V, d
 // The four direction waves of a workgroup share the 64 sites: a(x) and t(x) are read from HBM
 // once per workgroup (wave mu loads spin-colour components 3 mu .. 3 mu + 2) and handed over in
 // LDS, double-buffered so that one barrier per pair suffices; the forward neighbours a(x+mu),
-// t(x+mu) are read per thread, issued before the barrier.
+// t(x+mu) are read per thread, issued before the barrier.  Sites follow vjp_site (ty, tz from
+// the host; 0 = memory order).
 template <class C, class SE, class GE>
 __global__ void __launch_bounds__(256)
     link_vjp_kernel(GE *G, double2 *G64, const SE *a0, const SE *a1, int64_t a_step,
                     const SE *t0, const SE *t1, int64_t t_step, int len0, int len,
                     double coef_first, double coef_rest, Geom geo, int a_g5, int in_mode,
-                    int out_mode) {
+                    int out_mode, int ty, int tz) {
   const int mu = threadIdx.x >> 6, sl = threadIdx.x & 63;
-  const int site = blockIdx.x * 64 + sl;
   const Ext4 ex = ext_of(geo);
+  const int site = vjp_site(blockIdx.x, sl, ex, ty, tz);
   // no early return: every thread reaches the barriers; inactive lanes load and store nothing
   const bool active = site < ex.V;
   const int s_site = active ? site : 0;

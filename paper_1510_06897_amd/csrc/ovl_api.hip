@@ -2006,13 +2006,16 @@ int launch_vjp(Prec prec, const ovl_gauge *g, void *G, double2 *G64, const void 
     run.e1 = pool_event();
   }
   if (run.e0) HIP_TRY(hipEventRecord(run.e0, s));
+  // t-streaming tile order where the lattice allows it (whole tiles of 64 sites)
+  int ty = 0, tz = 0;
+  step_tile(g->g, 64, 2 * 96, ty, tz);
   switch (prec) {
     case P_F64:
       link_vjp_kernel<double, double2, double2><<<grid, 256, 0, s>>>(
           (double2 *)G, G64, (const double2 *)a0, (const double2 *)a1,
           (int64_t)(step_bytes / sizeof(double2)), (const double2 *)t0, (const double2 *)t1,
           (int64_t)(step_bytes / sizeof(double2)), len0, len, coef_first, coef_rest, g->g, a_g5,
-          in_mode, out_mode);
+          in_mode, out_mode, ty, tz);
       break;
     case P_F32:
     case P_F32_BF16:
@@ -2020,7 +2023,7 @@ int launch_vjp(Prec prec, const ovl_gauge *g, void *G, double2 *G64, const void 
           (float2 *)G, G64, (const float2 *)a0, (const float2 *)a1,
           (int64_t)(step_bytes / sizeof(float2)), (const float2 *)t0, (const float2 *)t1,
           (int64_t)(step_bytes / sizeof(float2)), len0, len, coef_first, coef_rest, g->g, a_g5,
-          in_mode, out_mode);
+          in_mode, out_mode, ty, tz);
       break;
     default:
       return fail(OVL_EDTYPE, "bad precision");

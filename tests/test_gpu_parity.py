@@ -575,6 +575,47 @@ def test_link_vjp_fp64(ovl):
     assert max_rel(host(acc), 2 * oforce.wilson_link_vjp(chi, psi)) < 1e-14
 
 
+@pytest.mark.parametrize("dims", [(6, 3, 4, 2), (2, 2, 3, 4), (5, 4, 2, 3), (16, 16, 16, 16)])
+def test_link_vjp_fp32(ovl, dims):
+    """FP32 link VJP against the oracle on the same FP32-rounded spinors, on extent-2, odd and
+    (16^4, 64K sites) t-streaming tile-ordered launches; accumulate adds to the existing G."""
+    chi = latgen.round_to_f32(latgen.gaussian_spinor(dims, 74))
+    psi = latgen.round_to_f32(latgen.gaussian_spinor(dims, 75))
+    g = ovl.GaugeField(dev(latgen.random_su3_field(dims, 76)), "f32")
+    got = ovl.wilson_link_vjp(g, dev(chi, torch.complex64), dev(psi, torch.complex64))
+    ref = oforce.wilson_link_vjp(chi, psi)
+    assert max_rel(host(got), ref) < 1e-6
+    ovl.wilson_link_vjp(g, dev(chi, torch.complex64), dev(psi, torch.complex64), out=got,
+                        accumulate=True)
+    assert max_rel(host(got), 2 * ref) < 1e-6
+
+
+def test_link_vjp_fp64_tile_order(ovl):
+    """FP64 link VJP on a lattice large enough for the tile order (16^3 x 16)."""
+    dims = (16, 16, 16, 16)
+    chi = latgen.gaussian_spinor(dims, 77)
+    psi = latgen.gaussian_spinor(dims, 78)
+    g = ovl.GaugeField(dev(latgen.random_su3_field(dims, 79)), "f64")
+    got = host(ovl.wilson_link_vjp(g, dev(chi), dev(psi)))
+    assert max_rel(got, oforce.wilson_link_vjp(chi, psi)) < 1e-14
+
+
+@pytest.mark.parametrize("dims", [(6, 4, 2, 4), (3, 4, 4, 2)])
+def test_sign_force_fp32_lattices(ovl, dims):
+    """Checkpointed FP32 force (segments over two runs of ring slots, FP64 running sum) on even
+    and odd extents against the oracle gradient on the same rounded inputs."""
+    u = latgen.smeared_field(dims, 87, steps=1)
+    chi = latgen.gaussian_spinor(dims, 88)
+    psi = latgen.gaussian_spinor(dims, 89)
+    alpha = och.coeffs_sign_interp(41, 0.1)
+    u32, chi32, psi32 = latgen.round_to_f32(u), latgen.round_to_f32(chi), latgen.round_to_f32(psi)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    got = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64),
+                              ckpt_stride=5))
+    assert rel_err(got, oforce.sign_force(u32, chi32, psi32, alpha, LMAX)) < 1e-6
+
+
 @pytest.mark.parametrize("stride", [0, 1, 5, 63])
 def test_sign_force_fp64(ovl, stride):
     dims = (4, 4, 4, 4)
