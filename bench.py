@@ -774,6 +774,20 @@ def main():
     if "c2" in extra:
         extra["c2"]["errors"] = {k: errs.get(f"c2_{k}") for k in ("f32", "f64")}
 
+    # the same figures against the measured device-memory stream ceilings (a plain 4 GiB read,
+    # copy and three-reads-one-write stream; the stencil reads several streams and writes one)
+    st = extra.get("streams_4GiB")
+    if st:
+        ceil = {k: st[k]["GBps"] for k in ("read", "copy", "three_to_one")}
+        rl["measured_ceilings_GBps"] = ceil
+        rl["frac_of_three_to_one_stream"] = round(rl["achieved"] / ceil["three_to_one"], 4)
+        for store, row in extra.get("k_and_sign_24x24x24x48", {}).items():
+            for form in row.values():
+                form["K_frac_of_three_to_one_stream"] = round(form["K_GBps"] / ceil["three_to_one"], 4)
+                form["step_frac_of_three_to_one_stream"] = round(form["step_GBps"] / ceil["three_to_one"], 4)
+        if "c5_force" in extra:
+            f = extra["c5_force"]["roofline"]
+            f["frac_of_three_to_one_stream"] = round(f["achieved"] / ceil["three_to_one"], 4)
     n_rhs = c4["n_rhs"]
     ms = c4["ms_per_batch"]
     line = {

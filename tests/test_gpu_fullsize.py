@@ -1,6 +1,7 @@
 """Parity at the full sizes of the measured workloads, in the launch configurations the benchmark
-times.  The oracle cannot run the benchmark's Chebyshev degrees at these volumes in a test, so the
-polynomial degree is lowered: every launch is the same kernel in the same configuration as in the
+times.  The batched workload also runs at its full degree, with the lattices the oracle evaluates
+in seconds compared element by element.  Elsewhere the oracle cannot run the benchmark's
+Chebyshev degrees at these volumes in a test, so the polynomial degree is lowered: every launch is the same kernel in the same configuration as in the
 benchmark (the degree only sets how many steps run), and every output element is compared with
 the FP64 oracle on the same rounded inputs."""
 import numpy as np
@@ -10,7 +11,7 @@ import latgen
 from oracle import chebyshev as och
 from oracle import deflation as odefl
 from oracle import force as oforce
-from tests.conftest import rel_err
+from tests.conftest import complete_third_row, rel_err
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -77,6 +78,43 @@ def test_batched_mixed_volumes_full_size(ovl):
         u_r, s_r = latgen.round_to_f32(u), latgen.round_to_f32(src)
         for r in range(src.shape[0]):
             assert rel_err(got[r], och.sign_apply(u_r, s_r[r], alpha, LMAX)) < 1e-6
+
+
+def test_batched_full_degree_sampled(ovl):
+    """The batched workload as the benchmark runs it -- stout-smeared fields, two-row link reads,
+    the tuned launch configuration, degree 300 (299 K applications) -- with the 8^3x16 and 12^3x24
+    outputs (sampled lattices the oracle evaluates in seconds) compared element by element with
+    the oracle on the same rounded inputs; the 16^3x32 sources are checked for finiteness and
+    against the single-problem launch."""
+    alpha = och.coeffs_sign_interp(300, 0.05)
+    p = ovl.Polynomial(alpha, LMAX)
+    shapes = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
+    fields, probs = [], []
+    for i, (dims, nrhs) in enumerate(shapes):
+        u = latgen.smeared_field(dims, latgen.seed_for("gauge", 4, i))
+        if nrhs == 12:
+            src = np.stack([latgen.point_source(dims, s, c) for s in range(4) for c in range(3)])
+        else:
+            src = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 4, i), nrhs=1)
+        g = ovl.GaugeField(dev(u), "f32")
+        g.reconstruct()
+        fields.append((u, src))
+        probs.append((g, dev(src, torch.complex64)))
+    outs = [torch.empty_like(x) for _, x in probs]
+    ovl.autotune(probs, p, outs=outs)
+    print(f"batch launch configuration {ovl.batch_launch_config(probs)}", flush=True)
+    outs = ovl.batch_sign_apply(p, probs, outs)
+    for item in (1, 5):
+        u, src = fields[item]
+        ref = och.poly_apply(complete_third_row(latgen.round_to_f32(u)),
+                             latgen.round_to_f32(src[0]), alpha, LMAX)
+        assert rel_err(host(outs[item])[0], ref) < 1e-6
+    got0 = host(outs[0])
+    assert np.isfinite(got0).all()
+    single = host(ovl.sign_apply(probs[0][0], p, probs[0][1]))
+    assert rel_err(got0, single) < 1e-6
+    for g, _ in probs:
+        assert g.flags() == 0
 
 
 def test_force_24x24x24x48(ovl):
