@@ -4,6 +4,9 @@ in seconds compared element by element.  Elsewhere the oracle cannot run the ben
 Chebyshev degrees at these volumes in a test, so the polynomial degree is lowered: every launch is the same kernel in the same configuration as in the
 benchmark (the degree only sets how many steps run), and every output element is compared with
 the FP64 oracle on the same rounded inputs."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -131,3 +134,31 @@ def test_force_24x24x24x48(ovl):
     ref = oforce.sign_force(latgen.round_to_f32(u), latgen.round_to_f32(chi),
                             latgen.round_to_f32(psi), alpha, LMAX)
     assert rel_err(got, ref) < 1e-6
+
+
+def test_force_24x24x24x48_full_degree_directional(ovl):
+    """The force workload as the benchmark runs it -- 24^3x48 stout-smeared links, FP32, degree 299,
+    checkpoint stride 18 -- projected on seeded Gaussian directions Y: Re sum tr(G^+ Y) against
+    the oracle's forward-mode derivative along Y (tests/golden/force_directional_24x24x24x48.json,
+    written by make_force_directional.py from oracle/ only), on the same FP32-rounded inputs and
+    on the exact ones."""
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "force_directional_24x24x24x48.json")))
+    dims = tuple(ref["dims"])
+    u = latgen.smeared_field(dims, ref["seeds"]["gauge"])
+    psi = latgen.gaussian_spinor(dims, ref["seeds"]["psi"])
+    chi = latgen.gaussian_spinor(dims, ref["seeds"]["chi"])
+    alpha = och.coeffs_sign_interp(ref["degree"], ref["eps"])
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, ref["lmax"])
+    G = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64),
+                            ckpt_stride=18))
+    for k, seed in enumerate(ref["direction_seeds"]):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        y = rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape)
+        dl = float(np.real(np.vdot(G, y)))
+        same, exact = ref["values"]["f32_rounded"][k], ref["values"]["exact"][k]
+        print(f"direction {seed}: device {dl:.9e}, oracle (rounded inputs) {same:.9e}, "
+              f"(exact inputs) {exact:.9e}", flush=True)
+        assert abs(dl - same) < 1e-6 * abs(same)
+        assert abs(dl - exact) < 1e-6 * abs(exact)
