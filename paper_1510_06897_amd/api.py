@@ -276,7 +276,7 @@ def overlap_solve(g: GaugeField, poly: Polynomial, b, mu: float, defl: Deflation
 
 def overlap_solve_gmresr(g: GaugeField, poly: Polynomial, b, mu: float, defl: Deflation = None,
                          g_inner: GaugeField = None, defl_inner: Deflation = None,
-                         tol: float = 1e-13, inner_tol: float = 0.1, inner_poly_tol: float = 1e-3,
+                         tol: float = 1e-13, inner_tol: float = 0.1, inner_poly_tol: float = 0.03,
                          relax: bool = True, max_outer: int = 64, max_inner: int = 20000,
                          out=None):
     """x with D[mu] x = b (FP64) by GMRESR around inner CG solves in the precision of g_inner
