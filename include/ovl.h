@@ -244,7 +244,8 @@ int ovl_stout_smear(const int32_t dims[4], void *U_out, const void *U_in, double
  * the contributions of all staples that contain it (no atomics: deterministic).
  *   G_thin, G_smeared, U_thin  caller-owned device arrays in the layout above, complex double,
  *                pairwise non-overlapping; G_smeared and U_thin are unchanged.
- * Allocates steps + 3 link fields of work space.  Asynchronous on `stream`.  Errors as
+ * Allocates up to 2 steps + 2 link fields of work space (the forward levels and their staple sums,
+ * dL/dC, the direct part, two derivative fields).  Asynchronous on `stream`.  Errors as
  * ovl_stout_smear. */
 int ovl_stout_backward(const int32_t dims[4], void *G_thin, const void *G_smeared,
                        const void *U_thin, double rho, double eps, int steps, void *stream);

@@ -2914,7 +2914,7 @@ int ovl_stout_smear(const int32_t dims[4], void *U_out, const void *U_in, double
   const double2 *cur = (const double2 *)U_in;
   for (int k = 0; k < steps; ++k) {
     double2 *dst = k == steps - 1 ? (double2 *)U_out : (double2 *)((char *)sc.p + (k % 2) * fb);
-    stout_step_kernel<<<grid, 256, 0, s>>>(cur, dst, wp, wr, geo);
+    stout_step_kernel<<<grid, 256, 0, s>>>(cur, dst, nullptr, wp, wr, geo);
     HIP_TRY(hipGetLastError());
     cur = dst;
   }
@@ -2939,28 +2939,32 @@ int ovl_stout_backward(const int32_t dims[4], void *G_thin, const void *G_smeare
   }
   double wp, wr;
   stout_weights(rho, eps, wp, wr);
-  // work fields: levels 1 .. steps-1 of the forward smearing, Gamma, the direct part and two
+  // work fields: levels 1 .. steps-1 of the forward smearing and the staple sums of levels
+  // 0 .. steps-2 (both from the regenerating forward pass), Gamma, the direct part and two
   // derivative fields between the steps
   const size_t fb = (bytes + 255) / 256 * 256;
   const int nlev = steps - 1;
   const int nder = steps >= 3 ? 2 : (steps == 2 ? 1 : 0);
   Scratch sc;
-  if ((rc = scratch_alloc(sc, (size_t)(nlev + 2 + nder) * fb, s))) return rc;
+  if ((rc = scratch_alloc(sc, (size_t)(2 * nlev + 2 + nder) * fb, s))) return rc;
   char *base = (char *)sc.p;
   auto field = [&](int i) { return (double2 *)(base + (size_t)i * fb); };
-  double2 *gam = field(nlev), *dir = field(nlev + 1);
+  double2 *gam = field(2 * nlev), *dir = field(2 * nlev + 1);
   const dim3 grid((unsigned)((geo.V + 255) / 256), 4);
-  std::vector<const double2 *> lev(steps);
+  std::vector<const double2 *> lev(steps), stap(steps, nullptr);
   lev[0] = (const double2 *)U_thin;
   for (int k = 1; k < steps; ++k) {
-    stout_step_kernel<<<grid, 256, 0, s>>>(lev[k - 1], field(k - 1), wp, wr, geo);
+    stout_step_kernel<<<grid, 256, 0, s>>>(lev[k - 1], field(k - 1), field(nlev + k - 1), wp, wr,
+                                           geo);
     HIP_TRY(hipGetLastError());
     lev[k] = field(k - 1);
+    stap[k - 1] = field(nlev + k - 1);
   }
   const double2 *gin = (const double2 *)G_smeared;
   for (int k = steps - 1; k >= 0; --k) {
-    double2 *gout = k == 0 ? (double2 *)G_thin : field(nlev + 2 + (nder == 2 ? 1 - (k & 1) : 0));
-    stout_back_local_kernel<<<grid, 256, 0, s>>>(lev[k], gin, gam, dir, wp, wr, geo);
+    double2 *gout =
+        k == 0 ? (double2 *)G_thin : field(2 * nlev + 2 + (nder == 2 ? 1 - (k & 1) : 0));
+    stout_back_local_kernel<<<grid, 256, 0, s>>>(lev[k], stap[k], gin, gam, dir, wp, wr, geo);
     HIP_TRY(hipGetLastError());
     stout_back_gather_kernel<<<grid, 256, 0, s>>>(lev[k], gam, dir, gout, wp, wr, geo);
     HIP_TRY(hipGetLastError());

@@ -295,14 +295,16 @@ __device__ inline M3 staple_sum(const double2 *__restrict__ U, const SiteCoord &
 }
 
 // One smearing step: out_mu(x) = exp(TA(C_mu(x) U_mu(x)^+)) U_mu(x).  Grid (ceil(V / 256), 4).
+// C_out (nullable) receives the staple sums for the chain rule.
 __global__ void __launch_bounds__(256)
-    stout_step_kernel(const double2 *__restrict__ U, double2 *__restrict__ out, double wp, double wr,
-                      Geom g) {
+    stout_step_kernel(const double2 *__restrict__ U, double2 *__restrict__ out,
+                      double2 *__restrict__ C_out, double wp, double wr, Geom g) {
   const int site = blockIdx.x * 256 + threadIdx.x;
   const int mu = blockIdx.y;
   if (site >= g.V) return;
   const SiteCoord x = site_coord(site, g);
   const M3 c = staple_sum(U, x, mu, wp, wr, g);
+  if (C_out) store_m3(C_out, mu, site, g.V, c);
   const M3 u = load_m3(U, mu, site, g.V);
   const M3 e = m3_exp(m3_ta(m3_muld(c, u)));
   store_m3(out, mu, site, g.V, m3_mul(e, u));
@@ -313,16 +315,16 @@ __global__ void __launch_bounds__(256)
 //   dL/dE = G' U^+,  dL/dM = L(M^+, dL/dE)  (the adjoint of the Frechet derivative of exp at M),
 //   dL/dOmega = (g - g^+)/2 - (i/3) Im tr(g) for g = dL/dM  (M = TA(Omega)),
 //   Gamma = dL/dC = dL/dOmega U,   direct = E^+ G' + (dL/dOmega)^+ C.
-// Writes Gamma and the direct part of dL/dU.
+// Writes Gamma and the direct part of dL/dU.  C_in (nullable): the level's staple sums.
 __global__ void __launch_bounds__(256)
-    stout_back_local_kernel(const double2 *__restrict__ U, const double2 *__restrict__ gout,
-                            double2 *__restrict__ gamma, double2 *__restrict__ direct, double wp,
-                            double wr, Geom g) {
+    stout_back_local_kernel(const double2 *__restrict__ U, const double2 *__restrict__ C_in,
+                            const double2 *__restrict__ gout, double2 *__restrict__ gamma,
+                            double2 *__restrict__ direct, double wp, double wr, Geom g) {
   const int site = blockIdx.x * 256 + threadIdx.x;
   const int mu = blockIdx.y;
   if (site >= g.V) return;
-  const SiteCoord x = site_coord(site, g);
-  const M3 c = staple_sum(U, x, mu, wp, wr, g);
+  // the staple sums of this level from the forward pass when available
+  const M3 c = C_in ? load_m3(C_in, mu, site, g.V) : staple_sum(U, site_coord(site, g), mu, wp, wr, g);
   const M3 u = load_m3(U, mu, site, g.V);
   const M3 m = m3_ta(m3_muld(c, u));
   const M3 gp = load_m3(gout, mu, site, g.V);
@@ -371,27 +373,35 @@ __global__ void __launch_bounds__(256)
               SiteCoord x;
               const int xs = site_at(y, xo, g);
               x = site_coord(xs, g);
+              // t = A^+ Gamma B^+ with A, B the products before and after step k (an empty
+              // product is the unit matrix and is not multiplied)
               int pos[4] = {0, 0, 0, 0};
-              M3 a = m3_unit();
-              for (int j = 0; j < k; ++j) {
+              M3 t = load_m3(gamma, mu, xs, g.V);
+              if (k > 0) {
                 int dj, sj;
-                path_step(mu, nu, s, shape, j, dj, sj);
-                a = m3_mul(a, path_factor(U, x, pos, dj, sj, g));
+                path_step(mu, nu, s, shape, 0, dj, sj);
+                M3 a = path_factor(U, x, pos, dj, sj, g);
+                for (int j = 1; j < k; ++j) {
+                  path_step(mu, nu, s, shape, j, dj, sj);
+                  a = m3_mul(a, path_factor(U, x, pos, dj, sj, g));
+                }
+                t = m3_dmul(a, t);
               }
-              // skip step k itself
               {
-                int dj, sj;
+                int dj, sj;  // step past link k itself
                 path_step(mu, nu, s, shape, k, dj, sj);
                 pos[dj] += sj;
               }
-              M3 b = m3_unit();
-              for (int j = k + 1; j < len; ++j) {
+              if (k + 1 < len) {
                 int dj, sj;
-                path_step(mu, nu, s, shape, j, dj, sj);
-                b = m3_mul(b, path_factor(U, x, pos, dj, sj, g));
+                path_step(mu, nu, s, shape, k + 1, dj, sj);
+                M3 b = path_factor(U, x, pos, dj, sj, g);
+                for (int j = k + 2; j < len; ++j) {
+                  path_step(mu, nu, s, shape, j, dj, sj);
+                  b = m3_mul(b, path_factor(U, x, pos, dj, sj, g));
+                }
+                t = m3_muld(t, b);
               }
-              const M3 gm = load_m3(gamma, mu, xs, g.V);
-              M3 t = m3_muld(m3_dmul(a, gm), b);  // A^+ Gamma B^+
               if (sgn < 0) t = m3_dag(t);
               acc = m3_axpy(acc, w, t);
             }
