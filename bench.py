@@ -33,11 +33,11 @@ HBM_PEAK_GBPS = 8000.0
 LMAX = 6.5
 LMAX_BF16 = LMAX * (1 + 2.0 ** -6)   # BF16 links are not unitary: margin on ||K||
 # batched workload (lattice, right-hand sides); item 0 carries the 12 point sources
-C4_SHAPES = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
-C4_DEGREE, C4_EPS = 300, 0.05
-C3_DIMS, C3_DEGREE, C3_NEV = (16, 16, 16, 32), 400, 24
-C5_DIMS, C5_DEGREE, C5_EPS, C5_STRIDE = (24, 24, 24, 48), 300, 0.05, 18
-C2_DIMS, C2_DEGREE, C2_NEV, MUS = (8, 8, 8, 16), 200, 12, (0.01, 0.05)
+BATCH_SHAPES = [((16, 16, 16, 32), 12)] + [((8, 8, 8, 16), 1)] * 4 + [((12, 12, 12, 24), 1)] * 2
+BATCH_DEGREE, BATCH_EPS = 300, 0.05
+BF16_DIMS, BF16_DEGREE, BF16_NEV = (16, 16, 16, 32), 400, 24
+FORCE_DIMS, FORCE_DEGREE, FORCE_EPS, FORCE_STRIDE = (24, 24, 24, 48), 300, 0.05, 18
+OVL_DIMS, OVL_DEGREE, OVL_NEV, MUS = (8, 8, 8, 16), 200, 12, (0.01, 0.05)
 # algorithmic bytes per site: each link, input and output read or written once
 BYTES_LINK = {"f64": 576, "f32": 288, "bf16": 144}          # 4 x 3 x 3 complex
 BYTES_LINK_R12 = {"f64": 384, "f32": 192, "bf16": 96}       # two rows read
@@ -90,10 +90,10 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the BF16/24-mode, force, overlap, 24^3x48 and "
                          "stream measurements")
-    ap.add_argument("--profile", choices=["c4", "c3", "force", "c2", "dw", "dw2", "proj", "copy"],
-                    help="run one part only, for rocprofv3: c4 = the timed batched loop of the "
-                         "headline (--steps batches), c3 = the BF16 24-mode loop, force = the "
-                         "FP32 force at 24^3x48, c2 = the FP32 overlap loop, dw = K at 24^3x48 "
+    ap.add_argument("--profile", choices=["batch", "bf16", "force", "overlap", "dw", "dw2", "proj", "copy"],
+                    help="run one part only, for rocprofv3: batch = the timed batched loop of the "
+                         "headline (--steps batches), bf16 = the BF16 24-mode loop, force = the "
+                         "FP32 force at 24^3x48, overlap = the FP32 overlap loop, dw = K at 24^3x48 "
                          "in FP64/FP32/BF16 (dw2: two-row link reads), proj = the FP32 "
                          "matrix-core projection at 16^3x32 with 24 vectors, copy = two plain "
                          "256 MiB device copies (scale of the byte counters)")
@@ -124,37 +124,37 @@ def rel(a, b):
 _FIELDS = {}
 
 
-def c4_inputs(latgen):
+def batch_inputs(latgen):
     """[(dims, links, sources)] of the batched workload (cached)."""
-    if "c4" not in _FIELDS:
+    if "batch" not in _FIELDS:
         out = []
-        for i, (dims, nrhs) in enumerate(C4_SHAPES):
+        for i, (dims, nrhs) in enumerate(BATCH_SHAPES):
             u = latgen.smeared_field(dims, latgen.seed_for("gauge", 4, i))
             if nrhs == 12:
                 src = np.stack([latgen.point_source(dims, s, c) for s in range(4) for c in range(3)])
             else:
                 src = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 4, i), nrhs=1)
             out.append((dims, u, src))
-        _FIELDS["c4"] = out
-    return _FIELDS["c4"]
+        _FIELDS["batch"] = out
+    return _FIELDS["batch"]
 
 
-def c5_inputs(latgen):
+def force_inputs(latgen):
     """Links, psi, chi of the force workload: the seeds of the stored oracle derivatives."""
-    if "c5" not in _FIELDS:
-        u = latgen.smeared_field(C5_DIMS, latgen.seed_for("gauge", 5))
-        psi = latgen.gaussian_spinor(C5_DIMS, latgen.seed_for("spinor", 5))
-        chi = latgen.gaussian_spinor(C5_DIMS, latgen.seed_for("spinor", 5, 1))
-        _FIELDS["c5"] = (u, psi, chi)
-    return _FIELDS["c5"]
+    if "force" not in _FIELDS:
+        u = latgen.smeared_field(FORCE_DIMS, latgen.seed_for("gauge", 5))
+        psi = latgen.gaussian_spinor(FORCE_DIMS, latgen.seed_for("spinor", 5))
+        chi = latgen.gaussian_spinor(FORCE_DIMS, latgen.seed_for("spinor", 5, 1))
+        _FIELDS["force"] = (u, psi, chi)
+    return _FIELDS["force"]
 
 
 # ------------------------------------------------------------------------------------------------
 # headline: the batched sign function
-def c4_handles(ovl, torch, dev, latgen, store, two_row):
+def batch_handles(ovl, torch, dev, latgen, store, two_row):
     probs = []
     cdt = torch.complex128 if store == "f64" else torch.complex64
-    for dims, u, src in c4_inputs(latgen):
+    for dims, u, src in batch_inputs(latgen):
         g = ovl.GaugeField(torch.from_numpy(u).to(dev), store)
         if two_row:
             g.reconstruct()
@@ -162,10 +162,10 @@ def c4_handles(ovl, torch, dev, latgen, store, two_row):
     return probs
 
 
-def c4_bytes_per_step(store, two_row):
+def batch_bytes_per_step(store, two_row):
     link = (BYTES_LINK_R12 if two_row else BYTES_LINK)[store]
     total = 0.0
-    for dims, nrhs in C4_SHAPES:
+    for dims, nrhs in BATCH_SHAPES:
         v = int(np.prod(dims))
         total += v * (link + nrhs * STEP_STREAMS * BYTES_SPIN[store])
     return total
@@ -184,14 +184,14 @@ def kernel_name(cfg, store, two_row, table=True):
             f"R12={int(two_row)},RB={rb}>")
 
 
-def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
+def measure_batch(ovl, torch, dev, latgen, steps, warmup, profile=False):
     t0 = time.time()
-    alpha = ovl.cheb_sign_coeffs(C4_DEGREE, C4_EPS)
+    alpha = ovl.cheb_sign_coeffs(BATCH_DEGREE, BATCH_EPS)
     p32 = ovl.Polynomial(alpha, LMAX)
-    probs = c4_handles(ovl, torch, dev, latgen, "f32", two_row=True)
+    probs = batch_handles(ovl, torch, dev, latgen, "f32", two_row=True)
     outs = [torch.empty_like(x) for _, x in probs]
-    n_rhs = sum(nrhs for _, nrhs in C4_SHAPES)
-    log(f"C4 inputs {time.time() - t0:.1f} s")
+    n_rhs = sum(nrhs for _, nrhs in BATCH_SHAPES)
+    log(f"batch inputs {time.time() - t0:.1f} s")
     res = {}
     if not profile:
         cfg_default = ovl.batch_launch_config(probs)
@@ -199,7 +199,7 @@ def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
         res["default_config"] = {"config": list(cfg_default), "ms_per_batch": round(ms_default, 3)}
     us_tune = ovl.autotune(probs, p32, outs=outs)
     cfg = ovl.batch_launch_config(probs)
-    log(f"C4 autotuned {cfg} ({us_tune:.1f} us per step in the tuner)")
+    log(f"batch autotuned {cfg} ({us_tune:.1f} us per step in the tuner)")
     # the timed loop: warm-up, then exactly `steps` batches, with the library's event pair around
     # the consecutive plain steps of every evaluation (the dominant kernel's average duration)
     for _ in range(warmup):
@@ -217,7 +217,7 @@ def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
     ovl.timing_enable(False)
     k_ms, k_n = ovl.timing_read(0)
     ms = e0.elapsed_time(e1) / steps
-    log(f"C4 batched FP32 two-row: {ms:.3f} ms/batch, step kernel {1e3 * k_ms / k_n:.2f} us")
+    log(f"batch FP32 two-row: {ms:.3f} ms/batch, step kernel {1e3 * k_ms / k_n:.2f} us")
     if profile:
         return None
     for g, _ in probs:
@@ -227,7 +227,7 @@ def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
     res["speedup_tuned_vs_default"] = round(res["default_config"]["ms_per_batch"] / ms, 3)
     del probs
     # full link reads (tuned for that form), unbatched FP32 and plain FP64
-    probs_f = c4_handles(ovl, torch, dev, latgen, "f32", two_row=False)
+    probs_f = batch_handles(ovl, torch, dev, latgen, "f32", two_row=False)
     ovl.autotune(probs_f, p32, outs=outs)
     ms_full = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs_f, outs), 5)
     res["full_link_reads"] = {"config": list(ovl.batch_launch_config(probs_f)),
@@ -236,7 +236,7 @@ def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
     ms_u = gpu_ms(torch, lambda: [ovl.sign_apply(g, p32, x, out=o)
                                   for (g, x), o in zip(probs_f, outs)], 3)
     del probs_f
-    probs64 = c4_handles(ovl, torch, dev, latgen, "f64", two_row=False)
+    probs64 = batch_handles(ovl, torch, dev, latgen, "f64", two_row=False)
     outs64 = [torch.empty_like(x) for _, x in probs64]
     ms_64 = gpu_ms(torch, lambda: [ovl.sign_apply(g, p32, x, out=o)
                                    for (g, x), o in zip(probs64, outs64)], 2)
@@ -245,30 +245,30 @@ def measure_c4(ovl, torch, dev, latgen, steps, warmup, profile=False):
     res["plain_f64_ms"] = round(ms_64, 3)
     res["speedup_vs_unbatched_f32"] = round(ms_u / ms, 3)
     res["speedup_vs_plain_f64"] = round(ms_64 / ms, 3)
-    log(f"C4: full reads {ms_full:.2f} ms, unbatched {ms_u:.2f} ms, plain FP64 {ms_64:.2f} ms")
+    log(f"batch: full reads {ms_full:.2f} ms, unbatched {ms_u:.2f} ms, plain FP64 {ms_64:.2f} ms")
     return res
 
 
 # ------------------------------------------------------------------------------------------------
-def measure_c3(ovl, torch, dev, latgen, low_modes, reps, profile=False):
+def measure_bf16(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     """BF16 links, FP32 spinors/accumulation, FP64 reductions, degree 400 (N = 399), 24 deflated
     modes found on the device, FP32 matrix-core projection."""
     t0 = time.time()
-    u = latgen.smeared_field(C3_DIMS, latgen.seed_for("gauge", 3))
-    psi = latgen.gaussian_spinor(C3_DIMS, latgen.seed_for("spinor", 3))
+    u = latgen.smeared_field(BF16_DIMS, latgen.seed_for("gauge", 3))
+    psi = latgen.gaussian_spinor(BF16_DIMS, latgen.seed_for("spinor", 3))
     du = torch.from_numpy(u).to(dev)
     g64 = ovl.GaugeField(du, "f64")
     gbf = ovl.GaugeField(du, "bf16")
     # a 128-vector block holds the 48-mode doubler cluster around the 24th eigenvalue whole
     t1 = time.time()
-    lam, phi, res_e, eps = low_modes(g64, C3_NEV, LMAX, block=128, cut=1.0)
+    lam, phi, res_e, eps = low_modes(g64, BF16_NEV, LMAX, block=128, cut=1.0)
     t_eig = time.time() - t1
-    alpha = ovl.cheb_sign_coeffs(C3_DEGREE, eps)
+    alpha = ovl.cheb_sign_coeffs(BF16_DEGREE, eps)
     pbf = ovl.Polynomial(alpha, LMAX_BF16)
     dbf = ovl.Deflation(phi, lam, "f32")
     x32 = torch.from_numpy(psi).to(dev).to(torch.complex64)
     y32 = torch.empty_like(x32)
-    log(f"C3 set-up {time.time() - t0:.1f} s (eigen-solve {t_eig:.1f} s, residual {res_e.max():.1e})")
+    log(f"BF16/24-mode set-up {time.time() - t0:.1f} s (eigen-solve {t_eig:.1f} s, residual {res_e.max():.1e})")
     if profile:
         for _ in range(reps):
             ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
@@ -291,8 +291,8 @@ def measure_c3(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     ms_r12 = gpu_ms(torch, lambda: ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32), reps)
     ms_proj = gpu_ms(torch, lambda: ovl.defl_project(dbf, x32), 20)
     assert gbf.flags() == 0
-    vol = int(np.prod(C3_DIMS))
-    proj_flops = 8.0 * C3_NEV * 12 * vol    # complex multiply-add = 8 real flops
+    vol = int(np.prod(BF16_DIMS))
+    proj_flops = 8.0 * BF16_NEV * 12 * vol    # complex multiply-add = 8 real flops
     out = {"ms_per_apply": ms_bf, "kernel_ms": k_ms, "kernel_launches": k_n,
            "config": list(cfg),
            "plain_f64_ms_per_apply": round(ms_64, 3),
@@ -303,48 +303,48 @@ def measure_c3(ovl, torch, dev, latgen, low_modes, reps, profile=False):
            "projection_us": round(ms_proj * 1e3, 2),
            "projection_mfma_TFLOPs": round(proj_flops / (ms_proj * 1e-3) / 1e12, 3),
            "projection_frac_of_fp32_matrix_peak": round(proj_flops / (ms_proj * 1e-3) / 157.3e12, 5),
-           "projection_GBps": round(C3_NEV * 12 * vol * 8 / (ms_proj * 1e-3) / 1e9, 1)}
-    log(f"C3 BF16 24 modes: {ms_bf:.2f} ms/apply (two-row {ms_r12:.2f}), FP64 {ms_64:.2f} ms")
-    _FIELDS["c3"] = (u, psi, float(eps))
+           "projection_GBps": round(BF16_NEV * 12 * vol * 8 / (ms_proj * 1e-3) / 1e9, 1)}
+    log(f"BF16 24 modes: {ms_bf:.2f} ms/apply (two-row {ms_r12:.2f}), FP64 {ms_64:.2f} ms")
+    _FIELDS["bf16"] = (u, psi, float(eps))
     return out
 
 
 # ------------------------------------------------------------------------------------------------
 def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     t0 = time.time()
-    u, psi, chi = c5_inputs(latgen)
+    u, psi, chi = force_inputs(latgen)
     g32 = ovl.GaugeField(torch.from_numpy(u).to(dev), "f32")
-    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(C5_DEGREE, C5_EPS), LMAX)
+    pf = ovl.Polynomial(ovl.cheb_sign_coeffs(FORCE_DEGREE, FORCE_EPS), LMAX)
     G = torch.empty((4, 3, 3) + tuple(psi.shape[-4:]), dtype=torch.complex64, device=dev)
     x32 = torch.from_numpy(psi).to(dev).to(torch.complex64)
     c32 = torch.from_numpy(chi).to(dev).to(torch.complex64)
     log(f"force inputs {time.time() - t0:.1f} s")
     if profile:
         for _ in range(reps):
-            ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G)
+            ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
         torch.cuda.synchronize()
         return None
-    ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G)
+    ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
     torch.cuda.synchronize()
     ovl.timing_read(1)
     ovl.timing_enable(True)
-    ms_f = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G),
+    ms_f = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G),
                   reps, warmup=0)
     ovl.timing_enable(False)
     v_ms, v_n = ovl.timing_read(1)
     # one segment: every t_m regenerated into HBM once (N vectors) instead of sqrt(N) checkpoints
-    ms_all = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_DEGREE,
+    ms_all = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_DEGREE,
                                                   out=G), 1)
     g32.reconstruct()
-    ms_r12 = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=C5_STRIDE,
+    ms_r12 = gpu_ms(torch, lambda: ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE,
                                                   out=G), reps)
     # the HMC chain on thin links (Sec. 1; Sec. 2: 3 steps of over-improved stout smearing,
     # rho 0.1, eps -0.25): smear on the device, force on the smeared links, chain rule back
-    u_thin = torch.from_numpy(latgen.random_su3_field(C5_DIMS, latgen.seed_for("gauge", 5))).to(dev)
+    u_thin = torch.from_numpy(latgen.random_su3_field(FORCE_DIMS, latgen.seed_for("gauge", 5))).to(dev)
     us = torch.empty_like(u_thin)
     ms_smear = gpu_ms(torch, lambda: ovl.stout_smear(u_thin, 0.1, -0.25, 3, out=us), 2)
     g_s = ovl.GaugeField(us, "f32")
-    ms_fs = gpu_ms(torch, lambda: ovl.sign_force(g_s, pf, c32, x32, ckpt_stride=C5_STRIDE, out=G), 1)
+    ms_fs = gpu_ms(torch, lambda: ovl.sign_force(g_s, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G), 1)
     g64 = G.to(torch.complex128)
     gt = torch.empty_like(u_thin)
     ms_back = gpu_ms(torch, lambda: ovl.stout_backward(u_thin, g64, 0.1, -0.25, 3, out=gt), 2)
@@ -359,9 +359,9 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     # bytes of the link-VJP launches: every pair reads a and t once (FP32 spinors), the FP64
     # running sum of G is written by the first segment, read and written by the middle ones and
     # read by the last, which writes G in FP32
-    vol = int(np.prod(C5_DIMS))
-    n = C5_DEGREE - 1
-    nseg = (n + C5_STRIDE - 1) // C5_STRIDE
+    vol = int(np.prod(FORCE_DIMS))
+    n = FORCE_DEGREE - 1
+    nseg = (n + FORCE_STRIDE - 1) // FORCE_STRIDE
     vjp_bytes = vol * (n * 2 * BYTES_SPIN["f32"] + (nseg - 1) * 2 * 36 * 16 + 36 * 8)
     out = {"ms_per_force": ms_f, "forces_per_s": round(1e3 / ms_f, 3),
            "ms_per_force_stride_299": round(ms_all, 2),
@@ -374,17 +374,17 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
 
 
 # ------------------------------------------------------------------------------------------------
-def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
+def measure_overlap(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     t0 = time.time()
-    u = latgen.smeared_field(C2_DIMS, latgen.seed_for("gauge", 2))
-    psi = latgen.gaussian_spinor(C2_DIMS, latgen.seed_for("spinor", 2))
+    u = latgen.smeared_field(OVL_DIMS, latgen.seed_for("gauge", 2))
+    psi = latgen.gaussian_spinor(OVL_DIMS, latgen.seed_for("spinor", 2))
     d_u = torch.from_numpy(u).to(dev)
     g64 = ovl.GaugeField(d_u, "f64")
     g32 = ovl.GaugeField(d_u, "f32")
     # the smooth synthetic fields keep K close to its free spectrum: 48 near-degenerate doubler
     # modes at |lambda| ~ 0.5, so the filtered block (64) must hold that whole cluster
-    lam, phi, res_e, eps = low_modes(g64, C2_NEV, LMAX, block=64, cut=1.0)
-    alpha = ovl.cheb_sign_coeffs(C2_DEGREE, eps)
+    lam, phi, res_e, eps = low_modes(g64, OVL_NEV, LMAX, block=64, cut=1.0)
+    alpha = ovl.cheb_sign_coeffs(OVL_DEGREE, eps)
     poly = ovl.Polynomial(alpha, LMAX)
     defl64 = ovl.Deflation(phi, lam, "f64")
     defl32 = ovl.Deflation(phi, lam, "f32")
@@ -392,7 +392,7 @@ def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     psi32 = psi64.to(torch.complex64)
     out64 = torch.empty_like(psi64)
     out32 = torch.empty_like(psi32)
-    log(f"C2 set-up {time.time() - t0:.1f} s (eps {eps:.4f})")
+    log(f"overlap 8^3x16 set-up {time.time() - t0:.1f} s (eps {eps:.4f})")
 
     def step(form, i):
         mu = MUS[i % 2]
@@ -412,7 +412,7 @@ def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
         return None
     ms32 = gpu_ms(torch, lambda: [step("f32", i) for i in range(reps)], 1, warmup=0) / reps
     ms64 = gpu_ms(torch, lambda: [step("f64", i) for i in range(reps)], 1, warmup=0) / reps
-    psi12 = torch.from_numpy(latgen.gaussian_spinor(C2_DIMS, latgen.seed_for("spinor", 2, 1),
+    psi12 = torch.from_numpy(latgen.gaussian_spinor(OVL_DIMS, latgen.seed_for("spinor", 2, 1),
                                                     nrhs=12)).to(dev).to(torch.complex64)
     out12 = torch.empty_like(psi12)
     ms12 = gpu_ms(torch, lambda: ovl.overlap_apply(g32, poly, psi12, MUS[0], defl=defl32,
@@ -438,8 +438,8 @@ def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
         solves[label] = {"s": round(time.perf_counter() - t0s, 4), "outer_steps": n_out,
                          "inner_cg_iterations": n_in, "rel_residual": sres}
     assert g32.flags() == 0 and g64.flags() == 0
-    log(f"C2 overlap: FP32 {ms32:.3f} ms, FP64 {ms64:.3f} ms, 12 sources {ms12:.3f} ms")
-    _FIELDS["c2"] = (u, psi, float(eps))
+    log(f"overlap 8^3x16: FP32 {ms32:.3f} ms, FP64 {ms64:.3f} ms, 12 sources {ms12:.3f} ms")
+    _FIELDS["overlap"] = (u, psi, float(eps))
     return {"ms_per_apply_f32": round(ms32, 4), "ms_per_apply_f64": round(ms64, 4),
             "applies_per_s_f32": round(1e3 / ms32, 1), "applies_per_s_f64": round(1e3 / ms64, 1),
             "speedup_f32_over_f64": round(ms64 / ms32, 3),
@@ -454,12 +454,12 @@ def measure_c2(ovl, torch, dev, latgen, low_modes, reps, profile=False):
 def measure_big(ovl, torch, dev, latgen, profile=None, reps=50):
     """K and sign(K) psi at 24^3x48 (the force lattice; working set above the 256 MB Infinity
     Cache) in FP64, FP32 and BF16-link storage, full and two-row link reads."""
-    u, psi, _ = c5_inputs(latgen)
+    u, psi, _ = force_inputs(latgen)
     d_u = torch.from_numpy(u).to(dev)
     d_p = torch.from_numpy(psi).to(dev)
-    vol = int(np.prod(C5_DIMS))
+    vol = int(np.prod(FORCE_DIMS))
     dw, sign_big = {}, {}
-    p_big = ovl.Polynomial(ovl.cheb_sign_coeffs(C2_DEGREE, 0.05), LMAX_BF16)
+    p_big = ovl.Polynomial(ovl.cheb_sign_coeffs(OVL_DEGREE, 0.05), LMAX_BF16)
     for store in ("f64", "f32", "bf16"):
         gb = ovl.GaugeField(d_u, store)
         x = d_p if store == "f64" else d_p.to(torch.complex64)
@@ -553,43 +553,43 @@ def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
     from oracle import deflation as odefl
     r32, rbf = latgen.round_to_f32, latgen.round_to_bf16
     jobs, gpu = [], {}
-    # C4: the headline form (FP32, two-row links, tuned batch launch) with the oracle's
+    # the batched headline form (FP32, two-row links, tuned batch launch) with the oracle's
     # coefficients; sampled right-hand sides: point source 5 of the 16^3x32 lattice, the first
     # 8^3x16 and the first 12^3x24 lattice
-    c4 = c4_inputs(latgen)
-    alpha4 = och.coeffs_sign_interp(C4_DEGREE, C4_EPS)
+    bat = batch_inputs(latgen)
+    alpha4 = och.coeffs_sign_interp(BATCH_DEGREE, BATCH_EPS)
     p4 = ovl.Polynomial(alpha4, LMAX)
-    probs = c4_handles(ovl, torch, dev, latgen, "f32", two_row=True)
+    probs = batch_handles(ovl, torch, dev, latgen, "f32", two_row=True)
     outs = ovl.batch_sign_apply(p4, probs)
     torch.cuda.synchronize()
     for item, r in ((0, 5), (1, 0), (5, 0)):
-        dims, u, src = c4[item]
-        name = f"c4_{'x'.join(map(str, dims))}_rhs{r}"
+        dims, u, src = bat[item]
+        name = f"batch_{'x'.join(map(str, dims))}_rhs{r}"
         gpu[name] = outs[item][r].cpu().to(torch.complex128).numpy()
         jobs.append((name + "|exact", "poly", (u, src[r], alpha4, LMAX)))
         jobs.append((name + "|same", "poly", (r32(u), r32(src[r]), alpha4, LMAX)))
     del probs, outs
-    # C3: BF16 links; a Gaussian basis orthonormalised by the oracle stands in for the low modes
+    # BF16 links; a Gaussian basis orthonormalised by the oracle stands in for the low modes
     # (same cost), with fixed eigenvalues
-    if "c3" in _FIELDS:
-        u, psi, eps = _FIELDS["c3"]
-        phi_o = odefl.cgs2(latgen.gaussian_spinor(C3_DIMS, 30301, nrhs=C3_NEV))
-        lam_o = np.linspace(-0.5, 0.5, C3_NEV) + 0.004
-        alpha3 = och.coeffs_sign_interp(C3_DEGREE, eps)
+    if "bf16" in _FIELDS:
+        u, psi, eps = _FIELDS["bf16"]
+        phi_o = odefl.cgs2(latgen.gaussian_spinor(BF16_DIMS, 30301, nrhs=BF16_NEV))
+        lam_o = np.linspace(-0.5, 0.5, BF16_NEV) + 0.004
+        alpha3 = och.coeffs_sign_interp(BF16_DEGREE, eps)
         gbf = ovl.GaugeField(torch.from_numpy(u).to(dev), "bf16")
         d3 = ovl.Deflation(torch.from_numpy(phi_o).to(dev), lam_o, "f32")
         p3 = ovl.Polynomial(alpha3, LMAX_BF16)
-        gpu["c3"] = ovl.sign_apply(gbf, p3, torch.from_numpy(psi).to(dev).to(torch.complex64),
+        gpu["bf16"] = ovl.sign_apply(gbf, p3, torch.from_numpy(psi).to(dev).to(torch.complex64),
                                    defl=d3).cpu().to(torch.complex128).numpy()
-        jobs.append(("c3|exact", "sign", (u, psi, alpha3, LMAX_BF16, phi_o, lam_o)))
-        jobs.append(("c3|same", "sign", (rbf(u), r32(psi), alpha3, LMAX_BF16, r32(phi_o), lam_o)))
+        jobs.append(("bf16|exact", "sign", (u, psi, alpha3, LMAX_BF16, phi_o, lam_o)))
+        jobs.append(("bf16|same", "sign", (rbf(u), r32(psi), alpha3, LMAX_BF16, r32(phi_o), lam_o)))
         del gbf, d3
-    # C2: the deflated overlap operator, FP32 and FP64
-    if "c2" in _FIELDS:
-        u, psi, eps = _FIELDS["c2"]
-        phi_o = odefl.cgs2(latgen.gaussian_spinor(C2_DIMS, 777, nrhs=C2_NEV))
-        lam_o = np.linspace(-0.52, 0.52, C2_NEV) + 0.003
-        alpha2 = och.coeffs_sign_interp(C2_DEGREE, eps)
+    # the deflated overlap operator on 8^3x16, FP32 and FP64
+    if "overlap" in _FIELDS:
+        u, psi, eps = _FIELDS["overlap"]
+        phi_o = odefl.cgs2(latgen.gaussian_spinor(OVL_DIMS, 777, nrhs=OVL_NEV))
+        lam_o = np.linspace(-0.52, 0.52, OVL_NEV) + 0.003
+        alpha2 = och.coeffs_sign_interp(OVL_DEGREE, eps)
         p2 = ovl.Polynomial(alpha2, LMAX)
         du = torch.from_numpy(u).to(dev)
         dphi = torch.from_numpy(phi_o).to(dev)
@@ -598,10 +598,10 @@ def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
             g = ovl.GaugeField(du, store)
             d = ovl.Deflation(dphi, lam_o, store)
             xs = x if store == "f64" else x.to(torch.complex64)
-            gpu[f"c2_{store}"] = ovl.overlap_apply(g, p2, xs, MUS[1], defl=d).cpu().to(
+            gpu[f"overlap_{store}"] = ovl.overlap_apply(g, p2, xs, MUS[1], defl=d).cpu().to(
                 torch.complex128).numpy()
-        jobs.append(("c2|exact", "overlap", (u, psi, MUS[1], alpha2, LMAX, phi_o, lam_o)))
-        jobs.append(("c2|same", "overlap", (r32(u), r32(psi), MUS[1], alpha2, LMAX, r32(phi_o),
+        jobs.append(("overlap|exact", "overlap", (u, psi, MUS[1], alpha2, LMAX, phi_o, lam_o)))
+        jobs.append(("overlap|same", "overlap", (r32(u), r32(psi), MUS[1], alpha2, LMAX, r32(phi_o),
                                             lam_o)))
     torch.cuda.synchronize()
     # CPU baseline: the oracle on a bounded sample of the headline batch, one thread, in this
@@ -609,15 +609,15 @@ def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
     # K applications on one 16^3x32 source (scaled linearly to 299)
     base = {}
     with threadpool_limits(limits=1):
-        for item, nk in ((1, C4_DEGREE - 1), (5, C4_DEGREE - 1), (0, 60)):
-            dims, u, src = c4[item]
+        for item, nk in ((1, BATCH_DEGREE - 1), (5, BATCH_DEGREE - 1), (0, 60)):
+            dims, u, src = bat[item]
             a = alpha4[: nk + 1]
             t0 = time.perf_counter()
             och.poly_apply(u, src[0], a, LMAX)
-            base[item] = (time.perf_counter() - t0) * (C4_DEGREE - 1) / nk
-    n_rhs = sum(nrhs for _, nrhs in C4_SHAPES)
+            base[item] = (time.perf_counter() - t0) * (BATCH_DEGREE - 1) / nk
+    n_rhs = sum(nrhs for _, nrhs in BATCH_SHAPES)
     t_batch = 12 * base[0] + 4 * base[1] + 2 * base[5]
-    sampled = sum(base[i] * (60 if i == 0 else C4_DEGREE - 1) / (C4_DEGREE - 1) for i in base)
+    sampled = sum(base[i] * (60 if i == 0 else BATCH_DEGREE - 1) / (BATCH_DEGREE - 1) for i in base)
     cpu = {"value": round(n_rhs / t_batch, 5), "unit": "sign(K)psi right-hand-side applies/s",
            "cores": 1, "kind": "oracle",
            "sample": f"FP64 NumPy oracle (forward Chebyshev recurrence), one thread: degree 299 on "
@@ -636,22 +636,22 @@ def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
     refs = {name: (y, sec) for name, y, sec in done}
     errs = {}
     for key in gpu:
-        base_name = key if not key.startswith("c2_") else "c2"
+        base_name = key if not key.startswith("overlap_") else "overlap"
         ex, same = refs[base_name + "|exact"][0], refs[base_name + "|same"][0]
         if key.endswith("_f64"):
             same = ex   # FP64 storage: the device sees the exact inputs
         errs[key] = {"vs_oracle_exact_inputs": rel(gpu[key], ex),
                      "vs_oracle_same_rounded_inputs": rel(gpu[key], same),
                      "oracle_s": round(refs[base_name + "|exact"][1], 1)}
-    # C5: the stored oracle derivatives along seeded directions (tests/golden)
-    if os.path.exists(GOLDEN_FORCE) and "c5" in _FIELDS:
+    # the force: the stored oracle derivatives along seeded directions (tests/golden)
+    if os.path.exists(GOLDEN_FORCE) and "force" in _FIELDS:
         ref = json.load(open(GOLDEN_FORCE))
-        u, psi, chi = c5_inputs(latgen)
+        u, psi, chi = force_inputs(latgen)
         g32 = ovl.GaugeField(torch.from_numpy(u).to(dev), "f32")
         pf = ovl.Polynomial(och.coeffs_sign_interp(ref["degree"], ref["eps"]), ref["lmax"])
         G = ovl.sign_force(g32, pf, torch.from_numpy(chi).to(dev).to(torch.complex64),
                            torch.from_numpy(psi).to(dev).to(torch.complex64),
-                           ckpt_stride=C5_STRIDE).cpu().to(torch.complex128).numpy()
+                           ckpt_stride=FORCE_STRIDE).cpu().to(torch.complex128).numpy()
         del g32
         e_ex, e_same = [], []
         for k, seed in enumerate(ref["direction_seeds"]):
@@ -661,7 +661,7 @@ def oracle_leg(ovl, torch, dev, latgen, results, workers=8):
             e_ex.append(abs(dl - ref["values"]["exact"][k]) / abs(ref["values"]["exact"][k]))
             e_same.append(abs(dl - ref["values"]["f32_rounded"][k])
                           / abs(ref["values"]["f32_rounded"][k]))
-        errs["c5_force"] = {"vs_oracle_exact_inputs": max(e_ex),
+        errs["force"] = {"vs_oracle_exact_inputs": max(e_ex),
                             "vs_oracle_same_rounded_inputs": max(e_same),
                             "measure": "relative error of Re sum tr(G^+ Y) against the oracle's "
                                        "forward-mode derivative along seeded Gaussian directions "
@@ -698,39 +698,39 @@ def main():
         torch.cuda.synchronize()
         log("copied 256 MiB twice")
         return
-    if args.profile == "c4":
-        measure_c4(ovl, torch, dev, latgen, args.steps, args.warmup, profile=True)
+    if args.profile == "batch":
+        measure_batch(ovl, torch, dev, latgen, args.steps, args.warmup, profile=True)
         return
-    if args.profile == "c3":
-        measure_c3(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
+    if args.profile == "bf16":
+        measure_bf16(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
         return
     if args.profile == "force":
         measure_force(ovl, torch, dev, latgen, args.steps, profile=True)
         return
-    if args.profile == "c2":
-        measure_c2(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
+    if args.profile == "overlap":
+        measure_overlap(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
         return
     if args.profile in ("dw", "dw2"):
         measure_big(ovl, torch, dev, latgen, profile=args.profile, reps=args.steps)
         return
     if args.profile == "proj":
         gen = torch.Generator(device=dev).manual_seed(7)
-        shape = (C3_NEV, 4, 3) + tuple(reversed(C3_DIMS))
+        shape = (BF16_NEV, 4, 3) + tuple(reversed(BF16_DIMS))
         phi = torch.randn(shape, dtype=torch.complex128, device=dev, generator=gen)
         psi = torch.randn(shape[1:], dtype=torch.complex64, device=dev, generator=gen)
-        d = ovl.Deflation(phi, np.linspace(-0.5, 0.5, C3_NEV), "f32")
+        d = ovl.Deflation(phi, np.linspace(-0.5, 0.5, BF16_NEV), "f32")
         for _ in range(args.steps):
             ovl.defl_project(d, psi)
         torch.cuda.synchronize()
         return
 
     t_start = time.time()
-    c4 = measure_c4(ovl, torch, dev, latgen, args.steps, args.warmup)
+    bt = measure_batch(ovl, torch, dev, latgen, args.steps, args.warmup)
     extra = {}
     if not args.no_extra:
-        extra["c3"] = measure_c3(ovl, torch, dev, latgen, low_modes, 5)
-        extra["c5_force"] = measure_force(ovl, torch, dev, latgen, 2)
-        extra["c2"] = measure_c2(ovl, torch, dev, latgen, low_modes, 20)
+        extra["bf16_24modes_16x16x16x32"] = measure_bf16(ovl, torch, dev, latgen, low_modes, 5)
+        extra["force_24x24x24x48"] = measure_force(ovl, torch, dev, latgen, 2)
+        extra["overlap_8x8x8x16"] = measure_overlap(ovl, torch, dev, latgen, low_modes, 20)
         extra["k_and_sign_24x24x24x48"] = measure_big(ovl, torch, dev, latgen)
         extra["streams_4GiB"] = measure_streams(ovl, torch, dev)
     cpu, errs = (None, {})
@@ -747,22 +747,22 @@ def main():
                 "avg_launch_us": round(avg_us, 3), "launches": k_n,
                 "bytes_per_launch": int(bytes_per_launch)}
 
-    c4_bytes = c4_bytes_per_step("f32", True)
-    rl = roofline(kernel_name(c4["config"], "f32", True), c4_bytes, c4["kernel_ms"],
-                  c4["kernel_launches"], tag="step_kernel_c4_batched")
+    batch_bytes = batch_bytes_per_step("f32", True)
+    rl = roofline(kernel_name(bt["config"], "f32", True), batch_bytes, bt["kernel_ms"],
+                  bt["kernel_launches"], tag="step2_kernel_sign_batch")
     rl["bytes_model"] = ("per step: every lattice's links once (two rows, 192 B/site) + "
                          "3.5 FP32 spinor streams (96 B each) per site and right-hand side")
-    if "c3" in extra:
-        c3 = extra["c3"]
-        c3["roofline"] = roofline(kernel_name(c3["config"], "bf16", False, False),
-                                  step_bytes("bf16") * int(np.prod(C3_DIMS)), c3.pop("kernel_ms"),
-                                  c3.pop("kernel_launches"))
-        c3["roofline"]["note"] = "62.9 MB per launch: the working set stays in the 256 MB Infinity Cache"
-        c3["applies_per_s"] = round(1e3 / c3["ms_per_apply"], 2)
-        c3["ms_per_apply"] = round(c3["ms_per_apply"], 3)
-        c3["errors"] = errs.get("c3")
-    if "c5_force" in extra:
-        f = extra["c5_force"]
+    if "bf16_24modes_16x16x16x32" in extra:
+        bf = extra["bf16_24modes_16x16x16x32"]
+        bf["roofline"] = roofline(kernel_name(bf["config"], "bf16", False, False),
+                                  step_bytes("bf16") * int(np.prod(BF16_DIMS)), bf.pop("kernel_ms"),
+                                  bf.pop("kernel_launches"))
+        bf["roofline"]["note"] = "62.9 MB per launch: the working set stays in the 256 MB Infinity Cache"
+        bf["applies_per_s"] = round(1e3 / bf["ms_per_apply"], 2)
+        bf["ms_per_apply"] = round(bf["ms_per_apply"], 3)
+        bf["errors"] = errs.get("bf16")
+    if "force_24x24x24x48" in extra:
+        f = extra["force_24x24x24x48"]
         nv = f.pop("vjp_launches")
         f["roofline"] = roofline("link_vjp_kernel<float,float2,float2>",
                                  f["vjp_bytes_per_force"] / f["vjp_launches_per_force"],
@@ -770,9 +770,9 @@ def main():
         f["roofline"]["bytes_model"] = ("per force: every (b_{m+1}, t_m) pair's two FP32 spinors "
                                         "once, the FP64 running sum of G between segments, G once")
         f["ms_per_force"] = round(f["ms_per_force"], 2)
-        f["errors"] = errs.get("c5_force")
-    if "c2" in extra:
-        extra["c2"]["errors"] = {k: errs.get(f"c2_{k}") for k in ("f32", "f64")}
+        f["errors"] = errs.get("force")
+    if "overlap_8x8x8x16" in extra:
+        extra["overlap_8x8x8x16"]["errors"] = {k: errs.get(f"overlap_{k}") for k in ("f32", "f64")}
 
     # the same figures against the measured device-memory stream ceilings (a plain 4 GiB read,
     # copy and three-reads-one-write stream; the stencil reads several streams and writes one)
@@ -785,11 +785,11 @@ def main():
             for form in row.values():
                 form["K_frac_of_three_to_one_stream"] = round(form["K_GBps"] / ceil["three_to_one"], 4)
                 form["step_frac_of_three_to_one_stream"] = round(form["step_GBps"] / ceil["three_to_one"], 4)
-        if "c5_force" in extra:
-            f = extra["c5_force"]["roofline"]
+        if "force_24x24x24x48" in extra:
+            f = extra["force_24x24x24x48"]["roofline"]
             f["frac_of_three_to_one_stream"] = round(f["achieved"] / ceil["three_to_one"], 4)
-    n_rhs = c4["n_rhs"]
-    ms = c4["ms_per_batch"]
+    n_rhs = bt["n_rhs"]
+    ms = bt["ms_per_batch"]
     line = {
         "metric": METRIC,
         "value": round(n_rhs * 1e3 / ms, 2),
@@ -811,16 +811,16 @@ def main():
                         "arithmetic, two-row link reads, one launch per K application for the "
                         "whole batch, autotuned launch configuration",
             "lattices": ["16x16x16x32 x12 rhs", "8x8x8x16 x4", "12x12x12x24 x2"],
-            "degree": C4_DEGREE - 1, "lmax": LMAX, "launch_config": c4["config"],
+            "degree": BATCH_DEGREE - 1, "lmax": LMAX, "launch_config": bt["config"],
         },
         "roofline": rl,
         "cpu_baseline": cpu,
-        "rel_err": {k: v for k, v in errs.items() if k.startswith("c4_")} or None,
-        "c4_batched": {k: v for k, v in c4.items() if k not in ("kernel_ms", "kernel_launches")},
+        "rel_err": {k: v for k, v in errs.items() if k.startswith("batch_")} or None,
+        "batch": {k: v for k, v in bt.items() if k not in ("kernel_ms", "kernel_launches")},
         **extra,
         "wall_s": round(time.time() - t_start, 1),
     }
-    line["c4_batched"]["ms_per_batch"] = round(ms, 4)
+    line["batch"]["ms_per_batch"] = round(ms, 4)
     print(json.dumps(line), flush=True)
 
 

@@ -50,7 +50,7 @@ def test_batch_mixed_volumes_vs_oracle(ovl, store):
         assert g.flags() == 0
 
 
-def test_batch_equals_single_launches_c4_shapes(ovl):
+def test_batch_equals_single_launches_mixed_volumes(ovl):
     """Full-size mixed-volume batch (12 point sources on 16^3x32, 4 x 8^3x16, 2 x 12^3x24) gives
     bitwise the results of the one-problem path (whose parity is pinned at smaller sizes)."""
     alpha = och.coeffs_sign_interp(300, 0.05)

@@ -408,7 +408,7 @@ def random_basis(dims, n_ev, seed):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def deflated_8x8x8x16():
     dims = (8, 8, 8, 16)
     u = latgen.smeared_field(dims, latgen.seed_for("gauge", 2))
     psi = latgen.gaussian_spinor(dims, latgen.seed_for("spinor", 2))
@@ -418,8 +418,8 @@ def c2():
     return dims, u, psi, phi, lam, alpha, ref_s
 
 
-def test_sign_c2_deflated_fp64(ovl, c2):
-    dims, u, psi, phi, lam, alpha, ref_s = c2
+def test_sign_8x8x8x16_deflated_fp64(ovl, deflated_8x8x8x16):
+    dims, u, psi, phi, lam, alpha, ref_s = deflated_8x8x8x16
     g = ovl.GaugeField(dev(u), "f64")
     p = ovl.Polynomial(alpha, LMAX)
     d = ovl.Deflation(dev(phi), lam, "f64")
@@ -433,8 +433,8 @@ def test_sign_c2_deflated_fp64(ovl, c2):
     assert g.flags() == 0
 
 
-def test_sign_c2_deflated_fp32(ovl, c2):
-    dims, u, psi, phi, lam, alpha, ref_s = c2
+def test_sign_8x8x8x16_deflated_fp32(ovl, deflated_8x8x8x16):
+    dims, u, psi, phi, lam, alpha, ref_s = deflated_8x8x8x16
     g = ovl.GaugeField(dev(u), "f32")
     p = ovl.Polynomial(alpha, LMAX)
     d = ovl.Deflation(dev(phi), lam, "f32")
