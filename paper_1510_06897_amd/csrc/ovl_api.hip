@@ -344,7 +344,9 @@ int plan_items(StepItem *items, int n, const LaunchCfg &cfg, int site_bytes) {
     StepItem &it = items[i];
     it.blk0 = total;
     it.ty = it.tz = 0;
-    if (cfg.tiles == 1) step_tile(it.g, cfg.spb, site_bytes, it.ty, it.tz);
+    // the slice budget covers every right-hand side of the item: they all pass through L2
+    // between a site and its t neighbour
+    if (cfg.tiles == 1) step_tile(it.g, cfg.spb, site_bytes * it.nrhs, it.ty, it.tz);
     total += item_blocks(it.g.V, cfg.spb) * ((it.nrhs + cfg.rb - 1) / cfg.rb);
   }
   return total;

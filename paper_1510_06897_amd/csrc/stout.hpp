@@ -336,10 +336,34 @@ __global__ void __launch_bounds__(256)
   store_m3(direct, mu, site, g.V, m3_axpy(m3_mul(ed, gp), 1.0, m3_dmul(go, c)));
 }
 
-// Backward of one step, the staple part, gathered per link (site y, direction d): every path of
-// every link (x, nu') whose step k is link d at y contributes  w A^+ Gamma_nu'(x) B^+  (its
-// adjoint when the step runs backwards), A and B the products of the steps before and after k.
-// out = direct + that sum: dL/dU of the step's input.  Grid (ceil(V / 256), 4).
+// Backward of one step, the staple part.  Link (y, d) receives w A^+ Gamma_nu(x) B^+ (its adjoint
+// for a backward step) from every staple path of every link (x, nu) that runs through it, A and B
+// the path's products before and after it.  Summed over the paths through (y, d), this equals the
+// derivative of (y, d)'s own staple sum C_d(y) in the direction Gamma: every factor of each of its
+// staple paths replaced in turn by the Gamma matrix of the same link, daggered like the factor
+// (the staple sum is the gradient of the gauge action, whose second derivative is symmetric).  So
+// each link walks its own 24 paths once, carrying the product X and its derivative T:
+//   X <- X F,  T <- T F + X Gamma(F).
+// out = direct + sum_paths w T: dL/dU of the step's input.  Grid (ceil(V / 256), 4).
+// factor of path step (dir, sgn) at `pos` of U and the same link of Gamma (both daggered for a
+// backward step); pos is advanced
+__device__ __forceinline__ void path_factor2(const double2 *__restrict__ U,
+                                             const double2 *__restrict__ Gm, const SiteCoord &x,
+                                             int pos[4], int dir, int sgn, const Geom &g, M3 &f,
+                                             M3 &gf) {
+  if (sgn > 0) {
+    const int site = site_at(x, pos, g);
+    f = load_m3(U, dir, site, g.V);
+    gf = load_m3(Gm, dir, site, g.V);
+    pos[dir] += 1;
+  } else {
+    pos[dir] -= 1;
+    const int site = site_at(x, pos, g);
+    f = m3_dag(load_m3(U, dir, site, g.V));
+    gf = m3_dag(load_m3(Gm, dir, site, g.V));
+  }
+}
+
 __global__ void __launch_bounds__(256)
     stout_back_gather_kernel(const double2 *__restrict__ U, const double2 *__restrict__ gamma,
                              const double2 *__restrict__ direct, double2 *__restrict__ out,
@@ -349,66 +373,28 @@ __global__ void __launch_bounds__(256)
   if (site >= g.V) return;
   const SiteCoord y = site_coord(site, g);
   M3 acc = load_m3(direct, d, site, g.V);
-  for (int mu = 0; mu < 4; ++mu)
-    for (int nu = 0; nu < 4; ++nu) {
-      if (nu == mu) continue;
-      for (int s = 1; s >= -1; s -= 2)
-        for (int shape = 0; shape < 4; ++shape) {
-          const double w = shape == 0 ? wp : wr;
-          if (w == 0.0) continue;
-          const int len = path_len(shape);
-          // positions of the steps relative to the path start
-          int zpos[4] = {0, 0, 0, 0};
-          for (int k = 0; k < len; ++k) {
-            int dir, sgn;
-            path_step(mu, nu, s, shape, k, dir, sgn);
-            // link of step k: U_dir(x + zpos) forwards, U_dir(x + zpos - e_dir) backwards
-            int lpos[4] = {zpos[0], zpos[1], zpos[2], zpos[3]};
-            if (sgn < 0) lpos[dir] -= 1;
-            if (dir == d) {
-              // the path start x = y - lpos
-              int xo[4];
-#pragma unroll
-              for (int q = 0; q < 4; ++q) xo[q] = -lpos[q];
-              SiteCoord x;
-              const int xs = site_at(y, xo, g);
-              x = site_coord(xs, g);
-              // t = A^+ Gamma B^+ with A, B the products before and after step k (an empty
-              // product is the unit matrix and is not multiplied)
-              int pos[4] = {0, 0, 0, 0};
-              M3 t = load_m3(gamma, mu, xs, g.V);
-              if (k > 0) {
-                int dj, sj;
-                path_step(mu, nu, s, shape, 0, dj, sj);
-                M3 a = path_factor(U, x, pos, dj, sj, g);
-                for (int j = 1; j < k; ++j) {
-                  path_step(mu, nu, s, shape, j, dj, sj);
-                  a = m3_mul(a, path_factor(U, x, pos, dj, sj, g));
-                }
-                t = m3_dmul(a, t);
-              }
-              {
-                int dj, sj;  // step past link k itself
-                path_step(mu, nu, s, shape, k, dj, sj);
-                pos[dj] += sj;
-              }
-              if (k + 1 < len) {
-                int dj, sj;
-                path_step(mu, nu, s, shape, k + 1, dj, sj);
-                M3 b = path_factor(U, x, pos, dj, sj, g);
-                for (int j = k + 2; j < len; ++j) {
-                  path_step(mu, nu, s, shape, j, dj, sj);
-                  b = m3_mul(b, path_factor(U, x, pos, dj, sj, g));
-                }
-                t = m3_muld(t, b);
-              }
-              if (sgn < 0) t = m3_dag(t);
-              acc = m3_axpy(acc, w, t);
-            }
-            zpos[dir] += sgn;
-          }
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == d) continue;
+    for (int s = 1; s >= -1; s -= 2)
+      for (int shape = 0; shape < 4; ++shape) {
+        const double w = shape == 0 ? wp : wr;
+        if (w == 0.0) continue;
+        int pos[4] = {0, 0, 0, 0};
+        int dir, sgn;
+        M3 x, t;
+        path_step(d, nu, s, shape, 0, dir, sgn);
+        path_factor2(U, gamma, y, pos, dir, sgn, g, x, t);
+        const int len = path_len(shape);
+        for (int k = 1; k < len; ++k) {
+          path_step(d, nu, s, shape, k, dir, sgn);
+          M3 f, gf;
+          path_factor2(U, gamma, y, pos, dir, sgn, g, f, gf);
+          t = m3_axpy(m3_mul(t, f), 1.0, m3_mul(x, gf));
+          if (k + 1 < len) x = m3_mul(x, f);
         }
-    }
+        acc = m3_axpy(acc, w, t);
+      }
+  }
   store_m3(out, d, site, g.V, acc);
 }
 
