@@ -274,6 +274,8 @@ def measure_bf16(ovl, torch, dev, latgen, low_modes, reps, profile=False):
             ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
         torch.cuda.synchronize()
         return None
+    cfg_default = ovl.batch_launch_config((gbf, x32))
+    ovl.autotune((gbf, x32), pbf, outs=[y32])
     cfg = ovl.batch_launch_config((gbf, x32))
     ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
     torch.cuda.synchronize()
@@ -294,7 +296,7 @@ def measure_bf16(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     vol = int(np.prod(BF16_DIMS))
     proj_flops = 8.0 * BF16_NEV * 12 * vol    # complex multiply-add = 8 real flops
     out = {"ms_per_apply": ms_bf, "kernel_ms": k_ms, "kernel_launches": k_n,
-           "config": list(cfg),
+           "config": list(cfg), "default_config": list(cfg_default),
            "plain_f64_ms_per_apply": round(ms_64, 3),
            "speedup_vs_plain_f64": round(ms_64 / ms_bf, 3),
            "two_row_links_ms_per_apply": round(ms_r12, 3),
@@ -324,6 +326,9 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
             ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
         torch.cuda.synchronize()
         return None
+    # the stencil steps of the force are single-problem launches on this lattice: tune them
+    ovl.autotune((g32, x32), pf, outs=[torch.empty_like(x32)])
+    step_cfg = ovl.batch_launch_config((g32, x32))
     ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
     torch.cuda.synchronize()
     ovl.timing_read(1)
@@ -364,6 +369,7 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     nseg = (n + FORCE_STRIDE - 1) // FORCE_STRIDE
     vjp_bytes = vol * (n * 2 * BYTES_SPIN["f32"] + (nseg - 1) * 2 * 36 * 16 + 36 * 8)
     out = {"ms_per_force": ms_f, "forces_per_s": round(1e3 / ms_f, 3),
+           "stencil_step_config": list(step_cfg),
            "ms_per_force_stride_299": round(ms_all, 2),
            "ms_per_force_two_row_links": round(ms_r12, 2),
            "vjp_ms": v_ms, "vjp_launches": v_n, "vjp_launches_per_force": v_n // reps,
