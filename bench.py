@@ -321,14 +321,14 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     x32 = torch.from_numpy(psi).to(dev).to(torch.complex64)
     c32 = torch.from_numpy(chi).to(dev).to(torch.complex64)
     log(f"force inputs {time.time() - t0:.1f} s")
+    # the stencil steps of the force are single-problem launches on this lattice: tune them
+    ovl.autotune((g32, x32), pf, outs=[torch.empty_like(x32)])
+    step_cfg = ovl.batch_launch_config((g32, x32))
     if profile:
         for _ in range(reps):
             ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
         torch.cuda.synchronize()
         return None
-    # the stencil steps of the force are single-problem launches on this lattice: tune them
-    ovl.autotune((g32, x32), pf, outs=[torch.empty_like(x32)])
-    step_cfg = ovl.batch_launch_config((g32, x32))
     ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
     torch.cuda.synchronize()
     ovl.timing_read(1)
