@@ -2732,7 +2732,9 @@ int ovl_autotune(const ovl_batch_item *items, int n_items, const ovl_poly *p, in
   HIP_TRY(hipEventCreate(&e1));
   LaunchCfg best{0, 0, 0, 1};
   float best_ms = 1e30f;
-  for (const LaunchCfg &cfg : cands) {
+  std::vector<float> times(cands.size(), 1e30f);
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    const LaunchCfg &cfg = cands[ci];
     if (table) {
       at.total_blocks = plan_items(its, n_items, cfg, sb);
       at.remap = cfg.remap;
@@ -2750,11 +2752,24 @@ int ovl_autotune(const ovl_batch_item *items, int n_items, const ovl_poly *p, in
                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
       rc = fail(OVL_EHIP, "event timing");
     if (rc) break;
+    times[ci] = ms;
     if (ms < best_ms) {
       best_ms = ms;
       best = cfg;
     }
   }
+  // Within 3% (run-to-run noise) the XCD-contiguous remap of the same form wins: it moves fewer
+  // bytes across the XCDs' L2 caches (measured on the headline batch: 1.52x against 1.93x the
+  // algorithmic bytes) at the same speed, and the choice stays stable from run to run.
+  if (rc == OVL_OK && best.remap == 0)
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      const LaunchCfg &c = cands[ci];
+      if (c.remap == 1 && c.spb == best.spb && c.tiles == best.tiles && c.rb == best.rb &&
+          times[ci] <= 1.03f * best_ms) {
+        best = c;
+        best_ms = times[ci];
+      }
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc == OVL_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(OVL_EHIP, "synchronise");
