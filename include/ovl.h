@@ -212,8 +212,11 @@ int ovl_wilson_link_vjp(const ovl_gauge *g, void *G_dev, const void *chi, const 
 
 /* G_dev = d Re <chi, p(X) psi> / dU with p the polynomial of the handle (no deflation term,
  * lmax held fixed): reverse Clenshaw sweep on chi with the forward Chebyshev vectors of psi
- * recomputed from checkpoints every ckpt_stride steps (0 = ceil(sqrt(N))).  Layout of G_dev as
- * in ovl_wilson_link_vjp; single right-hand side. */
+ * recomputed from checkpoints every ckpt_stride steps (0 = ceil(sqrt(N))).  The recomputation
+ * and the reverse sweep of a segment are independent, so their steps run two at a time in one
+ * launch that reads the links once (the launch configuration of a two-right-hand-side problem on
+ * this lattice, see ovl_autotune).  Layout of G_dev as in ovl_wilson_link_vjp; single right-hand
+ * side. */
 int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const void *chi,
                    const void *psi, int ckpt_stride, int spin_dt, void *stream);
 

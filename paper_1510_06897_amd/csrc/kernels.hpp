@@ -72,7 +72,27 @@ struct StepItem {
   int ty, tz;
   int n_ev, nrhs;
   int blk0;               // first global logical workgroup of this item
+  // Twin recurrence (plain steps only, nrhs = 2): right-hand side 1 is a second, independent
+  // vector set on the same field -- it reads twin_psi / twin_buf by role, without the
+  // right-hand-side offset, and takes the coefficient twin_a instead of the launch's a -- so two
+  // recurrences advance in one launch and share every link read.
+  int twin;
+  const void *twin_psi;
+  void *twin_buf[3];
+  double twin_a;
 };
+
+// address of a role's vector for right-hand side r of an item
+template <class SE>
+__device__ __forceinline__ const SE *role_vec(const StepItem &I, int role, int r, int V) {
+  if (I.twin && r == 1)
+    return reinterpret_cast<const SE *>(role == ROLE_PSI ? I.twin_psi : I.twin_buf[role - 1]);
+  const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
+  return reinterpret_cast<const SE *>(ptr) + (int64_t)r * 12 * V;
+}
+__device__ __forceinline__ double role_a(const StepItem &I, double a, int r) {
+  return (I.twin && r == 1) ? I.twin_a : a;
+}
 
 // Step coefficients plus the problems of one launch: a single problem travels in the kernel
 // arguments (TABLE = false); a batch reads its item table from device memory (TABLE = true),
@@ -183,17 +203,15 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   // after the exchange and keep the registers for occupancy.
   constexpr bool kEarly = SPB < 64;
   const uint32_t e0 = (uint32_t)(3 * q) * (uint32_t)V + site;  // element of component 3q
-  const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
 #pragma unroll 1
   for (int rr = 0; rr < RB; ++rr) {
     const int r = r0 + rr;
     const bool ractive = r < nrhs;   // the last block of an item may be ragged
     const bool act = active && ractive;
-    const int64_t base = (int64_t)(ractive ? r : 0) * 12 * V;
-    auto vec = [&](int role) -> const SE * {
-      const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
-      return reinterpret_cast<const SE *>(ptr) + base;
-    };
+    const int rv = ractive ? r : 0;
+    auto vec = [&](int role) -> const SE * { return role_vec<SE>(I, role, rv, V); };
+    const double pa = role_a(I, p.a, rv);
+    const bool need_src = (pa != 0.0) || p.mode >= MODE_SIGN;
     double nrm[2] = {0.0, 0.0};
     const rsrc_t v = make_rsrc(vec(p.v_role), vb);
     cx<C> vx[3], srcx[3], wx[3];
@@ -264,8 +282,8 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
         if (p.y_g5 && lower) y = -y;
         res[c] = y;
       }
-      if (p.a != 0.0) {
-        const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
+      if (pa != 0.0) {
+        const C a = (p.src_g5 && lower) ? C(-pa) : C(pa);
 #pragma unroll
         for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
       }
@@ -398,12 +416,9 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;
   const uint32_t vb = 12u * cs;
   const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
-  const int64_t base = (int64_t)r * 12 * V;
   const bool lower = q >= 2;
-  auto vec = [&](int role) -> const SE * {
-    const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
-    return reinterpret_cast<const SE *>(ptr) + base;
-  };
+  auto vec = [&](int role) -> const SE * { return role_vec<SE>(I, role, r, V); };
+  const double pa = role_a(I, p.a, r);
   double nrm[2] = {0.0, 0.0};
   const rsrc_t v = make_rsrc(vec(p.v_role), vb);
   const bool vg5 = p.v_g5 != 0;
@@ -484,14 +499,14 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
       }
     }
     cx<C> srcx[2][3];
-    const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
+    const bool need_src = (pa != 0.0) || p.mode >= MODE_SIGN;
     if (need_src) {
       const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
 #pragma unroll
       for (int c = 0; c < 3; ++c) bldv2<SE>(sr, e0 + c * V, srcx[0][c], srcx[1][c]);
     }
-    if (p.a != 0.0) {
-      const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
+    if (pa != 0.0) {
+      const C a = (p.src_g5 && lower) ? C(-pa) : C(pa);
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -605,12 +620,9 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;
   const uint32_t vb = 12u * cs;
   const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
-  const int64_t base = (int64_t)r * 12 * V;
   const bool lower = q >= 2;
-  auto vec = [&](int role) -> const SE * {
-    const void *ptr = role == ROLE_PSI ? I.psi : I.buf[role - 1];
-    return reinterpret_cast<const SE *>(ptr) + base;
-  };
+  auto vec = [&](int role) -> const SE * { return role_vec<SE>(I, role, r, V); };
+  const double pa = role_a(I, p.a, r);
   double nrm[2] = {0.0, 0.0};
   const rsrc_t v = make_rsrc(vec(p.v_role), vb);
   const bool vg5 = p.v_g5 != 0;
@@ -727,14 +739,14 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
     cx<C> srcx[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) srcx[c] = mk<C>(0, 0);
-    const bool need_src = (p.a != 0.0) || p.mode >= MODE_SIGN;
+    const bool need_src = (pa != 0.0) || p.mode >= MODE_SIGN;
     if (need_src) {
       const rsrc_t sr = make_rsrc(vec(ROLE_PSI), vb);
 #pragma unroll
       for (int c = 0; c < 3; ++c) srcx[c] = bldv<C, SE>(sr, e0 + c * V);
     }
-    if (p.a != 0.0) {
-      const C a = (p.src_g5 && lower) ? C(-p.a) : C(p.a);
+    if (pa != 0.0) {
+      const C a = (p.src_g5 && lower) ? C(-pa) : C(pa);
 #pragma unroll
       for (int c = 0; c < 3; ++c) res[c] = res[c] + scale(srcx[c], a);
     }

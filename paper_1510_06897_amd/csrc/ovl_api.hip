@@ -311,6 +311,11 @@ bool pairs_ok(Prec prec, const StepItem *items, int n) {
     if (it.g.L[0] % 2 || !aligned16(it.psi) || !aligned16(it.phi)) return false;
     for (int k = 0; k < 3; ++k)
       if (!aligned16(it.buf[k])) return false;
+    if (it.twin) {
+      if (!aligned16(it.twin_psi)) return false;
+      for (int k = 0; k < 3; ++k)
+        if (!aligned16(it.twin_buf[k])) return false;
+    }
   }
   return true;
 }
@@ -2122,6 +2127,32 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
     sp.t = t;
     return dispatch_single(prec, sp, s);
   };
+  // two such steps with the same stencil weight sx and w coefficient t in one launch (the twin
+  // recurrence: both read every link once): out = sx X v + a src + t w, out2 likewise
+  auto xstep2 = [&](void *out, const void *v, const void *src, double a, const void *w,
+                    void *out2, const void *v2, const void *src2, double a2, const void *w2,
+                    double sx, double t) -> int {
+    StepArgs<false> sp = single_args(g, 2);
+    sp.item.twin = 1;
+    sp.item.psi = src;
+    sp.item.buf[0] = const_cast<void *>(v);
+    sp.item.buf[1] = const_cast<void *>(w);
+    sp.item.buf[2] = out;
+    sp.item.twin_psi = src2;
+    sp.item.twin_buf[0] = const_cast<void *>(v2);
+    sp.item.twin_buf[1] = const_cast<void *>(w2);
+    sp.item.twin_buf[2] = out2;
+    sp.item.twin_a = src2 ? a2 : 0.0;
+    sp.v_role = ROLE_B0;
+    sp.w_role = ROLE_B1;
+    sp.out_role = ROLE_B2;
+    sp.y_g5 = 1;
+    sp.kd = sx * kdiag / p->lmax;
+    sp.kh = -0.5 * sx / p->lmax;
+    sp.a = src ? a : 0.0;
+    sp.t = t;
+    return dispatch_single(prec, sp, s);
+  };
   // forward sweep: t_0 = psi, t_1 = X psi, t_{m+1} = 2 X t_m - t_{m-1}, keeping the checkpoint
   // vectors; the others rotate through seg(0), seg(1) (never the buffer read as stencil input).
   // It stops at the last checkpoint: the top segment is regenerated by the backward sweep.
@@ -2154,16 +2185,32 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G, const void *c
   for (int j = nseg - 1; j >= 0; --j) {
     const int m0 = j * S;
     const int m1 = std::min(N - 1, m0 + S - 1);
-    // regenerate t_{m0} .. t_{m1} into seg(0..)
+    // regenerate t_{m0} .. t_{m1} into seg(0..) (ascending) and advance
+    // b_m = alpha_m chi + 2 X b_{m+1} - b_{m+2} for m = m1 .. max(m0, 1) (descending; b_{m1+1}
+    // and b_{m1+2} come from the segment above or the start values).  The two recurrences are
+    // independent, so their steps run as twins, one launch per pair of steps.
     HIP_TRY(hipMemcpyAsync(seg(0), ck(m0), vec, hipMemcpyDeviceToDevice, s));
     if (m1 >= m0 + 1) HIP_TRY(hipMemcpyAsync(seg(1), ck(m0 + 1), vec, hipMemcpyDeviceToDevice, s));
-    for (int m = m0 + 2; m <= m1; ++m)
-      if ((rc = xstep(seg(m - m0), seg(m - m0 - 1), 2.0, nullptr, 0.0, seg(m - m0 - 2), -1.0))) return rc;
-    // b_m = alpha_m chi + 2 X b_{m+1} - b_{m+2} for m = m1 .. max(m0, 1); b_{m1+1} and b_{m1+2}
-    // come from the segment above (or the start values)
-    for (int m = m1; m >= std::max(m0, 1); --m)
-      if ((rc = xstep(bv(m), bv(m + 1), 2.0, chi, al[m], m + 2 <= N ? bv(m + 2) : nullptr, -1.0)))
-        return rc;
+    int mt = m0 + 2, mb = m1;
+    const int mb_end = std::max(m0, 1);
+    while (mt <= m1 || mb >= mb_end) {
+      // b_{N-1} has no b_{N+1} term: it runs alone (the twins share the w coefficient)
+      const bool b_next = mb >= mb_end;
+      const bool b_w = b_next && mb + 2 <= N;
+      if (mt <= m1 && b_w) {
+        rc = xstep2(seg(mt - m0), seg(mt - m0 - 1), nullptr, 0.0, seg(mt - m0 - 2),
+                    bv(mb), bv(mb + 1), chi, al[mb], bv(mb + 2), 2.0, -1.0);
+        ++mt;
+        --mb;
+      } else if (b_next) {
+        rc = xstep(bv(mb), bv(mb + 1), 2.0, chi, al[mb], b_w ? bv(mb + 2) : nullptr, -1.0);
+        --mb;
+      } else {
+        rc = xstep(seg(mt - m0), seg(mt - m0 - 1), 2.0, nullptr, 0.0, seg(mt - m0 - 2), -1.0);
+        ++mt;
+      }
+      if (rc) return rc;
+    }
     // pairs (b_{m+1}, t_m), m = m0 .. m1, in one launch: the ring slots of b_{m0+1} .. b_{m1+1}
     // are consecutive up to one wrap (a segment holds at most S < R pairs), so they form at most
     // two runs; the t_m are consecutive in the segment buffer
