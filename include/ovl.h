@@ -234,8 +234,8 @@ int ovl_sign_force(const ovl_gauge *g, const ovl_poly *p, void *G_dev, const voi
  *                layout of ovl_gauge_create); they must not overlap; U_in is unchanged.
  *   steps        0 .. 64 (0 copies U_in).
  * Allocates two link fields of work space for steps >= 2.  Asynchronous on `stream`.
- * Errors: EINVAL (NULL, steps out of range), EDIMS, ENONFINITE (rho or eps), EALIAS, ENOMEM,
- * EHIP. */
+ * Errors: EINVAL (NULL, steps out of range), EDIMS (bad extents, or a link field of 4 GiB or more:
+ * V >= 7456540 sites), ENONFINITE (rho or eps), EALIAS, ENOMEM, EHIP. */
 int ovl_stout_smear(const int32_t dims[4], void *U_out, const void *U_in, double rho, double eps,
                     int steps, void *stream);
 

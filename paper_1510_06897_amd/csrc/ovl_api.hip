@@ -2940,6 +2940,9 @@ bool spans_overlap(const void *a, const void *b, size_t n) {
 int check_stout(const int32_t dims[4], double rho, double eps, int steps, Geom &geo) {
   int rc = check_dims(dims, geo);
   if (rc) return rc;
+  // the path kernels address a link field through 32-bit buffer offsets
+  if (!fits_u32(36ull * geo.V, OVL_F64))
+    return fail(OVL_EDIMS, "a link field of %d sites spans 4 GiB or more", geo.V);
   if (!std::isfinite(rho) || !std::isfinite(eps)) return fail(OVL_ENONFINITE, "non-finite rho or eps");
   if (steps < 0 || steps > 64) return fail(OVL_EINVAL, "steps = %d out of range [0, 64]", steps);
   return OVL_OK;

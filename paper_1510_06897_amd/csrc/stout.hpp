@@ -10,7 +10,9 @@
 // leaves the plaquette alone: plain stout smearing).
 //
 // Links are read and written in the caller layout U[mu][a][b][site] (complex double), so one
-// wave reads one matrix element of 64 consecutive sites per load.  A thread owns one link
+// wave reads one matrix element of 64 consecutive sites per load; the path factors are read
+// through raw buffer resources (lane offset site * 16 bytes, element offset in a scalar register),
+// so a field must span less than 4 GiB.  A thread owns one link
 // (site, mu); the workgroup's 256 threads share mu, so the path loops below are uniform over a
 // wave.  exp(M) is a Taylor series after scaling M to norm <= 1/2, followed by squaring; the
 // derivative of exp comes from the same series for the Frechet derivative (the directional
@@ -247,49 +249,110 @@ __device__ __forceinline__ SiteCoord site_coord(int site, const Geom &g) {
   }
   return r;
 }
-// site index of x + off (periodic)
-__device__ __forceinline__ int site_at(const SiteCoord &x, const int off[4], const Geom &g) {
-  int idx = 0;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    int v = (x.c[d] + off[d]) % g.L[d];
-    if (v < 0) v += g.L[d];
-    idx += v * g.stride[d];
-  }
-  return idx;
+
+// Positions on the paths of link (x, mu) in the plane (mu, nu): a path moves along mu and nu only,
+// so a position is x + a e_mu + b e_nu (|a|, |b| <= 2) and its site index takes two periodic wraps.
+struct PlaneAddr {
+  int rest;    // site index of x without its mu and nu parts
+  int xm, xn;  // coordinates of x along mu and nu
+  int lm, ln;  // extents along mu and nu
+  int sm, sn;  // strides along mu and nu
+};
+__device__ __forceinline__ PlaneAddr plane_addr(const SiteCoord &x, int site, int mu, int nu,
+                                                const Geom &g) {
+  PlaneAddr p;
+  p.xm = x.c[mu];
+  p.xn = x.c[nu];
+  p.lm = g.L[mu];
+  p.ln = g.L[nu];
+  p.sm = g.stride[mu];
+  p.sn = g.stride[nu];
+  p.rest = site - p.xm * p.sm - p.xn * p.sn;
+  return p;
 }
-// factor of path step (dir, sgn) taken at position `pos` (updated to the position after the step)
-__device__ __forceinline__ M3 path_factor(const double2 *__restrict__ U, const SiteCoord &x,
-                                          int pos[4], int dir, int sgn, const Geom &g) {
-  if (sgn > 0) {
-    const M3 f = load_m3(U, dir, site_at(x, pos, g), g.V);
-    pos[dir] += 1;
+// v mod L for -2 L <= v < 3 L (two conditional steps each way also cover extent 1)
+__device__ __forceinline__ int wrap2(int v, int L) {
+  v += v < 0 ? L : 0;
+  v += v < 0 ? L : 0;
+  v -= v >= L ? L : 0;
+  v -= v >= L ? L : 0;
+  return v;
+}
+__device__ __forceinline__ int plane_site(const PlaneAddr &p, int a, int b) {
+  return p.rest + wrap2(p.xm + a, p.lm) * p.sm + wrap2(p.xn + b, p.ln) * p.sn;
+}
+
+// link field U[dir][a][b][site] read through a buffer resource
+__device__ __forceinline__ M3 load_m3r(rsrc_t r, int dir, int site, int V) {
+  M3 m;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      m.e[i][j] = bld<double, double2>(r, (uint32_t)((dir * 9 + 3 * i + j) * V) * 16u, site);
+  return m;
+}
+
+// Path step k of (shape, s): along mu (along = 0) or nu (1), forward (fwd) or backward, from
+// the path_step table.  A forward step at position (a, b) takes U_dir(x + a e_mu + b e_nu) and
+// moves on; a backward step moves first and takes the link there, daggered.
+__device__ __forceinline__ void path_move(int shape, int k, int s, int &along, bool &fwd) {
+  int dir, sgn;
+  path_step(0, 1, s, shape, k, dir, sgn);
+  along = dir;
+  fwd = sgn > 0;
+}
+__device__ __forceinline__ M3 path_factor(rsrc_t U, const PlaneAddr &pa, int &a, int &b,
+                                          int along, bool fwd, int mu, int nu, int V) {
+  const int dir = along == 0 ? mu : nu;
+  int &z = along == 0 ? a : b;
+  if (fwd) {
+    const M3 f = load_m3r(U, dir, plane_site(pa, a, b), V);
+    z += 1;
     return f;
   }
-  pos[dir] -= 1;
-  return m3_dag(load_m3(U, dir, site_at(x, pos, g), g.V));
+  z -= 1;
+  return m3_dag(load_m3r(U, dir, plane_site(pa, a, b), V));
 }
 
 // C_mu(x) = sum over the paths of their products, plaquette paths weighted wp, rectangles wr
-__device__ inline M3 staple_sum(const double2 *__restrict__ U, const SiteCoord &x, int mu, double wp,
+__device__ inline M3 staple_sum(rsrc_t U, const SiteCoord &x, int site, int mu, double wp,
                                 double wr, const Geom &g) {
   M3 c = m3_zero();
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == mu) continue;
-    for (int s = 1; s >= -1; s -= 2)
-      for (int shape = 0; shape < 4; ++shape) {
-        const double w = shape == 0 ? wp : wr;
-        if (w == 0.0) continue;
-        int pos[4] = {0, 0, 0, 0};
-        int dir, sgn;
-        path_step(mu, nu, s, shape, 0, dir, sgn);
-        M3 p = path_factor(U, x, pos, dir, sgn, g);
-        for (int k = 1; k < path_len(shape); ++k) {
-          path_step(mu, nu, s, shape, k, dir, sgn);
-          p = m3_mul(p, path_factor(U, x, pos, dir, sgn, g));
-        }
-        c = m3_axpy(c, w, p);
+    const PlaneAddr pa = plane_addr(x, site, mu, nu, g);
+    for (int s = 1; s >= -1; s -= 2) {
+      // shapes 0 and 1 share their first two factors (nu,s)(mu,+): the plaquette closes from
+      // there, the rectangle goes on from the same product and position
+      int a = 0, b = 0, along;
+      bool fwd;
+      path_move(0, 0, s, along, fwd);
+      M3 p = path_factor(U, pa, a, b, along, fwd, mu, nu, g.V);
+      path_move(0, 1, s, along, fwd);
+      p = m3_mul(p, path_factor(U, pa, a, b, along, fwd, mu, nu, g.V));
+      if (wp != 0.0) {
+        int a0 = a, b0 = b;
+        path_move(0, 2, s, along, fwd);
+        c = m3_axpy(c, wp, m3_mul(p, path_factor(U, pa, a0, b0, along, fwd, mu, nu, g.V)));
       }
+      if (wr == 0.0) continue;
+      for (int k = 2; k < path_len(1); ++k) {
+        path_move(1, k, s, along, fwd);
+        p = m3_mul(p, path_factor(U, pa, a, b, along, fwd, mu, nu, g.V));
+      }
+      c = m3_axpy(c, wr, p);
+      for (int shape = 2; shape < 4; ++shape) {
+        a = b = 0;
+        path_move(shape, 0, s, along, fwd);
+        p = path_factor(U, pa, a, b, along, fwd, mu, nu, g.V);
+        for (int k = 1; k < path_len(shape); ++k) {
+          path_move(shape, k, s, along, fwd);
+          p = m3_mul(p, path_factor(U, pa, a, b, along, fwd, mu, nu, g.V));
+        }
+        c = m3_axpy(c, wr, p);
+      }
+    }
   }
   return c;
 }
@@ -303,7 +366,7 @@ __global__ void __launch_bounds__(256)
   const int mu = blockIdx.y;
   if (site >= g.V) return;
   const SiteCoord x = site_coord(site, g);
-  const M3 c = staple_sum(U, x, mu, wp, wr, g);
+  const M3 c = staple_sum(make_rsrc(U, 576u * (uint32_t)g.V), x, site, mu, wp, wr, g);
   if (C_out) store_m3(C_out, mu, site, g.V, c);
   const M3 u = load_m3(U, mu, site, g.V);
   const M3 e = m3_exp(m3_ta(m3_muld(c, u)));
@@ -324,7 +387,9 @@ __global__ void __launch_bounds__(256)
   const int mu = blockIdx.y;
   if (site >= g.V) return;
   // the staple sums of this level from the forward pass when available
-  const M3 c = C_in ? load_m3(C_in, mu, site, g.V) : staple_sum(U, site_coord(site, g), mu, wp, wr, g);
+  const M3 c = C_in ? load_m3(C_in, mu, site, g.V)
+                    : staple_sum(make_rsrc(U, 576u * (uint32_t)g.V), site_coord(site, g), site, mu,
+                                 wp, wr, g);
   const M3 u = load_m3(U, mu, site, g.V);
   const M3 m = m3_ta(m3_muld(c, u));
   const M3 gp = load_m3(gout, mu, site, g.V);
@@ -347,20 +412,21 @@ __global__ void __launch_bounds__(256)
 // out = direct + sum_paths w T: dL/dU of the step's input.  Grid (ceil(V / 256), 4).
 // factor of path step (dir, sgn) at `pos` of U and the same link of Gamma (both daggered for a
 // backward step); pos is advanced
-__device__ __forceinline__ void path_factor2(const double2 *__restrict__ U,
-                                             const double2 *__restrict__ Gm, const SiteCoord &x,
-                                             int pos[4], int dir, int sgn, const Geom &g, M3 &f,
-                                             M3 &gf) {
-  if (sgn > 0) {
-    const int site = site_at(x, pos, g);
-    f = load_m3(U, dir, site, g.V);
-    gf = load_m3(Gm, dir, site, g.V);
-    pos[dir] += 1;
+__device__ __forceinline__ void path_factor2(rsrc_t U, rsrc_t Gm, const PlaneAddr &pa, int &a,
+                                             int &b, int along, bool fwd, int mu, int nu, int V,
+                                             M3 &f, M3 &gf) {
+  const int dir = along == 0 ? mu : nu;
+  int &z = along == 0 ? a : b;
+  if (fwd) {
+    const int site = plane_site(pa, a, b);
+    f = load_m3r(U, dir, site, V);
+    gf = load_m3r(Gm, dir, site, V);
+    z += 1;
   } else {
-    pos[dir] -= 1;
-    const int site = site_at(x, pos, g);
-    f = m3_dag(load_m3(U, dir, site, g.V));
-    gf = m3_dag(load_m3(Gm, dir, site, g.V));
+    z -= 1;
+    const int site = plane_site(pa, a, b);
+    f = m3_dag(load_m3r(U, dir, site, V));
+    gf = m3_dag(load_m3r(Gm, dir, site, V));
   }
 }
 
@@ -372,28 +438,52 @@ __global__ void __launch_bounds__(256)
   const int d = blockIdx.y;
   if (site >= g.V) return;
   const SiteCoord y = site_coord(site, g);
+  const rsrc_t ru = make_rsrc(U, 576u * (uint32_t)g.V);
+  const rsrc_t rg = make_rsrc(gamma, 576u * (uint32_t)g.V);
   M3 acc = load_m3(direct, d, site, g.V);
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == d) continue;
-    for (int s = 1; s >= -1; s -= 2)
-      for (int shape = 0; shape < 4; ++shape) {
-        const double w = shape == 0 ? wp : wr;
-        if (w == 0.0) continue;
-        int pos[4] = {0, 0, 0, 0};
-        int dir, sgn;
-        M3 x, t;
-        path_step(d, nu, s, shape, 0, dir, sgn);
-        path_factor2(U, gamma, y, pos, dir, sgn, g, x, t);
+    const PlaneAddr pa = plane_addr(y, site, d, nu, g);
+    for (int s = 1; s >= -1; s -= 2) {
+      // shapes 0 and 1 share their first two factors (nu,s)(mu,+): the plaquette closes from
+      // there, the rectangle goes on from the same (X, T) and position
+      int a = 0, b = 0, along;
+      bool fwd;
+      M3 x, t, f, gf;
+      path_move(0, 0, s, along, fwd);
+      path_factor2(ru, rg, pa, a, b, along, fwd, d, nu, g.V, x, t);
+      path_move(0, 1, s, along, fwd);
+      path_factor2(ru, rg, pa, a, b, along, fwd, d, nu, g.V, f, gf);
+      t = m3_axpy(m3_mul(t, f), 1.0, m3_mul(x, gf));
+      x = m3_mul(x, f);
+      if (wp != 0.0) {
+        int a0 = a, b0 = b;
+        path_move(0, 2, s, along, fwd);
+        path_factor2(ru, rg, pa, a0, b0, along, fwd, d, nu, g.V, f, gf);
+        acc = m3_axpy(acc, wp, m3_axpy(m3_mul(t, f), 1.0, m3_mul(x, gf)));
+      }
+      if (wr == 0.0) continue;
+      for (int k = 2; k < path_len(1); ++k) {
+        path_move(1, k, s, along, fwd);
+        path_factor2(ru, rg, pa, a, b, along, fwd, d, nu, g.V, f, gf);
+        t = m3_axpy(m3_mul(t, f), 1.0, m3_mul(x, gf));
+        if (k + 1 < path_len(1)) x = m3_mul(x, f);
+      }
+      acc = m3_axpy(acc, wr, t);
+      for (int shape = 2; shape < 4; ++shape) {
+        a = b = 0;
+        path_move(shape, 0, s, along, fwd);
+        path_factor2(ru, rg, pa, a, b, along, fwd, d, nu, g.V, x, t);
         const int len = path_len(shape);
         for (int k = 1; k < len; ++k) {
-          path_step(d, nu, s, shape, k, dir, sgn);
-          M3 f, gf;
-          path_factor2(U, gamma, y, pos, dir, sgn, g, f, gf);
+          path_move(shape, k, s, along, fwd);
+          path_factor2(ru, rg, pa, a, b, along, fwd, d, nu, g.V, f, gf);
           t = m3_axpy(m3_mul(t, f), 1.0, m3_mul(x, gf));
           if (k + 1 < len) x = m3_mul(x, f);
         }
-        acc = m3_axpy(acc, w, t);
+        acc = m3_axpy(acc, wr, t);
       }
+    }
   }
   store_m3(out, d, site, g.V, acc);
 }

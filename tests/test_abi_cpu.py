@@ -220,6 +220,12 @@ def test_stout_validation_before_hip(lib):
     assert lib.ovl_stout_smear(dims, ctypes.c_void_p((1 << 40) + fb // 2), a, 0.1, -0.25, 3, None) == -4
     bad = (ctypes.c_int32 * 4)(4, 0, 4, 4)
     assert lib.ovl_stout_smear(bad, b, a, 0.1, -0.25, 3, None) == -2
+    # a link field of 4 GiB or more (the path kernels use 32-bit buffer offsets): 64^3 x 32
+    huge = (ctypes.c_int32 * 4)(64, 64, 64, 32)
+    far = ctypes.c_void_p(1 << 44)
+    assert lib.ovl_stout_smear(huge, far, a, 0.1, -0.25, 3, None) == -2
+    assert lib.ovl_stout_backward(huge, far, ctypes.c_void_p(2 << 44), ctypes.c_void_p(3 << 44),
+                                  0.1, -0.25, 3, None) == -2
     assert lib.ovl_stout_backward(dims, c, b, None, 0.1, -0.25, 3, None) == -1
     assert lib.ovl_stout_backward(dims, c, b, c, 0.1, -0.25, 3, None) == -4
     assert lib.ovl_stout_backward(dims, c, c, a, 0.1, -0.25, 3, None) == -4
