@@ -90,7 +90,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the BF16/24-mode, force, overlap, 24^3x48 and "
                          "stream measurements")
-    ap.add_argument("--profile", choices=["batch", "bf16", "force", "overlap", "dw", "dw2", "proj", "copy"],
+    ap.add_argument("--profile", choices=["batch", "bf16", "force", "stout", "overlap", "dw", "dw2", "proj",
+                                          "copy"],
                     help="run one part only, for rocprofv3: batch = the timed batched loop of the "
                          "headline (--steps batches), bf16 = the BF16 24-mode loop, force = the "
                          "FP32 force at 24^3x48, overlap = the FP32 overlap loop, dw = K at 24^3x48 "
@@ -324,6 +325,11 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     # the stencil steps of the force are single-problem launches on this lattice: tune them
     ovl.autotune((g32, x32), pf, outs=[torch.empty_like(x32)])
     step_cfg = ovl.batch_launch_config((g32, x32))
+    # the twin steps (checkpoint recomputation beside the reverse sweep) launch as a
+    # two-right-hand-side problem on the same lattice
+    x2 = x32.reshape((1,) + tuple(x32.shape[-6:])).expand((2,) + tuple(x32.shape[-6:])).contiguous()
+    twin_cfg = ovl.batch_launch_config((g32, x2))
+    del x2
     if profile:
         for _ in range(reps):
             ovl.sign_force(g32, pf, c32, x32, ckpt_stride=FORCE_STRIDE, out=G)
@@ -369,7 +375,7 @@ def measure_force(ovl, torch, dev, latgen, reps, profile=False):
     nseg = (n + FORCE_STRIDE - 1) // FORCE_STRIDE
     vjp_bytes = vol * (n * 2 * BYTES_SPIN["f32"] + (nseg - 1) * 2 * 36 * 16 + 36 * 8)
     out = {"ms_per_force": ms_f, "forces_per_s": round(1e3 / ms_f, 3),
-           "stencil_step_config": list(step_cfg),
+           "stencil_step_config": list(step_cfg), "twin_step_config": list(twin_cfg),
            "ms_per_force_stride_299": round(ms_all, 2),
            "ms_per_force_two_row_links": round(ms_r12, 2),
            "vjp_ms": v_ms, "vjp_launches": v_n, "vjp_launches_per_force": v_n // reps,
@@ -712,6 +718,19 @@ def main():
         return
     if args.profile == "force":
         measure_force(ovl, torch, dev, latgen, args.steps, profile=True)
+        return
+    if args.profile == "stout":
+        # the smearing and chain-rule kernels of the HMC chain on 24^3x48 thin links
+        u_thin = torch.from_numpy(latgen.random_su3_field(FORCE_DIMS, latgen.seed_for("gauge", 5))).to(dev)
+        us = torch.empty_like(u_thin)
+        g_s = torch.from_numpy(latgen.gaussian_spinor(FORCE_DIMS, latgen.seed_for("spinor", 5), nrhs=3)
+                               ).to(dev).reshape(u_thin.shape)
+        gt = torch.empty_like(u_thin)
+        for _ in range(args.steps):
+            ovl.stout_smear(u_thin, 0.1, -0.25, 3, out=us)
+            ovl.stout_backward(u_thin, g_s, 0.1, -0.25, 3, out=gt)
+        torch.cuda.synchronize()
+        log(f"stout smear + chain rule x {args.steps}")
         return
     if args.profile == "overlap":
         measure_overlap(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
