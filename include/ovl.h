@@ -278,7 +278,10 @@ int ovl_sign_residual(const ovl_gauge *g, const ovl_poly *p, const ovl_defl *d, 
  * numerically dependent directions are replaced by fresh random vectors), does a Rayleigh-Ritz
  * step with K itself (so +lambda and -lambda separate), orders the Ritz pairs by ||K v|| and
  * stops when the first n_ev residuals ||K phi - lambda phi|| are below tol or after max_iter
- * iterations.  Every K application runs in the fused stencil kernel with `block` right-hand sides;
+ * iterations.  Every K application runs in the fused stencil kernel with `block` right-hand sides,
+ * in the configuration ovl_autotune keeps for that problem (this lattice, FP64, `block`
+ * right-hand sides); when there is none yet, the call first measures the candidates on its own
+ * start block, as ovl_autotune would (the choice then holds for the rest of the process).
  * Gram products, block rotations and residual norms are FP64 device kernels; the block x block
  * Hermitian eigen-problems are solved on the host (Householder tridiagonalisation + implicit QL).
  * The start block is complex Gaussian from a counter-based generator keyed by `seed`.

@@ -80,7 +80,26 @@ struct StepItem {
   const void *twin_psi;
   void *twin_buf[3];
   double twin_a;
+  // Right-hand-side groups of the workgroup order: right-hand-side blocks run fastest inside
+  // groups of rgroup blocks, then the site blocks, then the groups (0: one group of all).
+  int rgroup;
 };
+
+// item-local workgroup lb -> (right-hand-side block rb, site block b) for nrb right-hand-side
+// blocks and nsb site blocks.  Inside a group the workgroups that read the same links run side by
+// side (they share them through L2); with many right-hand sides, groups keep the spinor data
+// between a site and its t neighbour within one XCD's L2.
+__device__ __forceinline__ void item_block(const StepItem &I, int lb, int nrb, int nsb, int &rb,
+                                           int &b) {
+  const int gs = (I.rgroup > 0 && I.rgroup < nrb) ? I.rgroup : nrb;
+  const int full = nrb / gs;      // groups of gs blocks; a last, smaller group follows
+  const int span = gs * nsb;
+  const int gi = min(lb / span, full);
+  const int gl = gi < full ? gs : nrb - full * gs;
+  const int within = lb - gi * span;
+  rb = gi * gs + within % gl;
+  b = within / gl;
+}
 
 // address of a role's vector for right-hand side r of an item
 template <class SE>
@@ -148,8 +167,9 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   const int nrhs = I.nrhs;
   const int nrb = (nrhs + RB - 1) / RB;  // right-hand-side blocks of the item
   const int lb = gb - I.blk0;
-  const int r0 = (lb % nrb) * RB;
-  const int b = lb / nrb;
+  int rbk, b;
+  item_block(I, lb, nrb, (ex.V + SPB - 1) / SPB, rbk, b);
+  const int r0 = rbk * RB;
   const int q = threadIdx.x / SPB;
   const int sl = threadIdx.x % SPB;
   const int dq = q & 3;       // direction of the thread's hop(s)
@@ -384,8 +404,8 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
   constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
   const int lb = gb - I.blk0;
-  const int r = lb % nrhs;
-  const int b = lb / nrhs;
+  int r, b;
+  item_block(I, lb, nrhs, (ex.V + 2 * SPB - 1) / (2 * SPB), r, b);
   const int q = threadIdx.x / SPB;
   const int sl = threadIdx.x % SPB;
   Coord4 c4;
@@ -562,8 +582,9 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
   if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
     block_sum<2>(nrm, lds);
     if (threadIdx.x == 0) {
-      I.norm_partial[(int64_t)lb * 2 + 0] = nrm[0];
-      I.norm_partial[(int64_t)lb * 2 + 1] = nrm[1];
+      const int64_t pb = (int64_t)b * nrhs + r;  // partial of (site block b, right-hand side r)
+      I.norm_partial[pb * 2 + 0] = nrm[0];
+      I.norm_partial[pb * 2 + 1] = nrm[1];
     }
   }
 }
@@ -597,8 +618,8 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
   constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
   const int lb = gb - I.blk0;
-  const int r = lb % nrhs;
-  int b = lb / nrhs;
+  int r, b;
+  item_block(I, lb, nrhs, ex.V / SPB, r, b);
   const int ny = SPB / ex.lx;
   const int nstage = SPB + 2 * ex.lx;
   cx<C> *stage = reinterpret_cast<cx<C> *>(slab_smem);  // [12][nstage]
@@ -784,8 +805,9 @@ __global__ void __launch_bounds__(256 * NW) step_slab_kernel(StepArgs<TABLE> p) 
   if (I.norm_partial != nullptr && p.mode >= MODE_SIGN) {
     block_sum<2>(nrm, lds);
     if (threadIdx.x == 0) {
-      I.norm_partial[(int64_t)lb * 2 + 0] = nrm[0];
-      I.norm_partial[(int64_t)lb * 2 + 1] = nrm[1];
+      const int64_t pb = (int64_t)b * nrhs + r;  // partial of (site block b, right-hand side r)
+      I.norm_partial[pb * 2 + 0] = nrm[0];
+      I.norm_partial[pb * 2 + 1] = nrm[1];
     }
   }
 }

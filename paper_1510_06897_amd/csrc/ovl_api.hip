@@ -342,6 +342,18 @@ LaunchCfg fit_slab(LaunchCfg c, const Geom &g, Prec prec, int64_t work, bool pai
   return c;
 }
 
+// Right-hand-side groups of the workgroup order, in right-hand-side blocks (0: one group).  Up
+// to 16 right-hand sides form one group: their workgroups for a site block run side by side and
+// share the links through L2 (grouping the 12 right-hand sides of the batched workload measured
+// no faster).  More right-hand sides (the eigen-solve's blocks of 64 to 256 vectors) run in
+// groups of kRhsGroup, so that between a site and its t neighbour only one group's spinors pass
+// through L2 (K on 128 FP64 vectors of 16^3 x 32 in the default configuration: 4.38 ms as one
+// group, 3.63 / 3.57 / 3.54 / 3.63 ms in groups of 1 / 2 / 4 / 8).
+constexpr int kRhsGroup = 4;
+int rhs_group_blocks(int nrhs, int rb) {
+  return nrhs <= 16 ? 0 : std::max(1, kRhsGroup / rb);
+}
+
 // workgroup order and first workgroup of every item; returns the launch's workgroup count
 int plan_items(StepItem *items, int n, const LaunchCfg &cfg, int site_bytes) {
   int total = 0;
@@ -349,9 +361,11 @@ int plan_items(StepItem *items, int n, const LaunchCfg &cfg, int site_bytes) {
     StepItem &it = items[i];
     it.blk0 = total;
     it.ty = it.tz = 0;
-    // the slice budget covers every right-hand side of the item: they all pass through L2
-    // between a site and its t neighbour
-    if (cfg.tiles == 1) step_tile(it.g, cfg.spb, site_bytes * it.nrhs, it.ty, it.tz);
+    it.rgroup = rhs_group_blocks(it.nrhs, cfg.rb);
+    // the slice budget covers every right-hand side of a group: they all pass through L2 between
+    // a site and its t neighbour
+    const int grhs = it.rgroup > 0 ? std::min(it.nrhs, it.rgroup * cfg.rb) : it.nrhs;
+    if (cfg.tiles == 1) step_tile(it.g, cfg.spb, site_bytes * grhs, it.ty, it.tz);
     total += item_blocks(it.g.V, cfg.spb) * ((it.nrhs + cfg.rb - 1) / cfg.rb);
   }
   return total;
@@ -2558,6 +2572,24 @@ int ovl_low_modes(const ovl_gauge *g, int n_ev, int block, double lmax, double c
     return OVL_OK;
   };
   if ((rc = fill(V, (int64_t)m * n))) return rc;
+  // The filter is K on a block of m right-hand sides, a problem of its own for the launch
+  // configuration (on 16^3 x 32 with 128 vectors the tuned form runs 1.2x faster than the default
+  // rule): without a configuration for it, measure the candidates once (as ovl_autotune does,
+  // on the block itself and W as output).
+  {
+    StepItem probe;
+    fill_item(probe, g, m);
+    const TuneKey key = tune_key((int)P_F64, &probe, 1);
+    bool known;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      known = g_tuned.count(key) > 0;
+    }
+    if (!known) {
+      const ovl_batch_item it{g, V, W, m};
+      if ((rc = ovl_autotune(&it, 1, nullptr, OVL_F64, nullptr, nullptr, stream))) return rc;
+    }
+  }
   std::vector<double> lam, res;
   const double bq = lmax * lmax, aq = cut * cut;
   const double c1 = 2.0 / (bq - aq), c0 = -(aq + bq) / (bq - aq);
