@@ -131,6 +131,33 @@ __global__ void write_item_kernel(StepItem it, StepItem *dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = it;
 }
 
+// Both hops of direction MU (compile-time: kernels whose waves each take one direction) for one
+// site, neighbours read raw with s5 = -1 applying gamma5; links read at lfw / lbw, or (PRE) taken
+// from mfw / mbw read earlier.
+template <int MU, bool PRE, class C, class SE, class LE>
+__device__ __forceinline__ void site_hops_k(cx<C> acc[12], rsrc_t v, uint32_t cs, rsrc_t U,
+                                            uint32_t ls, int fwd, int bwd, uint32_t lfw,
+                                            uint32_t lbw, bool r12, C s5, const cx<C> mfw[3][3],
+                                            const cx<C> mbw[3][3]) {
+  cx<C> u[2][3], d[2][3];
+  load_spinor<C, SE>(v, cs, fwd, false, u, d);
+  if constexpr (PRE) {
+    hop_apply_k<C, false, MU, 1>(acc, u, d, mfw, s5);
+  } else {
+    cx<C> m[3][3];
+    load_link3<C, LE>(U, ls, lfw, r12, m);
+    hop_apply_k<C, false, MU, 1>(acc, u, d, m, s5);
+  }
+  load_spinor<C, SE>(v, cs, bwd, false, u, d);
+  if constexpr (PRE) {
+    hop_apply_k<C, true, MU, -1>(acc, u, d, mbw, s5);
+  } else {
+    cx<C> m[3][3];
+    load_link3<C, LE>(U, ls, lbw, r12, m);
+    hop_apply_k<C, true, MU, -1>(acc, u, d, m, s5);
+  }
+}
+
 // Fused stencil step.  For every site and right-hand side r of every item:
 //   y   = kd v(x) + kh hop(v)(x)              (hop = the sum in eq. 2; v read with gamma5 if v_g5)
 //   y   = gamma5 y                            (if y_g5)
@@ -208,6 +235,8 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
   if (active) dir_neighbours(ex, c4, site, dq, fwd, bwd);
   const DirCoef<C> k = dir_coef<C>(dq);
   const uint32_t lane_links = (uint32_t)dq * 9u * (uint32_t)I.lstride;
+  // with at least 64 sites per workgroup and four threads per site, a wave takes one direction
+  constexpr bool kSpec = SPB % 64 == 0 && NQ == 4;
   // right-hand-side blocks: the thread's two links, read once for the RB right-hand sides
   cx<C> mfw[RB > 1 ? 3 : 1][3], mbw[RB > 1 ? 3 : 1][3];
   if constexpr (RB > 1) {
@@ -257,7 +286,18 @@ __global__ void __launch_bounds__(NQ * SPB) step_kernel(StepArgs<TABLE> p) {
       cx<C> acc[12];
 #pragma unroll
       for (int i = 0; i < 12; ++i) acc[i] = mk<C>(0, 0);
-      if (act) {
+      if (act && kSpec) {
+        // SPB >= 64: the wave's direction is uniform, one specialised path per direction
+        const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
+        const uint32_t lfw = lane_links + link_lane(site), lbw = lane_links + link_lane(bwd);
+        const C s5 = vg5 ? C(-1) : C(1);
+        switch (dq) {
+          case 0: site_hops_k<0, (RB > 1), C, SE, LE>(acc, v, cs, U, ls, fwd, bwd, lfw, lbw, r12, s5, mfw, mbw); break;
+          case 1: site_hops_k<1, (RB > 1), C, SE, LE>(acc, v, cs, U, ls, fwd, bwd, lfw, lbw, r12, s5, mfw, mbw); break;
+          case 2: site_hops_k<2, (RB > 1), C, SE, LE>(acc, v, cs, U, ls, fwd, bwd, lfw, lbw, r12, s5, mfw, mbw); break;
+          default: site_hops_k<3, (RB > 1), C, SE, LE>(acc, v, cs, U, ls, fwd, bwd, lfw, lbw, r12, s5, mfw, mbw); break;
+        }
+      } else if (act) {
         if constexpr (RB > 1) {
           cx<C> u[2][3], d[2][3];
           load_spinor<C, SE>(v, cs, fwd, vg5, u, d);
@@ -388,8 +428,60 @@ __device__ __forceinline__ void load_link_pair(rsrc_t U, uint32_t ls, uint32_t l
   }
 }
 
+// both hops of direction MU (a compile-time constant: every wave of the two-sites-per-lane kernel
+// takes one direction) for the pair (s0, s0 + 1): accA / accB += the direction's part of the
+// hopping sum at s0 / s0 + 1; the neighbours are read raw and s5 = -1 applies gamma5 to them
+template <int MU, class LE, bool R12>
+__device__ __forceinline__ void pair_hops_k(const StepItem &I, const Ext4 &ex, const Coord4 &c4,
+                                            int s0, rsrc_t v, uint32_t cs, float s5,
+                                            cx<float> accA[12], cx<float> accB[12]) {
+  using C = float;
+  using SE = float2;
+  const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
+  const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
+  const uint32_t ll = (uint32_t)MU * 9u * (uint32_t)I.lstride;
+  if constexpr (MU == 0) {
+    const int xn = (c4.x + 2 == ex.lx) ? s0 + 2 - ex.lx : s0 + 2;  // site x + 2
+    const int xp = (c4.x == 0) ? s0 + ex.lx - 1 : s0 - 1;          // site x - 1
+    {
+      cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
+      load_spinor_pair<SE>(v, cs, s0, false, u0, d0, u1, d1);
+      load_link_pair<LE>(U, ls, ll + link_lane(s0), R12, m0, m1);
+      hop_apply_k<C, false, 0, 1>(accA, u1, d1, m0, s5);  // x:     psi(x + 1), U(x)
+      hop_apply_k<C, true, 0, -1>(accB, u0, d0, m0, s5);  // x + 1: psi(x), U(x)^+
+      cx<C> un[2][3], dn[2][3];
+      load_spinor<C, SE>(v, cs, xn, false, un, dn);
+      hop_apply_k<C, false, 0, 1>(accB, un, dn, m1, s5);  // x + 1: psi(x + 2), U(x + 1)
+    }
+    {
+      cx<C> up[2][3], dp[2][3], mp[3][3];
+      load_spinor<C, SE>(v, cs, xp, false, up, dp);
+      load_link3<C, LE>(U, ls, ll + link_lane(xp), R12, mp);
+      hop_apply_k<C, true, 0, -1>(accA, up, dp, mp, s5);  // x: psi(x - 1), U(x - 1)^+
+    }
+  } else {
+    int fwd, bwd;
+    dir_neighbours(ex, c4, s0, MU, fwd, bwd);
+    {
+      cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
+      load_spinor_pair<SE>(v, cs, fwd, false, u0, d0, u1, d1);
+      load_link_pair<LE>(U, ls, ll + link_lane(s0), R12, m0, m1);
+      hop_apply_k<C, false, MU, 1>(accA, u0, d0, m0, s5);
+      hop_apply_k<C, false, MU, 1>(accB, u1, d1, m1, s5);
+    }
+    {
+      cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
+      load_spinor_pair<SE>(v, cs, bwd, false, u0, d0, u1, d1);
+      load_link_pair<LE>(U, ls, ll + link_lane(bwd), R12, m0, m1);
+      hop_apply_k<C, true, MU, -1>(accA, u0, d0, m0, s5);
+      hop_apply_k<C, true, MU, -1>(accB, u1, d1, m1, s5);
+    }
+  }
+}
+
 template <class LE, int SPB, bool TABLE, bool R12 = false>
 __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
+  static_assert(SPB % 64 == 0, "one direction per wave");
   using C = float;
   using SE = float2;
   __shared__ double lds[2 * 16];
@@ -401,7 +493,6 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
       if (p.table[i].blk0 <= gb) it = i;
   const StepItem &I = TABLE ? p.table[it] : p.item;
   const Ext4 ex = ext_of(I.g);
-  constexpr bool r12 = R12;  // two-row links (a launch-wide choice)
   const int nrhs = I.nrhs;
   const int lb = gb - I.blk0;
   int r, b;
@@ -435,7 +526,6 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
   const int V = ex.V;
   const uint32_t cs = (uint32_t)V * elem_traits<SE>::bytes;
   const uint32_t vb = 12u * cs;
-  const uint32_t ls = (uint32_t)I.lstride * elem_traits<LE>::bytes;
   const bool lower = q >= 2;
   auto vec = [&](int role) -> const SE * { return role_vec<SE>(I, role, r, V); };
   const double pa = role_a(I, p.a, r);
@@ -447,45 +537,13 @@ __global__ void __launch_bounds__(4 * SPB) step2_kernel(StepArgs<TABLE> p) {
 #pragma unroll
     for (int i = 0; i < 12; ++i) accA[i] = accB[i] = mk<C>(0, 0);
     if (active) {
-      const rsrc_t U = make_rsrc(I.U, link_bytes(ex.V, ls));
-      const DirCoef<C> k = dir_coef<C>(q);
-      const uint32_t ll = (uint32_t)q * 9u * (uint32_t)I.lstride;
-      if (q == 0) {
-        const int xn = (c4.x + 2 == ex.lx) ? s0 + 2 - ex.lx : s0 + 2;  // site x + 2
-        const int xp = (c4.x == 0) ? s0 + ex.lx - 1 : s0 - 1;          // site x - 1
-        {
-          cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
-          load_spinor_pair<SE>(v, cs, s0, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + link_lane(s0), r12, m0, m1);
-          hop_apply<C, false>(accA, u1, d1, m0, k, C(1));  // x:     psi(x + 1), U(x)
-          hop_apply<C, true>(accB, u0, d0, m0, k, C(-1));  // x + 1: psi(x), U(x)^+
-          cx<C> un[2][3], dn[2][3];
-          load_spinor<C, SE>(v, cs, xn, vg5, un, dn);
-          hop_apply<C, false>(accB, un, dn, m1, k, C(1));  // x + 1: psi(x + 2), U(x + 1)
-        }
-        {
-          cx<C> up[2][3], dp[2][3], mp[3][3];
-          load_spinor<C, SE>(v, cs, xp, vg5, up, dp);
-          load_link3<C, LE>(U, ls, ll + link_lane(xp), r12, mp);
-          hop_apply<C, true>(accA, up, dp, mp, k, C(-1));  // x: psi(x - 1), U(x - 1)^+
-        }
-      } else {
-        int fwd, bwd;
-        dir_neighbours(ex, c4, s0, q, fwd, bwd);
-        {
-          cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
-          load_spinor_pair<SE>(v, cs, fwd, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + link_lane(s0), r12, m0, m1);
-          hop_apply<C, false>(accA, u0, d0, m0, k, C(1));
-          hop_apply<C, false>(accB, u1, d1, m1, k, C(1));
-        }
-        {
-          cx<C> u0[2][3], d0[2][3], u1[2][3], d1[2][3], m0[3][3], m1[3][3];
-          load_spinor_pair<SE>(v, cs, bwd, vg5, u0, d0, u1, d1);
-          load_link_pair<LE>(U, ls, ll + link_lane(bwd), r12, m0, m1);
-          hop_apply<C, true>(accA, u0, d0, m0, k, C(-1));
-          hop_apply<C, true>(accB, u1, d1, m1, k, C(-1));
-        }
+      // the wave's direction q is uniform: one specialised path per direction
+      const C s5 = vg5 ? C(-1) : C(1);
+      switch (q) {
+        case 0: pair_hops_k<0, LE, R12>(I, ex, c4, s0, v, cs, s5, accA, accB); break;
+        case 1: pair_hops_k<1, LE, R12>(I, ex, c4, s0, v, cs, s5, accA, accB); break;
+        case 2: pair_hops_k<2, LE, R12>(I, ex, c4, s0, v, cs, s5, accA, accB); break;
+        default: pair_hops_k<3, LE, R12>(I, ex, c4, s0, v, cs, s5, accA, accB); break;
       }
     }
 #pragma unroll
@@ -1194,7 +1252,6 @@ __global__ void __launch_bounds__(256)
   const Coord4 c4 = coords_of(ex, s_site);
   int fwd, bwd;
   dir_neighbours(ex, c4, s_site, mu, fwd, bwd);
-  const DirCoef<C> k = dir_coef<C>(mu);
   const uint32_t cs = (uint32_t)ex.V * elem_traits<SE>::bytes;
   // own-site spinors of the 64 sites: [buffer][a, t][component][site]
   __shared__ cx<C> own[2][2][12][64];
@@ -1217,10 +1274,11 @@ __global__ void __launch_bounds__(256)
         xa[c] = bld<C, SE>(ra, comp * cs, site);
         xt[c] = bld<C, SE>(rt, comp * cs, site);
       }
+      // mu is uniform per wave: the projections take the direction-specialised form
       load_spinor<C, SE>(rt, cs, fwd, false, u, d);
-      dir_project(u, d, k, C(1), hmt);
+      dir_project_sw<C, 1>(mu, u, d, hmt);
       load_spinor<C, SE>(ra, cs, fwd, a_g5 != 0, u, d);
-      dir_project(u, d, k, C(-1), hpa);
+      dir_project_sw<C, -1>(mu, u, d, hpa);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int comp = mu * 3 + c;
@@ -1238,7 +1296,7 @@ __global__ void __launch_bounds__(256)
           ou[s2][c] = own[b][0][s2 * 3 + c][sl];
           od[s2][c] = own[b][0][(s2 + 2) * 3 + c][sl];
         }
-      dir_project(ou, od, k, C(1), hma);
+      dir_project_sw<C, 1>(mu, ou, od, hma);
 #pragma unroll
       for (int s2 = 0; s2 < 2; ++s2)
 #pragma unroll
@@ -1246,7 +1304,7 @@ __global__ void __launch_bounds__(256)
           ou[s2][c] = own[b][1][s2 * 3 + c][sl];
           od[s2][c] = own[b][1][(s2 + 2) * 3 + c][sl];
         }
-      dir_project(ou, od, k, C(-1), hpt);
+      dir_project_sw<C, -1>(mu, ou, od, hpt);
       const double cf = pi == 0 ? coef_first : coef_rest;
 #pragma unroll
       for (int i = 0; i < 3; ++i)

@@ -124,6 +124,75 @@ __device__ __forceinline__ void hop_apply(cx<C> acc[12], const cx<C> u[2][3], co
   }
 }
 
+// The same hop with the direction fixed at compile time (kernels whose waves each take one
+// direction): z, w in {+-1, +-i} become additions with swapped or negated components instead of
+// complex products by a per-thread coefficient, and the gamma5 of the input (s5 = -1: the lower
+// spin pair negated, uniform per launch) folds into those additions.  Bitwise the same sums as
+// hop_apply on the gamma5-applied input (the products there are exact).
+template <int MU>
+struct DirK {
+  static constexpr bool p = MU < 2;
+  static constexpr int z0r = MU == 1 ? 1 : (MU == 3 ? -1 : 0), z0i = (MU == 0 || MU == 2) ? 1 : 0;
+  static constexpr int z1r = (MU == 1 || MU == 3) ? -1 : 0, z1i = MU == 0 ? 1 : (MU == 2 ? -1 : 0);
+  static constexpr int w0r = (MU == 1 || MU == 3) ? -1 : 0, w0i = (MU == 0 || MU == 2) ? -1 : 0;
+  static constexpr int w1r = MU == 1 ? 1 : (MU == 3 ? -1 : 0), w1i = MU == 0 ? -1 : (MU == 2 ? 1 : 0);
+};
+// z x for a compile-time z in {+-1, +-i}
+template <int ZR, int ZI, class C>
+__device__ __forceinline__ cx<C> zc(cx<C> x) {
+  static_assert(ZR * ZR + ZI * ZI == 1, "z must be +-1 or +-i");
+  if constexpr (ZR == 1) return x;
+  else if constexpr (ZR == -1) return mk<C>(-x.re, -x.im);
+  else if constexpr (ZI == 1) return mk<C>(-x.im, x.re);
+  else return mk<C>(x.im, -x.re);
+}
+// u + s (z x), s = +-1 at run time
+template <int ZR, int ZI, class C>
+__device__ __forceinline__ cx<C> add_szx(cx<C> u, C s, cx<C> x) {
+  const cx<C> y = zc<ZR, ZI>(x);
+  return mk<C>(fma(s, y.re, u.re), fma(s, y.im, u.im));
+}
+
+// acc += (1 - SG gamma_MU) M h for the raw neighbour (u, d) (d not yet multiplied by s5)
+template <class C, bool DAG, int MU, int SG>
+__device__ __forceinline__ void hop_apply_k(cx<C> acc[12], const cx<C> u[2][3], const cx<C> d[2][3],
+                                            const cx<C> m[3][3], C s5) {
+  using K = DirK<MU>;
+  cx<C> h[2][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<C> dA = K::p ? d[1][c] : d[0][c];
+    const cx<C> dB = K::p ? d[0][c] : d[1][c];
+    h[0][c] = add_szx<SG * K::z0r, SG * K::z0i>(u[0][c], s5, dA);
+    h[1][c] = add_szx<SG * K::z1r, SG * K::z1i>(u[1][c], s5, dB);
+  }
+  cx<C> r[2][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    r[0][a] = mk<C>(0, 0);
+    r[1][a] = mk<C>(0, 0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (DAG) {
+        r[0][a] = cjmadd(r[0][a], m[b][a], h[0][b]);
+        r[1][a] = cjmadd(r[1][a], m[b][a], h[1][b]);
+      } else {
+        r[0][a] = cmadd(r[0][a], m[a][b], h[0][b]);
+        r[1][a] = cmadd(r[1][a], m[a][b], h[1][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc[c] = acc[c] + r[0][c];
+    acc[3 + c] = acc[3 + c] + r[1][c];
+    const cx<C> rA = K::p ? r[1][c] : r[0][c];
+    const cx<C> rB = K::p ? r[0][c] : r[1][c];
+    acc[6 + c] = acc[6 + c] + zc<SG * K::w0r, SG * K::w0i>(rA);
+    acc[9 + c] = acc[9 + c] + zc<SG * K::w1r, SG * K::w1i>(rB);
+  }
+}
+
 // one hop whose direction is chosen per lane (dag = backward: M = U^+, sgn = -1), so that the
 // forward and the backward hops of a wave run the same instructions
 template <class C, class SE, class LE>
@@ -160,6 +229,30 @@ __device__ __forceinline__ void dir_project(const cx<C> u[2][3], const cx<C> d[2
     const cx<C> dB = k.p ? d[0][c] : d[1][c];
     h[0][c] = u[0][c] + zmul(z0, dA);
     h[1][c] = u[1][c] + zmul(z1, dB);
+  }
+}
+
+// dir_project with the direction fixed at compile time, and a uniform run-time switch over it
+template <class C, int MU, int SG>
+__device__ __forceinline__ void dir_project_k(const cx<C> u[2][3], const cx<C> d[2][3],
+                                              cx<C> h[2][3]) {
+  using K = DirK<MU>;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const cx<C> dA = K::p ? d[1][c] : d[0][c];
+    const cx<C> dB = K::p ? d[0][c] : d[1][c];
+    h[0][c] = u[0][c] + zc<SG * K::z0r, SG * K::z0i>(dA);
+    h[1][c] = u[1][c] + zc<SG * K::z1r, SG * K::z1i>(dB);
+  }
+}
+template <class C, int SG>
+__device__ __forceinline__ void dir_project_sw(int mu, const cx<C> u[2][3], const cx<C> d[2][3],
+                                               cx<C> h[2][3]) {
+  switch (mu) {
+    case 0: dir_project_k<C, 0, SG>(u, d, h); break;
+    case 1: dir_project_k<C, 1, SG>(u, d, h); break;
+    case 2: dir_project_k<C, 2, SG>(u, d, h); break;
+    default: dir_project_k<C, 3, SG>(u, d, h); break;
   }
 }
 
