@@ -380,7 +380,8 @@ int ovl_overlap_solve_gmresr(const ovl_gauge *g, const ovl_poly *p, const ovl_de
  * 0 and 1).  Each candidate runs 2 untimed and 10 timed steps that read the items' inputs and
  * write their outputs (the outputs' contents are then undefined).  When the fastest has remap off
  * and the same form with remap on is within 3% of it, the remap-on form is kept (less traffic
- * between the XCDs' caches, a stable choice).  p (nullable) supplies lmax and
+ * between the XCDs' caches, a stable choice); likewise the tile order over memory order within 2%
+ * (fewer t-neighbour re-reads from HBM).  p (nullable) supplies lmax and
  * m_W for the step's coefficients.  The key includes whether every item's handle reads two-row
  * links (ovl_gauge_reconstruct).  The winner is appended to the text file cache_path when not
  * NULL (one line: B prec r12 n_items, then Lx Ly Lz Lt nrhs per item, then spb order remap rb
