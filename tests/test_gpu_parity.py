@@ -982,3 +982,50 @@ def test_two_row_links_force(ovl, store):
     got = host(ovl.sign_force(g, p, dev(chi, torch.complex64), dev(psi, torch.complex64)))
     ref = oforce.sign_force(u_two, latgen.round_to_f32(chi), latgen.round_to_f32(psi), alpha, LMAX)
     assert rel_err(got, ref) < 1e-6
+
+
+# more than 16 right-hand sides run in groups of four in the workgroup order (the last group
+# ragged for 17 and 19); every launch form that takes right-hand-side blocks
+_GROUP_FORMS = [(16, 0, 1), (16, 0, 2), (64, 0, 4), (64, 1, 1), (8, 0, 1)]
+
+
+@pytest.mark.parametrize("nrhs", [17, 19, 24])
+@pytest.mark.parametrize("spb,tiles,rb", _GROUP_FORMS)
+@pytest.mark.parametrize("store,cdt,tol", [("f64", torch.complex128, 1e-13),
+                                           ("f32", torch.complex64, 1e-6)])
+def test_kernel_many_rhs_groups(ovl, tmp_path, nrhs, spb, tiles, rb, store, cdt, tol):
+    """K on 17 to 24 right-hand sides (workgroups in right-hand-side groups) in a forced launch
+    form, every right-hand side against the oracle."""
+    dims = (6, 4, 4, 6)
+    prec = {"f64": 0, "f32": 1}[store]
+    cache = tmp_path / "groups.txt"
+    cache.write_text(f"B {prec} 0 1 {' '.join(map(str, dims))} {nrhs} {spb} {tiles} 1 {rb} 0\n")
+    assert ovl.autotune_load(str(cache)) == 1
+    u = latgen.random_su3_field(dims, 10190, noise=0.5)
+    psi = latgen.gaussian_spinor(dims, 20190, nrhs=nrhs)
+    g = ovl.GaugeField(dev(u), store)
+    assert ovl.batch_launch_config((g, dev(psi, cdt))) == (spb, tiles, 1, rb)
+    got = host(ovl.kernel_apply(g, dev(psi, cdt)))
+    u_r = u if store == "f64" else latgen.round_to_f32(u)
+    for r in range(nrhs):
+        psi_r = psi[r] if store == "f64" else latgen.round_to_f32(psi[r])
+        assert max_rel(got[r], ow.kop(u_r, psi_r)) < tol, r
+
+
+@pytest.mark.parametrize("nrhs", [17, 19])
+def test_sign_many_rhs_groups_norms(ovl, nrhs):
+    """The deflated sign function on 17 and 19 right-hand sides in one call: outputs against the
+    oracle and the FP64 norm partials of the final step (indexed by site block and right-hand
+    side) consistent with the bound (no flag raised)."""
+    dims = (4, 4, 2, 4)
+    u = latgen.smeared_field(dims, 10191, steps=1)
+    psi = latgen.gaussian_spinor(dims, 20191, nrhs=nrhs)
+    phi, lam = random_basis(dims, 3, 20192)
+    alpha = och.coeffs_sign_interp(21, 0.1)
+    g = ovl.GaugeField(dev(u), "f64")
+    p = ovl.Polynomial(alpha, LMAX)
+    d = ovl.Deflation(dev(phi), lam, "f64")
+    got = host(ovl.sign_apply(g, p, dev(psi), defl=d))
+    for r in range(nrhs):
+        assert rel_err(got[r], och.sign_apply(u, psi[r], alpha, LMAX, phi, lam)) < 1e-12, r
+    assert g.flags() == 0
