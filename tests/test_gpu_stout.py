@@ -45,8 +45,9 @@ def gauss(shape, seed):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
-# extent-2 and odd extents pin the periodic wrap of the five-link paths
-DIMS = [(4, 4, 4, 4), (3, 2, 5, 4), (2, 3, 2, 3)]
+# extent-1, extent-2 and odd extents pin the periodic wrap of the five-link paths (offsets up to
+# two sites along a direction of extent 1 or 2)
+DIMS = [(4, 4, 4, 4), (3, 2, 5, 4), (2, 3, 2, 3), (2, 1, 3, 2)]
 
 
 @pytest.mark.parametrize("dims", DIMS)
