@@ -170,8 +170,9 @@ __device__ __forceinline__ void site_hops_k(cx<C> acc[12], rsrc_t v, uint32_t cs
 // the LDS reduction.  NQ = 8 (small launches, bound by one wave's latency chain): threads q and
 // q + 4 take the forward and the backward hop of direction q, which halves the loads and the
 // arithmetic on each thread's path; threads q < 4 own the spin components afterwards.  Within
-// an item the right-hand side is the fastest logical index, so the workgroups that read the same
-// links run together and share them through L2.
+// an item the right-hand side is the fastest logical index inside each right-hand-side group
+// (item_block), so the workgroups that read the same links run together and share them through
+// L2.
 //
 // RB > 1 (right-hand-side block, NQ = 4): a workgroup takes RB consecutive right-hand sides of
 // its sites; each thread reads its direction's two links once into registers and reuses them for
