@@ -21,6 +21,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -54,20 +55,23 @@ def dw_bytes(store, r12=False):
     return (BYTES_LINK_R12 if r12 else BYTES_LINK)[store] + 2 * BYTES_SPIN[store]
 
 
-def counter_traffic(tag):
+def counter_traffic(tag, cfg=None):
     """HBM-side bytes per launch from the committed counter summary profiles/<tag>_counters.md
     (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy of known size), or None when the
-    kernel sources changed after the counters were taken."""
+    kernel sources changed after the counters were taken.  With cfg (a launch configuration), the
+    summary's figure for that configuration, or None when it holds none."""
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{tag}_counters.md")
     if not os.path.exists(path):
         return None
     fields = {}
+    key = "traffic_bytes_per_launch" if cfg is None else \
+        "traffic_bytes_per_launch[" + ",".join(str(int(c)) for c in cfg) + "]"
     for line in open(path):
-        if ":" in line and line.split(":", 1)[0] in ("traffic_bytes_per_launch", "sources_sha256"):
+        if ":" in line and line.split(":", 1)[0] in (key, "sources_sha256"):
             k, v = line.split(":", 1)
-            fields[k] = v.strip()
+            fields["traffic_bytes_per_launch" if k == key else k] = v.strip()
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1510_06897_amd", "csrc", "*"))):
         h.update(open(f, "rb").read())
@@ -90,6 +94,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="headline only: skip the BF16/24-mode, force, overlap, 24^3x48 and "
                          "stream measurements")
+    ap.add_argument("--config", default=None,
+                    help="with --profile batch: run in this launch configuration "
+                         "(spb,order,remap,rb) instead of the autotuned one")
     ap.add_argument("--profile", choices=["batch", "bf16", "force", "stout", "overlap", "dw", "dw2", "proj",
                                           "copy"],
                     help="run one part only, for rocprofv3: batch = the timed batched loop of the "
@@ -185,7 +192,7 @@ def kernel_name(cfg, store, two_row, table=True):
             f"R12={int(two_row)},RB={rb}>")
 
 
-def measure_batch(ovl, torch, dev, latgen, steps, warmup, profile=False):
+def measure_batch(ovl, torch, dev, latgen, steps, warmup, profile=False, force_cfg=None):
     t0 = time.time()
     alpha = ovl.cheb_sign_coeffs(BATCH_DEGREE, BATCH_EPS)
     p32 = ovl.Polynomial(alpha, LMAX)
@@ -198,7 +205,17 @@ def measure_batch(ovl, torch, dev, latgen, steps, warmup, profile=False):
         cfg_default = ovl.batch_launch_config(probs)
         ms_default = gpu_ms(torch, lambda: ovl.batch_sign_apply(p32, probs, outs), 3)
         res["default_config"] = {"config": list(cfg_default), "ms_per_batch": round(ms_default, 3)}
-    us_tune = ovl.autotune(probs, p32, outs=outs)
+    if profile and force_cfg:
+        # a profiled run in a given configuration (counters per configuration)
+        cache = os.path.join(tempfile.gettempdir(), f"ovl_batch_cfg_{os.getpid()}.txt")
+        items = " ".join(f"{d[0]} {d[1]} {d[2]} {d[3]} {n}" for d, n in BATCH_SHAPES)
+        with open(cache, "w") as f:
+            f.write(f"B 1 1 {len(BATCH_SHAPES)} {items} {' '.join(map(str, force_cfg))} 0\n")
+        ovl.autotune_load(cache)
+        os.remove(cache)
+        us_tune = float("nan")
+    else:
+        us_tune = ovl.autotune(probs, p32, outs=outs)
     cfg = ovl.batch_launch_config(probs)
     log(f"batch autotuned {cfg} ({us_tune:.1f} us per step in the tuner)")
     # the timed loop: warm-up, then exactly `steps` batches, with the library's event pair around
@@ -711,7 +728,9 @@ def main():
         log("copied 256 MiB twice")
         return
     if args.profile == "batch":
-        measure_batch(ovl, torch, dev, latgen, args.steps, args.warmup, profile=True)
+        force_cfg = tuple(int(c) for c in args.config.split(",")) if args.config else None
+        measure_batch(ovl, torch, dev, latgen, args.steps, args.warmup, profile=True,
+                      force_cfg=force_cfg)
         return
     if args.profile == "bf16":
         measure_bf16(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
@@ -763,18 +782,20 @@ def main():
         cpu, errs = oracle_leg(ovl, torch, dev, latgen, extra)
 
     # ---- roofline of each form's dominant kernel (algorithmic bytes / average launch) ----
-    def roofline(kernel, bytes_per_launch, k_ms, k_n, tag=None):
+    def roofline(kernel, bytes_per_launch, k_ms, k_n, tag=None, cfg=None):
         avg_us = 1e3 * k_ms / k_n
         ach = bytes_per_launch / (avg_us * 1e-6) / 1e9
         return {"kernel": kernel, "bound": "hbm", "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                "traffic": counter_traffic(tag) if tag else None,
+                "traffic": counter_traffic(tag, cfg) if tag else None,
                 "avg_launch_us": round(avg_us, 3), "launches": k_n,
                 "bytes_per_launch": int(bytes_per_launch)}
 
     batch_bytes = batch_bytes_per_step("f32", True)
+    # the counters of the configuration this run's tuner chose (the summary holds the forms the
+    # tuner picks between)
     rl = roofline(kernel_name(bt["config"], "f32", True), batch_bytes, bt["kernel_ms"],
-                  bt["kernel_launches"], tag="step2_kernel_sign_batch")
+                  bt["kernel_launches"], tag="step2_kernel_sign_batch", cfg=bt["config"])
     rl["bytes_model"] = ("per step: every lattice's links once (two rows, 192 B/site) + "
                          "3.5 FP32 spinor streams (96 B each) per site and right-hand side")
     if "bf16_24modes_16x16x16x32" in extra:
