@@ -812,7 +812,7 @@ def main():
         nv = f.pop("vjp_launches")
         f["roofline"] = roofline("link_vjp_kernel<float,float2,float2>",
                                  f["vjp_bytes_per_force"] / f["vjp_launches_per_force"],
-                                 f.pop("vjp_ms"), nv)
+                                 f.pop("vjp_ms"), nv, tag="link_vjp_kernel_24x24x24x48")
         f["roofline"]["bytes_model"] = ("per force: every (b_{m+1}, t_m) pair's two FP32 spinors "
                                         "once, the FP64 running sum of G between segments, G once")
         f["ms_per_force"] = round(f["ms_per_force"], 2)
