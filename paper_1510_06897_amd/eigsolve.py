@@ -27,7 +27,9 @@ def low_modes(g: GaugeField, n_ev: int, lmax: float, block: int = None, degree: 
     complex128 tensor [n_ev, 4, 3, T, Z, Y, X], residuals: np.ndarray[n_ev] = ||K phi - lambda
     phi||, eps_next = |lambda| of the first undeflated Ritz value / lmax).  With strict, a
     residual above tol after ``iters`` iterations raises OvlError (OVL_EDIVERGED); otherwise the
-    last iterate is returned and the residuals tell.
+    last iterate is returned and the residuals tell.  The filter's K launches on the block take the
+    configuration ``autotune`` keeps for (this lattice, FP64, ``block`` right-hand sides); without
+    one, the first call measures the candidates on its start block (about a second at 16^3 x 32).
     """
     if g.store != "f64":
         raise ValueError("the eigen-solve needs an FP64 gauge handle")
