@@ -616,6 +616,38 @@ def test_sign_force_fp32_lattices(ovl, dims):
     assert rel_err(got, oforce.sign_force(u32, chi32, psi32, alpha, LMAX)) < 1e-6
 
 
+@pytest.mark.parametrize("aligned", [True, False])
+def test_sign_force_fp32_pair_form_twins(ovl, tmp_path, aligned):
+    """The FP32 force with its single and twin (two-right-hand-side) steps forced into the
+    two-sites-per-lane form, against the oracle on the same rounded inputs; with chi and psi at an
+    8-byte offset (not 16-byte aligned) the steps that read them fall back to one site per lane."""
+    dims = (8, 4, 4, 6)
+    cache = tmp_path / "pairs.txt"
+    cache.write_text(f"B 1 0 1 {' '.join(map(str, dims))} 1 128 1 1 1 0\n"
+                     f"B 1 0 1 {' '.join(map(str, dims))} 2 128 1 1 1 0\n")
+    assert ovl.autotune_load(str(cache)) == 2
+    u = latgen.smeared_field(dims, 90, steps=1)
+    chi = latgen.gaussian_spinor(dims, 91)
+    psi = latgen.gaussian_spinor(dims, 92)
+    alpha = och.coeffs_sign_interp(41, 0.1)
+    u32, chi32, psi32 = latgen.round_to_f32(u), latgen.round_to_f32(chi), latgen.round_to_f32(psi)
+    g = ovl.GaugeField(dev(u), "f32")
+    p = ovl.Polynomial(alpha, LMAX)
+    x = dev(psi, torch.complex64)
+    c = dev(chi, torch.complex64)
+    assert ovl.batch_launch_config((g, x))[0] == 128
+    if not aligned:
+        n = psi.size
+        buf = torch.zeros(2 * n + 1, dtype=torch.complex64, device="cuda")
+        xo = buf[1:n + 1].view(psi.shape)
+        co = buf[n + 1:].view(chi.shape)
+        xo.copy_(x)
+        co.copy_(c)
+        x, c = xo, co
+    got = host(ovl.sign_force(g, p, c, x, ckpt_stride=5))
+    assert rel_err(got, oforce.sign_force(u32, chi32, psi32, alpha, LMAX)) < 1e-6
+
+
 @pytest.mark.parametrize("stride", [0, 1, 5, 63])
 def test_sign_force_fp64(ovl, stride):
     dims = (4, 4, 4, 4)
