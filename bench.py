@@ -95,7 +95,7 @@ def parse():
                     help="headline only: skip the BF16/24-mode, force, overlap, 24^3x48 and "
                          "stream measurements")
     ap.add_argument("--config", default=None,
-                    help="with --profile batch: run in this launch configuration "
+                    help="with --profile batch or bf16: run in this launch configuration "
                          "(spb,order,remap,rb) instead of the autotuned one")
     ap.add_argument("--profile", choices=["batch", "bf16", "force", "stout", "overlap", "dw", "dw2", "proj",
                                           "copy"],
@@ -268,7 +268,7 @@ def measure_batch(ovl, torch, dev, latgen, steps, warmup, profile=False, force_c
 
 
 # ------------------------------------------------------------------------------------------------
-def measure_bf16(ovl, torch, dev, latgen, low_modes, reps, profile=False):
+def measure_bf16(ovl, torch, dev, latgen, low_modes, reps, profile=False, force_cfg=None):
     """BF16 links, FP32 spinors/accumulation, FP64 reductions, degree 400 (N = 399), 24 deflated
     modes found on the device, FP32 matrix-core projection."""
     t0 = time.time()
@@ -288,6 +288,16 @@ def measure_bf16(ovl, torch, dev, latgen, low_modes, reps, profile=False):
     y32 = torch.empty_like(x32)
     log(f"BF16/24-mode set-up {time.time() - t0:.1f} s (eigen-solve {t_eig:.1f} s, residual {res_e.max():.1e})")
     if profile:
+        if force_cfg:
+            # a profiled run in a given configuration (counters per configuration)
+            cache = os.path.join(tempfile.gettempdir(), f"ovl_bf16_cfg_{os.getpid()}.txt")
+            with open(cache, "w") as f:
+                f.write(f"B 2 0 1 {' '.join(map(str, BF16_DIMS))} 1 {' '.join(map(str, force_cfg))} 0\n")
+            ovl.autotune_load(cache)
+            os.remove(cache)
+        else:
+            ovl.autotune((gbf, x32), pbf, outs=[y32])
+        log(f"bf16 configuration {ovl.batch_launch_config((gbf, x32))}")
         for _ in range(reps):
             ovl.sign_apply(gbf, pbf, x32, defl=dbf, out=y32)
         torch.cuda.synchronize()
@@ -733,7 +743,9 @@ def main():
                       force_cfg=force_cfg)
         return
     if args.profile == "bf16":
-        measure_bf16(ovl, torch, dev, latgen, low_modes, args.steps, profile=True)
+        force_cfg = tuple(int(c) for c in args.config.split(",")) if args.config else None
+        measure_bf16(ovl, torch, dev, latgen, low_modes, args.steps, profile=True,
+                     force_cfg=force_cfg)
         return
     if args.profile == "force":
         measure_force(ovl, torch, dev, latgen, args.steps, profile=True)
@@ -802,7 +814,8 @@ def main():
         bf = extra["bf16_24modes_16x16x16x32"]
         bf["roofline"] = roofline(kernel_name(bf["config"], "bf16", False, False),
                                   step_bytes("bf16") * int(np.prod(BF16_DIMS)), bf.pop("kernel_ms"),
-                                  bf.pop("kernel_launches"))
+                                  bf.pop("kernel_launches"), tag="step_kernel_sign_bf16_16x16x16x32",
+                                  cfg=bf["config"])
         bf["roofline"]["note"] = "62.9 MB per launch: the working set stays in the 256 MB Infinity Cache"
         bf["applies_per_s"] = round(1e3 / bf["ms_per_apply"], 2)
         bf["ms_per_apply"] = round(bf["ms_per_apply"], 3)
